@@ -1,0 +1,289 @@
+"""Benchmark of the Montgomery-type modular arithmetic library on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+
+A step is one Montgomery product (classic REDC, R = 2^64) over the
+residue-number-system workload: eight distinct random 60-bit primes, uint64
+operands of shape [8][2^25] (limb-major), row i uniform in [0, N_i).  The
+headline value is Gmodmul/s with inputs resident in HBM.  The JSON line also
+carries the roofline of the product kernel (algorithmic bytes per launch over
+its HIP-event duration, against 8 TB/s), the CPU oracle timed on the host
+cores, and secondary measurements: the 32-bit variants, the 16-bit workload,
+exponentiation, and the ragged batch (one persistent launch vs one launch
+per vector).  Everything runs in libmont.so's kernels; the oracle is used only
+for the cpu_baseline figure and a sampled correctness check.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+VALU_INT32_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 64 lanes/clk x 2.4 GHz
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--quick", action="store_true", help="headline only (no secondary measurements)")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--ragged-segments", type=int, default=4096)
+    return p.parse_args()
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("mont_arith.hpp", "mont_kernels.hpp", "mont_dispatch.hpp", "mont_k64.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2402_00675_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(launch_units: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if current."""
+    path = os.path.join(ROOT, "profiles", "rns64_mul_pmc.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != source_hash() or d.get("units_per_launch") != launch_units:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def timed(fn, torch, steps, warmup):
+    """Runs fn warmup + steps times; returns (wall s, HIP-event ms per call)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, e0.elapsed_time(e1) / steps
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this library has no multi-GPU path "
+              "(each shard of the work would be independent); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2402_00675_amd as mg
+    from paper_2402_00675_amd import inputs as inp
+
+    mg.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    result = {}
+
+    # ------------------------------------------------------------ headline
+    wl = inp.RNS64Workload()
+    log("generating RNS workload: %d x %d uint64, moduli %s" % (wl.k, wl.n, [hex(m) for m in wl.moduli]))
+    a_h, b_h = wl.operands()
+    a = torch.from_numpy(a_h).to(dev)
+    b = torch.from_numpy(b_h).to(dev)
+    out = torch.empty_like(a)
+    ctxs = [mg.setup(N, 64) for N in wl.moduli]
+    units = wl.k * wl.n
+
+    def step():
+        mg.mul_rns(ctxs, a, b, out=out)
+
+    wall, ms_launch = timed(step, torch, args.steps, args.warmup)
+    ms_step = wall * 1e3 / args.steps
+    value = units / (ms_step * 1e-3) / 1e9
+    algo_bytes = 24 * units
+    achieved = algo_bytes / (ms_launch * 1e-3) / 1e9
+    log("rns64 mul: %.3f ms/step (wall), %.3f ms/launch (events), %.1f Gmodmul/s, %.0f GB/s"
+        % (ms_step, ms_launch, value, achieved))
+
+    # sampled correctness check of the timed output against the oracle
+    out_h = out.cpu().numpy()
+    g = np.random.default_rng(1)
+    idx = g.integers(0, wl.n, size=4096)
+    import oracle as orc
+    for i, N in enumerate(wl.moduli):
+        want = orc.mul("classic", 64, N, a_h[i, idx], b_h[i, idx])
+        if not np.array_equal(out_h[i, idx], want):
+            raise SystemExit("bench: output mismatch against the oracle on row %d" % i)
+
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(units),
+                "kernel": "k_map<64,classic,mul> (mont_mul_rns)", "bytes_per_unit": 24,
+                "units_per_launch": units, "ms_per_launch": round(ms_launch, 4)}
+
+    # -------------------------------------------------------- CPU baseline
+    cpu = None
+    if not args.no_cpu:
+        import concurrent.futures as cf
+        cores = min(16, len(os.sched_getaffinity(0)))
+        chunks = [(i, s, min(s + (1 << 22), wl.n)) for i in range(wl.k) for s in range(0, wl.n, 1 << 22)]
+
+        def work(c):
+            i, s, e = c
+            orc.mul("classic", 64, wl.moduli[i], a_h[i, s:e], b_h[i, s:e])
+
+        t0 = time.perf_counter()
+        with cf.ThreadPoolExecutor(cores) as ex:
+            list(ex.map(work, chunks))
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(units / dt / 1e9, 4), "unit": "Gmodmul/s", "cores": cores, "kind": "oracle",
+               "sample": "the whole headline workload (8 x 2^25 classic 64-bit products), "
+                         "128-bit '%%' oracle, %d threads, %.2f s" % (cores, dt)}
+        log("cpu oracle: %.3f Gmodmul/s on %d threads (%.2f s)" % (units / dt / 1e9, cores, dt))
+    del a, b, out
+    torch.cuda.empty_cache()
+
+    extra = {}
+    if not args.quick:
+        extra = secondary(torch, mg, inp, args)
+
+    line = {
+        "metric": "Gmodmul/s & % HBM peak (64-bit REDC mul); ragged-batch vs per-call speedup",
+        "value": round(value, 2),
+        "unit": "Gmodmul/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic (seeded numpy PCG64)",
+        "config": {"workload": "RNS mont_mul: 8 random 60-bit primes, uint64 [8][2^25], classic REDC R=2^64",
+                   "elements": units},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if extra:
+        line["extra"] = extra
+    print(json.dumps(line), flush=True)
+
+
+def secondary(torch, mg, inp, args):
+    dev = torch.device("cuda:0")
+    ex = {}
+
+    # practical HBM ceiling: a plain device-to-device copy of 2 x 2 GiB
+    src = torch.empty(1 << 28, dtype=torch.int64, device=dev)
+    dst = torch.empty_like(src)
+    _, ms = timed(lambda: dst.copy_(src), torch, 10, 3)
+    ex["copy_ceiling_GBs"] = round(2 * src.numel() * 8 / (ms * 1e-3) / 1e9, 1)
+    log("copy ceiling: %.0f GB/s" % ex["copy_ceiling_GBs"])
+    del src, dst
+
+    # 32-bit workload: N = 8380417, 2^26 residues, four variants
+    w2 = inp.R32Workload()
+    c32 = mg.setup(w2.N, 32)
+    r32 = {}
+    for signed in (False, True):
+        ah, bh = w2.operands(signed)
+        a = torch.from_numpy(ah).to(dev)
+        b = torch.from_numpy(bh).to(dev)
+        o = torch.empty_like(a)
+        for v in (["signed", "signed_plantard", "signed_plantard_alpha"] if signed else ["classic", "plantard"]):
+            _, ms = timed(lambda: mg.mul(c32, a, b, out=o, variant=v), torch, 20, 5)
+            gms = w2.n / (ms * 1e-3) / 1e9
+            r32[v] = {"Gmodmul_s": round(gms, 1), "GB_s": round(12 * gms, 1),
+                      "frac_hbm": round(12 * gms / HBM_PEAK_GBS, 4)}
+            log("r32 %s: %.1f Gmodmul/s" % (v, gms))
+        del a, b, o
+    ex["r32_mul"] = r32
+
+    # 16-bit workload: N = 3329, 2^20 residues + the exhaustive REDC sweep
+    w1 = inp.R16Workload()
+    c16 = mg.setup(w1.N, 16)
+    ah, bh = w1.operands()
+    a = torch.from_numpy(ah).to(dev)
+    b = torch.from_numpy(bh).to(dev)
+    o = torch.empty_like(a)
+    _, ms = timed(lambda: mg.mul(c16, a, b, out=o), torch, 200, 20)
+    ex["r16_mul"] = {"us": round(ms * 1e3, 2), "Gmodmul_s": round(w1.n / (ms * 1e-3) / 1e9, 1)}
+    total = w1.N << 16
+    ro = torch.empty(total, dtype=torch.uint16, device=dev)
+    _, ms = timed(lambda: mg.redc_range(c16, 0, total, out=ro), torch, 10, 2)
+    ex["r16_exhaustive_redc"] = {"T": total, "us": round(ms * 1e3, 1),
+                                 "GB_s_written": round(2 * total / (ms * 1e-3) / 1e9, 1)}
+    log("r16: mul %s, exhaustive %s" % (ex["r16_mul"], ex["r16_exhaustive_redc"]))
+    del a, b, o, ro
+
+    # exponentiation: 2^22 elements, 31- and 62-bit odd moduli, uniform 64-bit exponents
+    g = inp.rng(inp.W_SERVE, 7)
+    pw = {}
+    for bits, w in ((31, 32), (62, 64)):
+        N = inp.odd_modulus(g, bits)
+        n = 1 << 22
+        dt = np.uint32 if w == 32 else np.uint64
+        x = torch.from_numpy(inp.uniform_residues(g, N, n, dt)).to(dev)
+        e = torch.from_numpy(inp.u64_uniform(g, n)).to(dev)
+        o = torch.empty_like(x)
+        c = mg.setup(N, w)
+        _, ms = timed(lambda: mg.pow(c, x, e, out=o), torch, 5, 2)
+        rate = n / (ms * 1e-3) / 1e9
+        pw["w%d" % w] = {"Gpow_s": round(rate, 3), "ms": round(ms, 3),
+                         "Gmontmul_s": round(rate * 97, 1)}  # 3 + 32 windows x 3 + 1 REDC products
+        log("pow w%d: %.3f Gpow/s" % (w, rate))
+    ex["pow"] = pw
+
+    # ragged batch
+    ex["ragged"] = ragged(torch, mg, inp, args.ragged_segments)
+    return ex
+
+
+def ragged(torch, mg, inp, nseg):
+    dev = torch.device("cuda:0")
+    wl = inp.RaggedWorkload(nseg=nseg)
+    lens, wide, mods = wl.segments()
+    offs, (a32, b32), (a64, b64) = wl.operands(lens, wide, mods)
+    log("ragged: %d segments, %d elements (%d x u32, %d x u64)" % (nseg, int(lens.sum()), a32.size, a64.size))
+    ctxs = [mg.setup(N, 64 if wd else 32) for N, wd in zip(mods, wide)]
+    segs = [(i, mg.OP_MUL, "classic", int(n), int(o), int(o)) for i, (n, o) in enumerate(zip(lens, offs))]
+    d = {k: torch.from_numpy(v).to(dev) for k, v in (("a32", a32), ("b32", b32), ("a64", a64), ("b64", b64))}
+    o32 = torch.empty_like(d["a32"])
+    o64 = torch.empty_like(d["a64"])
+    P = mg.pools([None, d["a32"], d["a64"]], [None, d["b32"], d["b64"]], [None, o32, o64])
+    nbytes = 12 * a32.size + 24 * a64.size
+    res = {"segments": nseg, "elements": int(lens.sum()), "bytes": nbytes}
+    for name, flags in (("persistent_graph", mg.BATCH_GRAPH | mg.BATCH_TUNE),):
+        bt = mg.Batch(ctxs, segs, flags=flags)
+        bt.run(P)  # tunes
+        torch.cuda.synchronize()
+        _, ms = timed(lambda: bt.run(P), torch, 10, 2)
+        res[name] = {"ms": round(ms, 3), "GB_s": round(nbytes / (ms * 1e-3) / 1e9, 1), "info": bt.info()}
+        o32h, o64h = o32.cpu().numpy(), o64.cpu().numpy()
+        _, ms_pv = timed(lambda: bt.run_pervector(P), torch, 3, 1)
+        res["per_vector_launches"] = {"ms": round(ms_pv, 3)}
+        if not (np.array_equal(o32h, o32.cpu().numpy()) and np.array_equal(o64h, o64.cpu().numpy())):
+            raise SystemExit("bench: ragged persistent and per-vector results differ")
+        res["speedup_vs_per_vector"] = round(ms_pv / ms, 2)
+        bt.close()
+    log("ragged: %s" % res)
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,357 @@
+/*
+ * mont.h -- C ABI of a gfx950 (MI355X) library for batched Montgomery-type
+ * modular reduction, multiplication and exponentiation over arrays of
+ * residues.
+ *
+ * The operations follow Xu, Jia and Yang, "Chinese Remainder Theorem
+ * Approach to Montgomery-Type Algorithms" (arXiv 2402.00675):
+ *
+ *   MONT_CLASSIC              Montgomery's REDC (Section 1): T R^{-1} mod N,
+ *                             R = 2^w, for 0 <= T < R N; result in [0, N).
+ *   MONT_SIGNED               signed Montgomery (Section 3.1, Algorithm 1),
+ *                             R = 2^w, odd N with 2N < R, |T| < N R / 2;
+ *                             result r = T R^{-1} (mod N), -N < r < N, the
+ *                             unique such r with T/R - N/2 < r <= T/R + N/2
+ *                             (quotient digit N^{-1} a0 mods R taken in
+ *                             [-R/2, R/2), Section 2).
+ *   MONT_PLANTARD             Plantard (Section 3.2, Algorithm 2), R = 2^(2w),
+ *                             N < 2^w / phi, 0 <= T <= N^2;
+ *                             result -T R^{-1} mod N in [0, N).
+ *   MONT_SIGNED_PLANTARD      signed Plantard (Section 3.2, Algorithm 3),
+ *                             R = 2^(2w), N < 2^(w-1), |T| <= 2^(2w-2);
+ *                             result -T R^{-1} mods N in [-(N-1)/2, (N-1)/2].
+ *   MONT_SIGNED_PLANTARD_ALPHA
+ *                             Huang's signed Plantard (Section 3.3,
+ *                             Algorithm 4) with the context's alpha >= 1,
+ *                             R = 2^(2w), N < 2^(w-alpha-1),
+ *                             |T| <= 2^(2 alpha) N^2; same result as
+ *                             MONT_SIGNED_PLANTARD.  alpha = 0 is refused:
+ *                             the paper's Example 3.1 shows it is wrong.
+ *
+ * Word sizes w = 16, 32, 64.  Element types:
+ *   w = 16: residues uint16_t / int16_t (signed variants), T uint32_t / int32_t
+ *   w = 32: residues uint32_t / int32_t,                   T uint64_t / int64_t
+ *   w = 64: residues uint64_t / int64_t,                   T 128-bit: (lo, hi)
+ *           pairs of uint64_t, little-endian, two's complement when signed.
+ * Signed variants read and write the signed types; the others the unsigned.
+ *
+ * Memory and streams.  Every array argument is a DEVICE pointer that the
+ * caller owns (for example a torch tensor's storage); the library never
+ * allocates or frees caller buffers.  `stream` is a hipStream_t (NULL = the
+ * legacy default stream).  Calls enqueue work on that stream and return
+ * without waiting; results are ready once the stream is synchronised.
+ * In-place operation (out == an input of the same width) is allowed; other
+ * overlaps are not.  n == 0 returns MONT_OK and launches nothing.
+ *
+ * Errors.  Argument and domain errors are found on the host before any
+ * launch and returned synchronously; nothing is enqueued then.  A HIP
+ * error while launching returns MONT_E_DEVICE; the message is available
+ * from mont_last_error() (thread-local).  Nothing aborts or throws across
+ * this interface.  Residues outside a variant's input range are a
+ * precondition violation: the output is then unspecified (but the kernels
+ * stay in bounds and terminate).
+ *
+ * Contexts are plain values: immutable after mont_setup, safe to share
+ * across threads and streams, and copied by value into kernel arguments.
+ */
+#ifndef MONT_H
+#define MONT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mont_status_t;
+#define MONT_OK 0
+#define MONT_E_INVAL (-1)       /* null pointer, even N, N < 3, N >= 2^w, bad w, bad enum */
+#define MONT_E_DOMAIN (-2)      /* the variant's precondition on N (or alpha) fails */
+#define MONT_E_UNSUPPORTED (-3) /* combination not provided (see each call) */
+#define MONT_E_NOMEM (-4)       /* library-owned device/host memory could not be allocated */
+#define MONT_E_DEVICE (-5)      /* HIP runtime error; see mont_last_error() */
+#define MONT_E_BUSY (-6)        /* resource held by another call (serving loop) */
+
+typedef enum {
+    MONT_CLASSIC = 0,
+    MONT_SIGNED = 1,
+    MONT_PLANTARD = 2,
+    MONT_SIGNED_PLANTARD = 3,
+    MONT_SIGNED_PLANTARD_ALPHA = 4
+} mont_variant_t;
+
+/*
+ * Per-modulus constants (Section 1 and Section 3).  Filled by mont_setup;
+ * callers treat it as opaque but may copy it freely (64 bytes).
+ */
+typedef struct mont_ctx {
+    uint64_t N;        /* odd modulus, 3 <= N < 2^w */
+    uint32_t w;        /* word size: 16, 32 or 64 */
+    uint32_t valid;    /* bit v set iff variant v's precondition on N holds */
+    uint64_t nprime;   /* N' = 2^w - (N^{-1} mod 2^w), REDC's multiplier (Section 1) */
+    uint64_t ninv;     /* N^{-1} mod 2^w; read as w-bit two's complement it is
+                          N^{-1} mods 2^w (Algorithm 1) */
+    uint64_t ninv2_lo; /* N^{-1} mod 2^(2w), low 64 bits (Algorithms 2-4) */
+    uint64_t ninv2_hi; /* N^{-1} mod 2^(2w), high 64 bits (w = 64 only, else 0) */
+    uint64_t r_mod_n;  /* 2^w mod N  (Montgomery form of 1) */
+    uint64_t r2_mod_n; /* 2^(2w) mod N (maps x to its Montgomery form x R mod N) */
+    uint32_t alpha;    /* Algorithm 4 parameter (default 1 where valid, else 0) */
+    uint32_t reserved;
+} mont_ctx_t;
+
+/*
+ * mont_setup -- per-modulus constants for modulus N and word size
+ * log2R = w in {16, 32, 64} (Section 1: N' = R - (N^{-1} mod R); Theorem 2.1
+ * is checked on the result).  Host only, synchronous, no device use.
+ * Classic and signed reduce modulo R = 2^w, the Plantard family modulo
+ * 2^(2w).  Returns MONT_E_INVAL for an even N, N < 3, N >= 2^w or a bad w.
+ * A variant whose precondition fails is cleared in ctx->valid (calls with it
+ * return MONT_E_DOMAIN).
+ */
+mont_status_t mont_setup(uint64_t N, uint32_t log2R, mont_ctx_t *ctx);
+
+/*
+ * mont_set_alpha -- choose Algorithm 4's alpha (Section 3.3).  Requires
+ * alpha >= 1 and N < 2^(w - alpha - 1); alpha = 0 returns MONT_E_DOMAIN.
+ */
+mont_status_t mont_set_alpha(mont_ctx_t *ctx, uint32_t alpha);
+
+/*
+ * mont_redc -- out[i] = REDC_variant(T[i]) for i < n (Section 1; Algorithms
+ * 1-4).  T holds 2w-bit integers (see the element types above); out holds
+ * w-bit residues.  The Require range of the variant applies to each T[i].
+ */
+mont_status_t mont_redc(const mont_ctx_t *ctx, const void *T, void *out, size_t n, mont_variant_t variant,
+                        void *stream);
+
+/*
+ * mont_mul -- out[i] = REDC_variant(a[i] * b[i]) (the Montgomery product,
+ * Section 1).  Unsigned variants take residues in [0, N); signed variants
+ * take centred residues |a|, |b| <= (N - 1)/2 (any inputs whose product meets
+ * the variant's Require range are valid).
+ */
+mont_status_t mont_mul(const mont_ctx_t *ctx, const void *a, const void *b, void *out, size_t n,
+                       mont_variant_t variant, void *stream);
+
+/*
+ * mont_mul_rns -- the Montgomery product over k residue rows ("limbs"), row
+ * j reduced with ctxs[j] (all of one word size w).  a, b, out are limb-major
+ * [k][ld] arrays; the first n entries of each row are processed.
+ * 1 <= k <= MONT_RNS_MAX, n <= ld.  ctxs is a HOST array.
+ */
+#define MONT_RNS_MAX 32
+mont_status_t mont_mul_rns(const mont_ctx_t *ctxs, uint32_t k, const void *a, const void *b, void *out, size_t n,
+                           size_t ld, mont_variant_t variant, void *stream);
+
+/*
+ * mont_pow -- out[i] = x[i]^e[i] mod N for residues x[i] in [0, N) and
+ * unsigned 64-bit exponents e[i] (x^0 = 1, including 0^0).  Ordinary
+ * residues in and out; inside, x is mapped to x R mod N with one REDC of
+ * x (R^2 mod N), raised with Montgomery products (classic REDC, R = 2^w) and
+ * mapped back with REDC (Section 1: the representation x -> x R mod N and
+ * REDC's "pull back").  Valid for every odd N < 2^w.
+ */
+mont_status_t mont_pow(const mont_ctx_t *ctx, const void *x, const uint64_t *e, void *out, size_t n,
+                       void *stream);
+
+/*
+ * mont_redc_range -- out[i] = REDC_variant(T0 + i) for i < n, with T
+ * generated in the kernel (no input array): exhaustive sweeps of the input
+ * space.  Unsigned variants (classic, Plantard) at w = 16 and 32; the last
+ * input T0 + n - 1 must stay in the variant's Require range.
+ */
+mont_status_t mont_redc_range(const mont_ctx_t *ctx, uint64_t T0, void *out, size_t n, mont_variant_t variant,
+                              void *stream);
+
+/* --------------------------------------------------------------------------
+ * Ragged batches: many independent vectors, each with its own modulus,
+ * length and operation, processed by ONE persistent launch.  Elements of a
+ * vector live in the caller's pool of its word size at offset `off`.
+ */
+#define MONT_OP_MUL 0  /* out = REDC_variant(in0 * in1) */
+#define MONT_OP_REDC 1 /* out = REDC_variant(in0), in0 holds 2w-bit T */
+#define MONT_OP_POW 2  /* out = in0 ^ in1 mod N, in1 the uint64 exponent pool; classic only */
+
+typedef struct mont_seg {
+    uint32_t ctx;     /* index into the batch's context table */
+    uint16_t op;      /* MONT_OP_* */
+    uint16_t variant; /* mont_variant_t */
+    uint64_t n;       /* element count (0 allowed) */
+    uint64_t off;     /* offset of the segment in in0 and out, in their element units */
+    uint64_t off1;    /* offset in in1, in its element units (w-bit b, or uint64_t
+                         exponents); for MONT_OP_MUL, (off1 - off) must be a multiple
+                         of 128 / w so that both operands stay 16-byte aligned */
+} mont_seg_t;
+
+/*
+ * Device pools, indexed by word-size class: [0] w = 16, [1] w = 32,
+ * [2] w = 64.  in0 holds a (w-bit), x (w-bit) or T (2w-bit, for
+ * MONT_OP_REDC); in1 holds b (w-bit) or exponents (uint64_t); out holds
+ * w-bit results.  Pool pointers must be 16-byte aligned; unused entries may
+ * be NULL.  The caller keeps the segments' byte ranges disjoint inside each
+ * pool (a MONT_OP_REDC segment's T range is twice as wide as its out range).
+ */
+typedef struct mont_pools {
+    const void *in0[3];
+    const void *in1[3];
+    void *out[3];
+} mont_pools_t;
+
+typedef struct mont_batch mont_batch_t;
+
+/* batch flags */
+#define MONT_BATCH_GRAPH 1u   /* replay the launch from a hipGraph */
+#define MONT_BATCH_DYNAMIC 2u /* tiles taken from an atomic counter (else static round-robin) */
+#define MONT_BATCH_TUNE 4u    /* autotune tile size and grid on the first run */
+
+/*
+ * mont_batch_create -- validates every segment (context valid for its
+ * variant, op/variant pair supported), splits the segments into tiles, and
+ * uploads the context, segment and tile tables to library-owned device
+ * memory on `stream`.  ctxs and segs are HOST arrays, copied.  Returns
+ * MONT_E_DOMAIN / MONT_E_INVAL / MONT_E_UNSUPPORTED with the offending
+ * segment index in mont_last_error().
+ */
+mont_status_t mont_batch_create(const mont_ctx_t *ctxs, uint32_t nctx, const mont_seg_t *segs, uint32_t nseg,
+                                uint32_t flags, mont_batch_t **out, void *stream);
+
+/*
+ * mont_batch_run -- performs every segment's operation in one launch (a
+ * hipGraph replay with MONT_BATCH_GRAPH).  A batch is used by one stream at
+ * a time; runs on one batch must not overlap.
+ */
+mont_status_t mont_batch_run(mont_batch_t *batch, const mont_pools_t *pools, void *stream);
+
+/* Ragged forms of mont_mul / mont_redc / mont_pow: mont_batch_run for a
+ * batch whose segments all have that op (else MONT_E_INVAL). */
+mont_status_t mont_mul_ragged(mont_batch_t *batch, const mont_pools_t *pools, void *stream);
+mont_status_t mont_redc_ragged(mont_batch_t *batch, const mont_pools_t *pools, void *stream);
+mont_status_t mont_pow_ragged(mont_batch_t *batch, const mont_pools_t *pools, void *stream);
+
+/*
+ * mont_batch_run_pervector -- the same work as mont_batch_run, issued the
+ * conventional way: one mont_mul / mont_redc / mont_pow launch per segment,
+ * from a host loop.  A reference schedule for measuring what the persistent
+ * launch saves.
+ */
+mont_status_t mont_batch_run_pervector(mont_batch_t *batch, const mont_pools_t *pools, void *stream);
+
+/* Tiles and launch shape chosen for the batch (for reports). */
+typedef struct mont_batch_info {
+    uint64_t ntiles;
+    uint64_t elements;
+    uint32_t tile_elems; /* elements per tile for 32-bit mul/redc (others scale by bytes) */
+    uint32_t grid;       /* workgroups of the persistent launch */
+    uint32_t block;
+    uint32_t flags;
+} mont_batch_info_t;
+mont_status_t mont_batch_info(const mont_batch_t *batch, mont_batch_info_t *info);
+
+/* Frees the batch's device tables and graph (after its runs completed). */
+void mont_batch_destroy(mont_batch_t *batch);
+
+/* --------------------------------------------------------------------------
+ * Launch-shape tuning for the streaming kernels.
+ */
+typedef struct mont_launch {
+    uint32_t unroll;     /* 16-byte chunks per thread per iteration: 1, 2 or 4 */
+    uint32_t nontemporal;/* 1: non-temporal loads/stores */
+    uint32_t blocks_per_cu; /* 0: one pass over the data; else grid = CUs * this */
+} mont_launch_t;
+
+/*
+ * mont_tune -- times the candidate launch shapes of mont_mul for this
+ * (w, variant) on n elements of the given device buffers with HIP events and
+ * keeps the fastest for later calls in this process (and in the JSON file
+ * named by $MONT_TUNE_CACHE, if set).  Buffers are overwritten with results.
+ */
+mont_status_t mont_tune_mul(const mont_ctx_t *ctx, const void *a, const void *b, void *out, size_t n,
+                            mont_variant_t variant, mont_launch_t *best, void *stream);
+
+/* Sets / reads the launch shape used for (op, w, variant). */
+mont_status_t mont_set_launch(uint32_t op, uint32_t w, mont_variant_t variant, const mont_launch_t *l);
+mont_status_t mont_get_launch(uint32_t op, uint32_t w, mont_variant_t variant, mont_launch_t *l);
+
+/* --------------------------------------------------------------------------
+ * Serving loop: a request loop with continuous batching.  Jobs (a vector
+ * product or a vector exponentiation, classic REDC, each with its own odd
+ * modulus) are queued as they arrive, admitted in FIFO order while their
+ * operands and results fit a fixed device-memory budget, and fused into
+ * ragged batches that run as one persistent launch each; up to `streams`
+ * batches are in flight at once, so work that arrives while the device is
+ * busy joins the next batch.  Per-modulus constants are cached on the host
+ * and travel inside each batch's segment table.  A service thread does the
+ * admission, copies, launches and completion polling.
+ */
+typedef struct mont_server mont_server_t;
+
+typedef struct mont_server_cfg {
+    uint64_t hbm_budget_bytes; /* device memory for job operands and results, split
+                                  evenly between 32-bit and 64-bit jobs (0: 8 GiB) */
+    uint32_t max_jobs_in_flight; /* admitted, unfinished jobs (0: 4096) */
+    uint32_t streams;            /* batches in flight, one HIP stream each (0: 3) */
+    uint32_t max_batch_jobs;     /* jobs fused into one launch (0: 512) */
+    uint32_t tile_elems;         /* 32-bit product tile in elements (0: 8192) */
+} mont_server_cfg_t;
+
+typedef struct mont_job {
+    uint64_t id;     /* caller's id, echoed in the completion */
+    uint64_t N;      /* odd modulus, 3 <= N < 2^w */
+    uint32_t w;      /* 32 or 64 */
+    uint32_t op;     /* MONT_OP_MUL (out = REDC(a b), classic) or MONT_OP_POW (out = x^e mod N) */
+    uint64_t n;      /* elements */
+    const void *in0; /* HOST: a or x, n w-bit residues in [0, N) */
+    const void *in1; /* HOST: b (n w-bit residues) or e (n uint64_t exponents) */
+    void *out;       /* HOST: n w-bit results.  All three stay valid until the job's
+                        completion is returned; pinned memory gives asynchronous copies */
+} mont_job_t;
+
+typedef struct mont_completion {
+    uint64_t id;
+    int32_t status;  /* MONT_OK, or MONT_E_DEVICE if the batch failed */
+    uint32_t reserved;
+    double t_submit; /* mont_serve_now() clock, seconds */
+    double t_admit;  /* device memory reserved */
+    double t_launch; /* batch enqueued */
+    double t_done;   /* results copied to job.out and seen complete */
+} mont_completion_t;
+
+typedef struct mont_server_stats {
+    uint64_t submitted, completed, rejected, launches, jobs_launched;
+    uint64_t queued, staged, in_flight;
+    uint64_t bytes_in_use, peak_bytes_in_use;
+} mont_server_stats_t;
+
+/* Allocates the device arena and starts the service thread on the current device. */
+mont_status_t mont_serve_create(const mont_server_cfg_t *cfg, mont_server_t **out);
+/* Queues one job.  MONT_E_INVAL for a malformed job, MONT_E_DOMAIN for one that
+ * can never fit the budget (no completion is produced for either). */
+mont_status_t mont_serve_submit(mont_server_t *s, const mont_job_t *job);
+/* Submits jobs[i] when mont_serve_now() reaches t0 + arrival_s[i] (blocking;
+ * arrival_s non-decreasing, t0 = the clock at the call).  Returns the number
+ * accepted, or a negative status. */
+int64_t mont_serve_submit_timed(mont_server_t *s, const mont_job_t *jobs, const double *arrival_s, uint64_t n);
+/* Moves up to max completions into out, waiting up to wait_ms for the first;
+ * returns the count (>= 0) or a negative status. */
+int64_t mont_serve_poll(mont_server_t *s, mont_completion_t *out, uint32_t max, int32_t wait_ms);
+/* Waits until every accepted job has completed (timeout_ms < 0: no limit);
+ * MONT_E_BUSY on timeout. */
+mont_status_t mont_serve_drain(mont_server_t *s, int32_t timeout_ms);
+mont_status_t mont_serve_stats(const mont_server_t *s, mont_server_stats_t *st);
+double mont_serve_now(void);
+/* Stops the service thread after in-flight batches finish and frees the arena. */
+void mont_serve_destroy(mont_server_t *s);
+
+/* --------------------------------------------------------------------------
+ * Misc.
+ */
+const char *mont_last_error(void);
+/* Library version (ABI revision in the low 16 bits). */
+uint32_t mont_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MONT_H */

@@ -1,0 +1,20 @@
+"""Batched Montgomery-type modular arithmetic on MI355X (gfx950).
+
+Operations (all in HIP kernels of libmont.so, called through its C ABI):
+
+* ``setup(N, w)``                 per-modulus constants (Section 1 of the paper)
+* ``redc / mul``                  classic REDC, signed Montgomery (Algorithm 1),
+                                  Plantard (Algorithm 2), signed Plantard
+                                  (Algorithm 3), Huang's variant with alpha >= 1
+                                  (Algorithm 4), at 16/32/64-bit words
+* ``mul_rns``                     the product over residue-number-system rows
+* ``pow``                         x^e mod N through the Montgomery representation
+* ``redc_range``                  REDC over a generated range of T
+* ``Batch``                       ragged batches in one persistent launch
+* ``serve``                       the continuous-batching request loop
+"""
+from ._lib import (  # noqa: F401
+    BATCH_DYNAMIC, BATCH_GRAPH, BATCH_TUNE, CLASSIC, OP_MUL, OP_POW, OP_REDC, PLANTARD, SIGNED,
+    SIGNED_PLANTARD, SIGNED_PLANTARD_ALPHA, VARIANTS, Batch, Ctx, MontError, elem_dtype, get_launch,
+    header_functions, load, mul, mul_rns, pools, pow, redc, redc_range, set_launch, setup, tune_mul,
+)

@@ -1,0 +1,324 @@
+"""ctypes binding of libmont.so (argument marshalling only).
+
+Every operation runs in the library's HIP kernels; this module checks tensor
+shapes and dtypes, passes device pointers and the current HIP stream, and
+turns status codes into exceptions.  Torch supplies device memory and
+streams, nothing else.  If the library has not been built the import fails
+loudly: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmont.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "mont.h")
+
+CLASSIC, SIGNED, PLANTARD, SIGNED_PLANTARD, SIGNED_PLANTARD_ALPHA = range(5)
+VARIANTS = {"classic": CLASSIC, "signed": SIGNED, "plantard": PLANTARD,
+            "signed_plantard": SIGNED_PLANTARD, "signed_plantard_alpha": SIGNED_PLANTARD_ALPHA}
+SIGNED_VARIANTS = {SIGNED, SIGNED_PLANTARD, SIGNED_PLANTARD_ALPHA}
+OP_MUL, OP_REDC, OP_POW = 0, 1, 2
+BATCH_GRAPH, BATCH_DYNAMIC, BATCH_TUNE = 1, 2, 4
+
+STATUS = {0: "MONT_OK", -1: "MONT_E_INVAL", -2: "MONT_E_DOMAIN", -3: "MONT_E_UNSUPPORTED",
+          -4: "MONT_E_NOMEM", -5: "MONT_E_DEVICE", -6: "MONT_E_BUSY"}
+
+
+class MontError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (STATUS.get(code, code), msg))
+        self.code = code
+
+
+class CtxStruct(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_uint64), ("w", ctypes.c_uint32), ("valid", ctypes.c_uint32),
+                ("nprime", ctypes.c_uint64), ("ninv", ctypes.c_uint64), ("ninv2_lo", ctypes.c_uint64),
+                ("ninv2_hi", ctypes.c_uint64), ("r_mod_n", ctypes.c_uint64), ("r2_mod_n", ctypes.c_uint64),
+                ("alpha", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class SegStruct(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_uint32), ("op", ctypes.c_uint16), ("variant", ctypes.c_uint16),
+                ("n", ctypes.c_uint64), ("off", ctypes.c_uint64), ("off1", ctypes.c_uint64)]
+
+
+class PoolsStruct(ctypes.Structure):
+    _fields_ = [("in0", ctypes.c_void_p * 3), ("in1", ctypes.c_void_p * 3), ("out", ctypes.c_void_p * 3)]
+
+
+class BatchInfoStruct(ctypes.Structure):
+    _fields_ = [("ntiles", ctypes.c_uint64), ("elements", ctypes.c_uint64), ("tile_elems", ctypes.c_uint32),
+                ("grid", ctypes.c_uint32), ("block", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class LaunchStruct(ctypes.Structure):
+    _fields_ = [("unroll", ctypes.c_uint32), ("nontemporal", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def load():
+    """Loads libmont.so (built by paper_2402_00675_amd.build); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libmont.so is not built (%s); run `python -m paper_2402_00675_amd.build`" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, u64, u32, i32, sz = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_size_t
+    P = ctypes.POINTER
+    sig = {
+        "mont_setup": (i32, [u64, u32, P(CtxStruct)]),
+        "mont_set_alpha": (i32, [P(CtxStruct), u32]),
+        "mont_redc": (i32, [P(CtxStruct), vp, vp, sz, i32, vp]),
+        "mont_mul": (i32, [P(CtxStruct), vp, vp, vp, sz, i32, vp]),
+        "mont_mul_rns": (i32, [P(CtxStruct), u32, vp, vp, vp, sz, sz, i32, vp]),
+        "mont_pow": (i32, [P(CtxStruct), vp, vp, vp, sz, vp]),
+        "mont_redc_range": (i32, [P(CtxStruct), u64, vp, sz, i32, vp]),
+        "mont_batch_create": (i32, [P(CtxStruct), u32, P(SegStruct), u32, u32, P(vp), vp]),
+        "mont_batch_run": (i32, [vp, P(PoolsStruct), vp]),
+        "mont_batch_run_pervector": (i32, [vp, P(PoolsStruct), vp]),
+        "mont_mul_ragged": (i32, [vp, P(PoolsStruct), vp]),
+        "mont_redc_ragged": (i32, [vp, P(PoolsStruct), vp]),
+        "mont_pow_ragged": (i32, [vp, P(PoolsStruct), vp]),
+        "mont_batch_info": (i32, [vp, P(BatchInfoStruct)]),
+        "mont_batch_destroy": (None, [vp]),
+        "mont_tune_mul": (i32, [P(CtxStruct), vp, vp, vp, sz, i32, P(LaunchStruct), vp]),
+        "mont_set_launch": (i32, [u32, u32, i32, P(LaunchStruct)]),
+        "mont_get_launch": (i32, [u32, u32, i32, P(LaunchStruct)]),
+        "mont_last_error": (ctypes.c_char_p, []),
+        "mont_version": (u32, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def header_functions(path: str = HEADER) -> list:
+    """Names of the functions include/mont.h declares."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mont_[a-z0-9_]+)\s*\(", text)))
+
+
+def check(rc: int):
+    if rc != 0:
+        raise MontError(rc, load().mont_last_error().decode(errors="replace"))
+
+
+def variant_id(v) -> int:
+    return VARIANTS[v] if isinstance(v, str) else int(v)
+
+
+# ------------------------------------------------------------------ contexts
+
+
+class Ctx:
+    """Per-modulus constants (mont_setup)."""
+
+    def __init__(self, N: int, w: int):
+        self.s = CtxStruct()
+        check(load().mont_setup(N, w, ctypes.byref(self.s)))
+
+    @property
+    def N(self):
+        return int(self.s.N)
+
+    @property
+    def w(self):
+        return int(self.s.w)
+
+    def valid(self, variant) -> bool:
+        return bool(self.s.valid >> variant_id(variant) & 1)
+
+    def set_alpha(self, alpha: int):
+        check(load().mont_set_alpha(ctypes.byref(self.s), alpha))
+        return self
+
+    def as_dict(self):
+        return {f: getattr(self.s, f) for f, _ in CtxStruct._fields_}
+
+
+def setup(N: int, w: int) -> Ctx:
+    return Ctx(N, w)
+
+
+# ------------------------------------------------------------------ tensors
+
+_ELEM_BYTES = {16: 2, 32: 4, 64: 8}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    """The hipStream_t to enqueue on: the given torch stream, else torch's current one."""
+    if stream is None:
+        torch = _torch()
+        if not torch.cuda.is_available():
+            return ctypes.c_void_p(None)  # the library reports the missing device itself
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, what, nbytes_per, n):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("%s must be a CUDA (HIP) tensor" % what)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    if t.numel() * t.element_size() < nbytes_per * n:
+        raise ValueError("%s holds fewer than %d elements" % (what, n))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def elem_dtype(w: int, variant=CLASSIC):
+    torch = _torch()
+    s = variant_id(variant) in SIGNED_VARIANTS
+    return {16: torch.int16 if s else torch.uint16, 32: torch.int32 if s else torch.uint32,
+            64: torch.int64 if s else torch.uint64}[w]
+
+
+def mul(ctx: Ctx, a, b, out=None, variant="classic", stream=None):
+    n = a.numel()
+    eb = _ELEM_BYTES[ctx.w]
+    if out is None:
+        out = _torch().empty(n, dtype=elem_dtype(ctx.w, variant), device=a.device)
+    check(load().mont_mul(ctypes.byref(ctx.s), _dev(a, "a", eb, n), _dev(b, "b", eb, n), _dev(out, "out", eb, n),
+                          n, variant_id(variant), _stream(stream)))
+    return out
+
+
+def redc(ctx: Ctx, T, n: int | None = None, out=None, variant="classic", stream=None):
+    eb = _ELEM_BYTES[ctx.w]
+    if n is None:
+        n = T.numel() * T.element_size() // (2 * eb)
+    if out is None:
+        out = _torch().empty(n, dtype=elem_dtype(ctx.w, variant), device=T.device)
+    check(load().mont_redc(ctypes.byref(ctx.s), _dev(T, "T", 2 * eb, n), _dev(out, "out", eb, n), n,
+                           variant_id(variant), _stream(stream)))
+    return out
+
+
+def mul_rns(ctxs, a, b, out=None, n: int | None = None, variant="classic", stream=None):
+    k, ld = a.shape
+    n = ld if n is None else n
+    eb = _ELEM_BYTES[ctxs[0].w]
+    arr = (CtxStruct * k)(*[c.s for c in ctxs])
+    if out is None:
+        out = _torch().empty_like(a)
+    check(load().mont_mul_rns(arr, k, _dev(a, "a", eb, k * ld), _dev(b, "b", eb, k * ld),
+                              _dev(out, "out", eb, k * ld), n, ld, variant_id(variant), _stream(stream)))
+    return out
+
+
+def pow(ctx: Ctx, x, e, out=None, stream=None):  # noqa: A001
+    n = x.numel()
+    eb = _ELEM_BYTES[ctx.w]
+    if out is None:
+        out = _torch().empty_like(x)
+    check(load().mont_pow(ctypes.byref(ctx.s), _dev(x, "x", eb, n), _dev(e, "e", 8, n), _dev(out, "out", eb, n),
+                          n, _stream(stream)))
+    return out
+
+
+def redc_range(ctx: Ctx, T0: int, n: int, out=None, variant="classic", stream=None):
+    eb = _ELEM_BYTES[ctx.w]
+    if out is None:
+        out = _torch().empty(n, dtype=elem_dtype(ctx.w, variant), device="cuda")
+    check(load().mont_redc_range(ctypes.byref(ctx.s), T0, _dev(out, "out", eb, n), n, variant_id(variant),
+                                 _stream(stream)))
+    return out
+
+
+def set_launch(op: int, w: int, variant, unroll=2, nontemporal=0, blocks_per_cu=0):
+    L = LaunchStruct(unroll, nontemporal, blocks_per_cu)
+    check(load().mont_set_launch(op, w, variant_id(variant), ctypes.byref(L)))
+
+
+def get_launch(op: int, w: int, variant="classic"):
+    L = LaunchStruct()
+    check(load().mont_get_launch(op, w, variant_id(variant), ctypes.byref(L)))
+    return {"unroll": L.unroll, "nontemporal": L.nontemporal, "blocks_per_cu": L.blocks_per_cu}
+
+
+def tune_mul(ctx: Ctx, a, b, out, variant="classic", stream=None):
+    n = a.numel()
+    eb = _ELEM_BYTES[ctx.w]
+    L = LaunchStruct()
+    check(load().mont_tune_mul(ctypes.byref(ctx.s), _dev(a, "a", eb, n), _dev(b, "b", eb, n),
+                               _dev(out, "out", eb, n), n, variant_id(variant), ctypes.byref(L), _stream(stream)))
+    return {"unroll": L.unroll, "nontemporal": L.nontemporal, "blocks_per_cu": L.blocks_per_cu}
+
+
+# ------------------------------------------------------------------- batches
+
+
+def pools(in0=(None, None, None), in1=(None, None, None), out=(None, None, None)) -> PoolsStruct:
+    """Pools by word-size class [16, 32, 64]; entries are CUDA tensors or None."""
+    p = PoolsStruct()
+    for i in range(3):
+        p.in0[i] = in0[i].data_ptr() if in0[i] is not None else None
+        p.in1[i] = in1[i].data_ptr() if in1[i] is not None else None
+        p.out[i] = out[i].data_ptr() if out[i] is not None else None
+    return p
+
+
+class Batch:
+    """A ragged batch (mont_batch_create).
+
+    segs: tuples (ctx index, op, variant, n, off[, off1]); off1 defaults to off.
+    """
+
+    def __init__(self, ctxs, segs, flags=0, stream=None):
+        arr = (CtxStruct * max(len(ctxs), 1))(*[c.s for c in ctxs])
+        sa = (SegStruct * max(len(segs), 1))()
+        for i, sg in enumerate(segs):
+            ci, op, var, n, off = sg[:5]
+            off1 = sg[5] if len(sg) > 5 else off
+            sa[i].ctx, sa[i].op, sa[i].variant, sa[i].n, sa[i].off, sa[i].off1 = ci, op, variant_id(var), n, off, off1
+        self.h = ctypes.c_void_p()
+        check(load().mont_batch_create(arr, len(ctxs), sa, len(segs), flags, ctypes.byref(self.h),
+                                       _stream(stream)))
+
+    def run(self, p: PoolsStruct, stream=None):
+        check(load().mont_batch_run(self.h, ctypes.byref(p), _stream(stream)))
+
+    def run_pervector(self, p: PoolsStruct, stream=None):
+        check(load().mont_batch_run_pervector(self.h, ctypes.byref(p), _stream(stream)))
+
+    def run_op(self, op: int, p: PoolsStruct, stream=None):
+        f = {OP_MUL: load().mont_mul_ragged, OP_REDC: load().mont_redc_ragged, OP_POW: load().mont_pow_ragged}[op]
+        check(f(self.h, ctypes.byref(p), _stream(stream)))
+
+    def info(self):
+        i = BatchInfoStruct()
+        check(load().mont_batch_info(self.h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in BatchInfoStruct._fields_}
+
+    def close(self):
+        if self.h:
+            load().mont_batch_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def as_numpy_u64(t) -> np.ndarray:
+    """Copies a CUDA tensor to host numpy, keeping unsigned dtypes."""
+    return t.cpu().numpy()

@@ -1,0 +1,373 @@
+// C ABI: per-modulus setup, argument checking and launches of the streaming,
+// exponentiation and range kernels.  See include/mont.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "../../include/mont.h"
+#include "mont_common.hpp"
+#include "mont_kernels.hpp"
+
+namespace mont {
+
+// ------------------------------------------------------------ error text
+
+static thread_local std::string g_err;
+
+mont_status_t fail(mont_status_t code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+mont_status_t hip_fail(hipError_t e, const char *what)
+{
+    return fail(MONT_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int device_cus()
+{
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return 256;
+    if (!cus[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+            v = 256;
+        cus[dev] = v;
+    }
+    return cus[dev];
+}
+
+KCtx to_kctx(const mont_ctx_t &c)
+{
+    KCtx k;
+    k.N = c.N;
+    k.nprime = c.nprime;
+    k.ninv = c.ninv;
+    k.n2lo = c.ninv2_lo;
+    k.n2hi = c.ninv2_hi;
+    k.r2 = c.r2_mod_n;
+    k.rmodn = c.r_mod_n;
+    k.alpha = c.alpha;
+    k.w = c.w;
+    return k;
+}
+
+int width_class(uint32_t w) { return w == 16 ? 0 : w == 32 ? 1 : w == 64 ? 2 : -1; }
+
+// ------------------------------------------------------- launch shapes
+
+static std::mutex g_launch_mu;
+static Launch g_launch[3][3][NVARIANT];  // [op][width class][variant]
+static bool g_launch_init = false;
+
+static void launch_defaults()
+{
+    if (g_launch_init)
+        return;
+    for (auto &a : g_launch)
+        for (auto &b : a)
+            for (auto &l : b)
+                l = Launch{};
+    g_launch_init = true;
+}
+
+Launch get_launch(int op, int wc, int variant)
+{
+    std::lock_guard<std::mutex> g(g_launch_mu);
+    launch_defaults();
+    return g_launch[op][wc][variant];
+}
+
+void set_launch(int op, int wc, int variant, const Launch &l)
+{
+    std::lock_guard<std::mutex> g(g_launch_mu);
+    launch_defaults();
+    g_launch[op][wc][variant] = l;
+}
+
+// -------------------------------------------------------------- checks
+
+mont_status_t check_ctx(const mont_ctx_t *ctx)
+{
+    if (!ctx)
+        return fail(MONT_E_INVAL, "null context");
+    if (width_class(ctx->w) < 0 || ctx->N < 3 || !(ctx->N & 1u) || (ctx->w < 64 && (ctx->N >> ctx->w)))
+        return fail(MONT_E_INVAL, "context not initialised by mont_setup");
+    return MONT_OK;
+}
+
+mont_status_t check_variant(const mont_ctx_t *ctx, int variant)
+{
+    if (variant < 0 || variant >= NVARIANT)
+        return fail(MONT_E_INVAL, "unknown variant %d", variant);
+    if (!(ctx->valid & (1u << variant)))
+        return fail(MONT_E_DOMAIN, "variant %d is not valid for N=%llu at w=%u", variant,
+                    (unsigned long long)ctx->N, ctx->w);
+    if (variant == SIGNED_PLANTARD_ALPHA && ctx->alpha < 1)
+        return fail(MONT_E_DOMAIN, "Algorithm 4 needs alpha >= 1");
+    return MONT_OK;
+}
+
+}  // namespace mont
+
+using namespace mont;
+
+// ===================================================================== ABI
+
+extern "C" {
+
+const char *mont_last_error(void) { return g_err.c_str(); }
+
+uint32_t mont_version(void) { return (1u << 16) | 1u; }
+
+mont_status_t mont_setup(uint64_t N, uint32_t log2R, mont_ctx_t *ctx) { return setup_ctx(N, log2R, ctx); }
+
+mont_status_t mont_set_alpha(mont_ctx_t *ctx, uint32_t alpha)
+{
+    mont_status_t rc = check_ctx(ctx);
+    if (rc)
+        return rc;
+    if (alpha < 1)
+        return fail(MONT_E_DOMAIN, "alpha = 0 makes Algorithm 4 incorrect (Example 3.1)");
+    if (alpha + 2 > ctx->w || (ctx->N >> (ctx->w - alpha - 1)) != 0)
+        return fail(MONT_E_DOMAIN, "Algorithm 4 needs N < 2^(w - alpha - 1)");
+    ctx->alpha = alpha;
+    ctx->valid |= 1u << SIGNED_PLANTARD_ALPHA;
+    return MONT_OK;
+}
+
+static mont_status_t run_map(int op, const mont_ctx_t *ctxs, uint32_t rows, const void *in0, const void *in1,
+                             void *out, size_t n, size_t ld, mont_variant_t variant, void *stream)
+{
+    for (uint32_t r = 0; r < rows; ++r) {
+        mont_status_t rc = check_ctx(&ctxs[r]);
+        if (rc)
+            return rc;
+        if (ctxs[r].w != ctxs[0].w)
+            return fail(MONT_E_INVAL, "all residue rows must share one word size");
+        rc = check_variant(&ctxs[r], variant);
+        if (rc)
+            return rc;
+    }
+    if (n == 0)
+        return MONT_OK;
+    if (!in0 || !out || (op == 0 && !in1))
+        return fail(MONT_E_INVAL, "null data pointer");
+    KCtx k[MAX_ROWS];
+    for (uint32_t r = 0; r < rows; ++r)
+        k[r] = to_kctx(ctxs[r]);
+    MapArgs a;
+    a.op = op;
+    a.variant = variant;
+    a.rows = (int)rows;
+    a.ctx = k;
+    a.in0 = in0;
+    a.in1 = in1;
+    a.out = out;
+    a.n = n;
+    a.ld = ld;
+    const int wc = width_class(ctxs[0].w);
+    const Launch L = get_launch(op, wc, variant);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = wc == 0 ? launch_map<16>(a, L, s) : wc == 1 ? launch_map<32>(a, L, s) : launch_map<64>(a, L, s);
+    if (e != hipSuccess)
+        return hip_fail(e, op == 0 ? "mont_mul launch" : "mont_redc launch");
+    return MONT_OK;
+}
+
+mont_status_t mont_redc(const mont_ctx_t *ctx, const void *T, void *out, size_t n, mont_variant_t variant,
+                        void *stream)
+{
+    return run_map(1, ctx, 1, T, nullptr, out, n, n, variant, stream);
+}
+
+mont_status_t mont_mul(const mont_ctx_t *ctx, const void *a, const void *b, void *out, size_t n,
+                       mont_variant_t variant, void *stream)
+{
+    return run_map(0, ctx, 1, a, b, out, n, n, variant, stream);
+}
+
+mont_status_t mont_mul_rns(const mont_ctx_t *ctxs, uint32_t k, const void *a, const void *b, void *out, size_t n,
+                           size_t ld, mont_variant_t variant, void *stream)
+{
+    if (!ctxs || k < 1 || k > MONT_RNS_MAX)
+        return fail(MONT_E_INVAL, "need 1 <= k <= %d contexts", MONT_RNS_MAX);
+    if (n > ld)
+        return fail(MONT_E_INVAL, "n > ld");
+    return run_map(0, ctxs, k, a, b, out, n, ld, variant, stream);
+}
+
+mont_status_t mont_pow(const mont_ctx_t *ctx, const void *x, const uint64_t *e, void *out, size_t n, void *stream)
+{
+    mont_status_t rc = check_ctx(ctx);
+    if (rc)
+        return rc;
+    if (n == 0)
+        return MONT_OK;
+    if (!x || !e || !out)
+        return fail(MONT_E_INVAL, "null data pointer");
+    const KCtx k = to_kctx(*ctx);
+    const int wc = width_class(ctx->w);
+    const Launch L = get_launch(2, wc, CLASSIC);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t err = wc == 0   ? launch_pow<16>(k, x, e, out, n, L.unroll, L.blocks_per_cu, s)
+                     : wc == 1 ? launch_pow<32>(k, x, e, out, n, L.unroll, L.blocks_per_cu, s)
+                               : launch_pow<64>(k, x, e, out, n, L.unroll, L.blocks_per_cu, s);
+    if (err != hipSuccess)
+        return hip_fail(err, "mont_pow launch");
+    return MONT_OK;
+}
+
+mont_status_t mont_redc_range(const mont_ctx_t *ctx, uint64_t T0, void *out, size_t n, mont_variant_t variant,
+                              void *stream)
+{
+    mont_status_t rc = check_ctx(ctx);
+    if (rc)
+        return rc;
+    rc = check_variant(ctx, variant);
+    if (rc)
+        return rc;
+    if (variant != MONT_CLASSIC && variant != MONT_PLANTARD)
+        return fail(MONT_E_UNSUPPORTED, "mont_redc_range covers the unsigned variants");
+    if (ctx->w == 64)
+        return fail(MONT_E_UNSUPPORTED, "mont_redc_range covers w = 16 and 32");
+    if (n == 0)
+        return MONT_OK;
+    // the last T must stay in the Require range: T < R N (classic), T <= N^2 (Plantard)
+    const unsigned __int128 last = (unsigned __int128)T0 + n - 1;
+    const unsigned __int128 lim = variant == MONT_CLASSIC ? ((unsigned __int128)ctx->N << ctx->w) - 1
+                                                          : (unsigned __int128)ctx->N * ctx->N;
+    if (last > lim)
+        return fail(MONT_E_DOMAIN, "range leaves the variant's input range");
+    if (!out)
+        return fail(MONT_E_INVAL, "null output");
+    const KCtx k = to_kctx(*ctx);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = ctx->w == 16 ? launch_range<16>(k, variant, T0, out, n, s)
+                                : launch_range<32>(k, variant, T0, out, n, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "mont_redc_range launch");
+    return MONT_OK;
+}
+
+mont_status_t mont_set_launch(uint32_t op, uint32_t w, mont_variant_t variant, const mont_launch_t *l)
+{
+    const int wc = width_class(w);
+    if (op > 2 || wc < 0 || (int)variant < 0 || (int)variant >= NVARIANT || !l)
+        return fail(MONT_E_INVAL, "bad launch key");
+    if (l->unroll != 1 && l->unroll != 2 && l->unroll != 4)
+        return fail(MONT_E_INVAL, "unroll must be 1, 2 or 4");
+    Launch L;
+    L.unroll = (int)l->unroll;
+    L.nontemporal = l->nontemporal ? 1 : 0;
+    L.blocks_per_cu = (int)l->blocks_per_cu;
+    set_launch((int)op, wc, (int)variant, L);
+    return MONT_OK;
+}
+
+mont_status_t mont_get_launch(uint32_t op, uint32_t w, mont_variant_t variant, mont_launch_t *l)
+{
+    const int wc = width_class(w);
+    if (op > 2 || wc < 0 || (int)variant < 0 || (int)variant >= NVARIANT || !l)
+        return fail(MONT_E_INVAL, "bad launch key");
+    const Launch L = get_launch((int)op, wc, (int)variant);
+    l->unroll = (uint32_t)L.unroll;
+    l->nontemporal = (uint32_t)L.nontemporal;
+    l->blocks_per_cu = (uint32_t)L.blocks_per_cu;
+    return MONT_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ tuning
+
+namespace mont {
+
+static void save_tuned(int op, uint32_t w, int variant, const Launch &L, float ms)
+{
+    const char *path = std::getenv("MONT_TUNE_CACHE");
+    if (!path || !*path)
+        return;
+    FILE *f = std::fopen(path, "a");
+    if (!f)
+        return;
+    std::fprintf(f,
+                 "{\"op\": %d, \"w\": %u, \"variant\": %d, \"unroll\": %d, \"nontemporal\": %d, "
+                 "\"blocks_per_cu\": %d, \"ms\": %.5f}\n",
+                 op, w, variant, L.unroll, L.nontemporal, L.blocks_per_cu, ms);
+    std::fclose(f);
+}
+
+}  // namespace mont
+
+extern "C" mont_status_t mont_tune_mul(const mont_ctx_t *ctx, const void *a, const void *b, void *out, size_t n,
+                                       mont_variant_t variant, mont_launch_t *best, void *stream)
+{
+    mont_status_t rc = check_ctx(ctx);
+    if (rc)
+        return rc;
+    rc = check_variant(ctx, variant);
+    if (rc)
+        return rc;
+    if (n == 0 || !a || !b || !out)
+        return fail(MONT_E_INVAL, "tuning needs non-empty device buffers");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(MONT_E_DEVICE, "event create");
+    const int wc = width_class(ctx->w);
+    const Launch saved = get_launch(0, wc, variant);
+    Launch bestL = saved;
+    float best_ms = 1e30f;
+    const int unrolls[] = {1, 2, 4};
+    const int bpcs[] = {0, 4, 8, 16};
+    for (int u : unrolls)
+        for (int nt = 0; nt < 2; ++nt)
+            for (int bpc : bpcs) {
+                Launch L;
+                L.unroll = u;
+                L.nontemporal = nt;
+                L.blocks_per_cu = bpc;
+                set_launch(0, wc, variant, L);
+                rc = mont_mul(ctx, a, b, out, n, variant, stream);  // warm
+                (void)hipEventRecord(e0, s);
+                for (int r = 0; r < 5 && !rc; ++r)
+                    rc = mont_mul(ctx, a, b, out, n, variant, stream);
+                (void)hipEventRecord(e1, s);
+                if (!rc && hipEventSynchronize(e1) != hipSuccess)
+                    rc = fail(MONT_E_DEVICE, "tuning run failed");
+                if (rc)
+                    break;
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    bestL = L;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    set_launch(0, wc, variant, rc ? saved : bestL);
+    if (rc)
+        return rc;
+    save_tuned(0, ctx->w, variant, bestL, best_ms / 5);
+    if (best) {
+        best->unroll = (uint32_t)bestL.unroll;
+        best->nontemporal = (uint32_t)bestL.nontemporal;
+        best->blocks_per_cu = (uint32_t)bestL.blocks_per_cu;
+    }
+    return MONT_OK;
+}

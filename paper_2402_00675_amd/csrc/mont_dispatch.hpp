@@ -1,0 +1,149 @@
+// Host-side launch templates for the streaming, exponentiation and range
+// kernels.  Each word size is instantiated in its own translation unit
+// (mont_k16.hip, mont_k32.hip, mont_k64.hip) so the builds run in parallel.
+#pragma once
+
+#include <algorithm>
+
+#include "mont_kernels.hpp"
+
+namespace mont {
+
+inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+template <int W, int V, int OP, int E, int U, bool NT>
+hipError_t go_map(const MapArgs &a, dim3 grid, hipStream_t s)
+{
+    if (a.rows == 1) {
+        KTab<1> t;
+        t.c[0] = a.ctx[0];
+        hipLaunchKernelGGL((k_map<W, V, OP, E, U, NT, 1>), grid, dim3(BLOCK), 0, s, t, a.in0, a.in1, a.out, a.n,
+                           a.ld);
+    } else if constexpr (OP == 0) {
+        KTab<MAX_ROWS> t{};
+        for (int r = 0; r < a.rows; ++r)
+            t.c[r] = a.ctx[r];
+        hipLaunchKernelGGL((k_map<W, V, OP, E, U, NT, MAX_ROWS>), grid, dim3(BLOCK), 0, s, t, a.in0, a.in1,
+                           a.out, a.n, a.ld);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+inline uint64_t grid_x(uint64_t nchunk, int per_thread, int rows, const Launch &L)
+{
+    const uint64_t per_block = (uint64_t)BLOCK * per_thread;
+    uint64_t gx = (nchunk + per_block - 1) / per_block;
+    if (L.blocks_per_cu > 0) {
+        const uint64_t cap = std::max<uint64_t>(1, (uint64_t)device_cus() * L.blocks_per_cu / rows);
+        gx = std::min(gx, cap);
+    }
+    return std::min<uint64_t>(std::max<uint64_t>(gx, 1), 0x7fffffffu);
+}
+
+template <int W, int V, int OP>
+hipError_t launch_map_v(const MapArgs &a, const Launch &L, hipStream_t s)
+{
+    using R = Red<W, V>;
+    using El = typename R::E;
+    constexpr int E = 16 / (int)sizeof(El);
+    const bool vec = aligned16(a.in0) && (OP == 1 || aligned16(a.in1)) && aligned16(a.out) &&
+                     (a.rows == 1 || (a.ld * sizeof(El)) % 16 == 0);
+    if (!vec) {
+        dim3 grid((unsigned)grid_x(a.n, 1, a.rows, L), (unsigned)a.rows);
+        return go_map<W, V, OP, 1, 1, false>(a, grid, s);
+    }
+    const int U = (L.unroll == 4 || L.unroll == 1) ? L.unroll : 2;
+    dim3 grid((unsigned)grid_x(a.n / E, U, a.rows, L), (unsigned)a.rows);
+    if (L.nontemporal) {
+        if (U == 1)
+            return go_map<W, V, OP, E, 1, true>(a, grid, s);
+        if (U == 2)
+            return go_map<W, V, OP, E, 2, true>(a, grid, s);
+        return go_map<W, V, OP, E, 4, true>(a, grid, s);
+    }
+    if (U == 1)
+        return go_map<W, V, OP, E, 1, false>(a, grid, s);
+    if (U == 2)
+        return go_map<W, V, OP, E, 2, false>(a, grid, s);
+    return go_map<W, V, OP, E, 4, false>(a, grid, s);
+}
+
+template <int W, int OP>
+hipError_t launch_map_op(const MapArgs &a, const Launch &L, hipStream_t s)
+{
+    switch (a.variant) {
+    case CLASSIC:
+        return launch_map_v<W, CLASSIC, OP>(a, L, s);
+    case SIGNED:
+        return launch_map_v<W, SIGNED, OP>(a, L, s);
+    case PLANTARD:
+        return launch_map_v<W, PLANTARD, OP>(a, L, s);
+    case SIGNED_PLANTARD:
+        return launch_map_v<W, SIGNED_PLANTARD, OP>(a, L, s);
+    case SIGNED_PLANTARD_ALPHA:
+        return launch_map_v<W, SIGNED_PLANTARD_ALPHA, OP>(a, L, s);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+template <int W>
+hipError_t launch_map(const MapArgs &a, const Launch &L, hipStream_t s)
+{
+    return a.op == 0 ? launch_map_op<W, 0>(a, L, s) : launch_map_op<W, 1>(a, L, s);
+}
+
+template <int W>
+hipError_t launch_pow(const KCtx &c, const void *x, const uint64_t *e, void *out, uint64_t n, int unroll,
+                      int blocks_per_cu, hipStream_t s)
+{
+    Launch L;
+    L.blocks_per_cu = blocks_per_cu;
+    const int U = unroll == 2 ? 2 : 1;
+    dim3 grid((unsigned)grid_x(n, U, 1, L));
+    if (U == 2)
+        hipLaunchKernelGGL((k_pow<W, 2>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
+    else
+        hipLaunchKernelGGL((k_pow<W, 1>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
+    return hipGetLastError();
+}
+
+template <int W>
+hipError_t launch_range(const KCtx &c, int variant, uint64_t T0, void *out, uint64_t n, hipStream_t s)
+{
+    if constexpr (W == 64) {
+        return hipErrorInvalidValue;
+    } else {
+        using El = typename Red<W, CLASSIC>::E;
+        constexpr int E = 16 / (int)sizeof(El);
+        Launch L;
+        const bool vec = aligned16(out);
+        dim3 grid((unsigned)grid_x(vec ? n / E : n, 1, 1, L));
+        if (variant == CLASSIC) {
+            if (vec)
+                hipLaunchKernelGGL((k_range<W, CLASSIC, E>), grid, dim3(BLOCK), 0, s, c, T0, out, n);
+            else
+                hipLaunchKernelGGL((k_range<W, CLASSIC, 1>), grid, dim3(BLOCK), 0, s, c, T0, out, n);
+        } else if (variant == PLANTARD) {
+            if (vec)
+                hipLaunchKernelGGL((k_range<W, PLANTARD, E>), grid, dim3(BLOCK), 0, s, c, T0, out, n);
+            else
+                hipLaunchKernelGGL((k_range<W, PLANTARD, 1>), grid, dim3(BLOCK), 0, s, c, T0, out, n);
+        } else {
+            return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+}
+
+}  // namespace mont
+
+#define MONT_INSTANTIATE_WIDTH(W)                                                                             \
+    namespace mont {                                                                                          \
+    template hipError_t launch_map<W>(const MapArgs &, const Launch &, hipStream_t);                          \
+    template hipError_t launch_pow<W>(const KCtx &, const void *, const uint64_t *, void *, uint64_t, int, int, \
+                                      hipStream_t);                                                           \
+    template hipError_t launch_range<W>(const KCtx &, int, uint64_t, void *, uint64_t, hipStream_t);          \
+    }

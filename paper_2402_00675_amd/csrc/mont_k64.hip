@@ -1,0 +1,4 @@
+// Streaming, exponentiation and range kernels for 64-bit words.
+#include "mont_dispatch.hpp"
+
+MONT_INSTANTIATE_WIDTH(64)

@@ -1,0 +1,294 @@
+// Streaming, exponentiation and exhaustive-range kernels for gfx950.
+//
+// Streaming kernels (mont_mul, mont_redc) are HBM-bound: each lane moves
+// 16-byte chunks (8 x u16, 4 x u32 or 2 x u64 residues) with optional
+// non-temporal hints, U chunks in flight per lane, a grid-stride loop whose
+// grid is either one pass over the data or a multiple of the CU count, and a
+// scalar tail.  Per-modulus constants are kernel arguments (wave-uniform, so
+// they live in SGPRs); a residue-number-system call indexes a by-value table
+// of contexts with the row number blockIdx.y.
+#pragma once
+
+#include "mont_arith.hpp"
+
+namespace mont {
+
+constexpr int BLOCK = 256;
+constexpr int MAX_ROWS = 32;
+
+template <int NR>
+struct KTab {
+    KCtx c[NR];
+};
+
+struct Launch {
+    int unroll = 2;        // 1, 2, 4
+    int nontemporal = 0;   // 0 / 1
+    int blocks_per_cu = 0; // 0: one pass
+};
+
+struct MapArgs {
+    int op;        // 0 mul, 1 redc
+    int variant;
+    int rows;      // >= 1
+    const KCtx *ctx;  // rows entries (host)
+    const void *in0, *in1;
+    void *out;
+    uint64_t n, ld;   // per row: n elements, row stride ld elements
+};
+
+// ------------------------------------------------------------ memory helpers
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+template <int B>
+struct Raw;
+template <>
+struct Raw<16> {
+    using type = u32x4;
+};
+template <>
+struct Raw<8> {
+    using type = u32x2;
+};
+template <>
+struct Raw<4> {
+    using type = uint32_t;
+};
+template <>
+struct Raw<2> {
+    using type = uint16_t;
+};
+
+template <int B, bool NT>
+__device__ __forceinline__ typename Raw<B>::type ld_raw(const void *p)
+{
+    using R = typename Raw<B>::type;
+    if constexpr (NT)
+        return __builtin_nontemporal_load((const R *)p);
+    else
+        return *(const R *)p;
+}
+
+template <int B, bool NT>
+__device__ __forceinline__ void st_raw(void *p, typename Raw<B>::type v)
+{
+    using R = typename Raw<B>::type;
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, (R *)p);
+    else
+        *(R *)p = v;
+}
+
+// E consecutive X's, loaded with 16-byte (or narrower) accesses.
+template <class X, int E, bool NT>
+__device__ __forceinline__ void load_chunk(const X *p, X (&v)[E])
+{
+    constexpr int B = E * (int)sizeof(X);
+    if constexpr (B <= 16) {
+        auto r = ld_raw<B, NT>(p);
+        __builtin_memcpy(&v[0], &r, B);
+    } else {
+#pragma unroll
+        for (int k = 0; k < B / 16; ++k) {
+            auto r = ld_raw<16, NT>((const char *)p + 16 * k);
+            __builtin_memcpy((char *)&v[0] + 16 * k, &r, 16);
+        }
+    }
+}
+
+template <class X, int E, bool NT>
+__device__ __forceinline__ void store_chunk(X *p, const X (&v)[E])
+{
+    constexpr int B = E * (int)sizeof(X);
+    static_assert(B <= 16, "stores are at most 16 bytes");
+    typename Raw<B>::type r;
+    __builtin_memcpy(&r, &v[0], B);
+    st_raw<B, NT>(p, r);
+}
+
+// ------------------------------------------------------------------ kernels
+
+// out[i] = red.mul(a[i], b[i]) (OP 0) or red.redc(T[i]) (OP 1), per row.
+template <int W, int V, int OP, int E, int U, bool NT, int NR>
+__global__ void __launch_bounds__(BLOCK)
+    k_map(KTab<NR> tab, const void *__restrict__ in0, const void *__restrict__ in1, void *__restrict__ out,
+          uint64_t n, uint64_t ld)
+{
+    using R = Red<W, V>;
+    using El = typename R::E;
+    using TT = typename R::TT;
+    const R red(tab.c[NR == 1 ? 0 : blockIdx.y]);
+    const uint64_t row = (uint64_t)blockIdx.y * ld;
+    const El *pa = (const El *)in0 + row;
+    const El *pb = (const El *)in1 + row;
+    const TT *pt = (const TT *)in0 + row;
+    El *po = (El *)out + row;
+
+    const uint64_t nchunk = n / E;
+    const uint64_t step = (uint64_t)gridDim.x * (BLOCK * U);
+    for (uint64_t base = (uint64_t)blockIdx.x * (BLOCK * U) + threadIdx.x; base < nchunk; base += step) {
+        El a[U][E], b[U][E];
+        TT t[U][E];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = base + (uint64_t)u * BLOCK;
+            if (i < nchunk) {
+                if constexpr (OP == 0) {
+                    load_chunk<El, E, NT>(pa + i * E, a[u]);
+                    load_chunk<El, E, NT>(pb + i * E, b[u]);
+                } else {
+                    load_chunk<TT, E, NT>(pt + i * E, t[u]);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = base + (uint64_t)u * BLOCK;
+            if (i < nchunk) {
+                El o[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    if constexpr (OP == 0)
+                        o[e] = red.mul(a[u][e], b[u][e]);
+                    else
+                        o[e] = red.redc(t[u][e]);
+                }
+                store_chunk<El, E, NT>(po + i * E, o);
+            }
+        }
+    }
+    if constexpr (E > 1) {
+        // the last n mod E elements of the row
+        if (blockIdx.x == 0 && threadIdx.x < (unsigned)E) {
+            const uint64_t i = nchunk * E + threadIdx.x;
+            if (i < n) {
+                if constexpr (OP == 0)
+                    po[i] = red.mul(pa[i], pb[i]);
+                else
+                    po[i] = red.redc(pt[i]);
+            }
+        }
+    }
+}
+
+template <int W>
+struct WideT;
+template <>
+struct WideT<16> {
+    __device__ static uint32_t of(uint16_t y) { return y; }
+};
+template <>
+struct WideT<32> {
+    __device__ static uint64_t of(uint32_t y) { return y; }
+};
+template <>
+struct WideT<64> {
+    __device__ static T128 of(uint64_t y) { return {y, 0}; }
+};
+
+// 2-bit fixed-window selection, branch-free.
+template <class El>
+__device__ __forceinline__ El sel4(uint32_t d, El t0, El t1, El t2, El t3)
+{
+    const El lo = (d & 1u) ? t1 : t0;
+    const El hi = (d & 1u) ? t3 : t2;
+    return (d & 2u) ? hi : lo;
+}
+
+// x^e mod N: Montgomery form x R = REDC(x * (R^2 mod N)), a left-to-right
+// 2-bit fixed-window ladder of Montgomery products (every lane runs the same
+// 32 windows: no divergence), and REDC back to an ordinary residue.
+template <class R>
+__device__ __forceinline__ typename R::E pow_one(const R &red, typename R::E x, uint64_t k,
+                                                 typename R::E r2, typename R::E one)
+{
+    using El = typename R::E;
+    const El x1 = red.mul(x, r2);
+    const El x2 = red.sqr(x1);
+    const El x3 = red.mul(x2, x1);
+    El y = sel4<El>((uint32_t)(k >> 62), one, x1, x2, x3);
+#pragma unroll 4
+    for (int s = 60; s >= 0; s -= 2) {
+        y = red.sqr(y);
+        y = red.sqr(y);
+        y = red.mul(y, sel4<El>((uint32_t)(k >> s) & 3u, one, x1, x2, x3));
+    }
+    return y;
+}
+
+template <int W, int U>
+__global__ void __launch_bounds__(BLOCK)
+    k_pow(KCtx c, const void *__restrict__ xin, const uint64_t *__restrict__ ein, void *__restrict__ out, uint64_t n)
+{
+    using R = Red<W, CLASSIC>;
+    using El = typename R::E;
+    const R red(c);
+    const El r2 = (El)c.r2, one = (El)c.rmodn;
+    const El *px = (const El *)xin;
+    El *po = (El *)out;
+    const uint64_t step = (uint64_t)gridDim.x * (BLOCK * U);
+    for (uint64_t base = (uint64_t)blockIdx.x * (BLOCK * U) + threadIdx.x; base < n; base += step) {
+        El x[U];
+        uint64_t k[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = base + (uint64_t)u * BLOCK;
+            x[u] = i < n ? px[i] : (El)0;
+            k[u] = i < n ? ein[i] : 0;
+        }
+        El y[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            y[u] = pow_one(red, x[u], k[u], r2, one);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = base + (uint64_t)u * BLOCK;
+            if (i < n)
+                po[i] = red.redc(WideT<W>::of(y[u]));
+        }
+    }
+}
+
+// out[i] = REDC(T0 + i): exhaustive sweeps with no input traffic.
+template <int W, int V, int E>
+__global__ void __launch_bounds__(BLOCK) k_range(KCtx c, uint64_t T0, void *__restrict__ out, uint64_t n)
+{
+    using R = Red<W, V>;
+    using El = typename R::E;
+    using TT = typename R::TT;
+    const R red(c);
+    El *po = (El *)out;
+    const uint64_t nchunk = n / E;
+    const uint64_t step = (uint64_t)gridDim.x * BLOCK;
+    for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i < nchunk; i += step) {
+        El o[E];
+        const TT t0 = (TT)(T0 + i * E);
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            o[e] = red.redc((TT)(t0 + (TT)e));
+        store_chunk<El, E, false>(po + i * E, o);
+    }
+    if constexpr (E > 1) {
+        if (blockIdx.x == 0 && threadIdx.x < (unsigned)E) {
+            const uint64_t i = nchunk * E + threadIdx.x;
+            if (i < n)
+                po[i] = red.redc((TT)(T0 + i));
+        }
+    }
+}
+
+// ----------------------------------------------------------- host launchers
+
+int device_cus();
+
+template <int W>
+hipError_t launch_map(const MapArgs &a, const Launch &L, hipStream_t s);
+template <int W>
+hipError_t launch_pow(const KCtx &c, const void *x, const uint64_t *e, void *out, uint64_t n, int unroll,
+                      int blocks_per_cu, hipStream_t s);
+template <int W>
+hipError_t launch_range(const KCtx &c, int variant, uint64_t T0, void *out, uint64_t n, hipStream_t s);
+
+}  // namespace mont

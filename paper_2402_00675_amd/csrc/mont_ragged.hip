@@ -1,0 +1,653 @@
+// Ragged batches: thousands of independent vectors, each with its own
+// modulus, word size, length and operation, in ONE persistent launch.
+//
+// Host side: every segment is cut into tiles (equal output bytes for the
+// streaming ops, a fixed element count for exponentiation) and a tile table
+// {segment, start, count} plus a segment table {constants, pool offset, op,
+// variant} are uploaded once.  Device side: a persistent grid (a multiple of
+// the CU count) walks the tile table either round-robin (static) or through
+// an atomic tile counter (dynamic; the last workgroup to finish resets the
+// counter, so a replay needs no memset).  The tile's descriptor is
+// wave-uniform, so it is fetched with scalar loads and its constants stay in
+// SGPRs; the op / word size / variant switch is a uniform branch.
+//
+// Launches can be replayed from a hipGraph whose kernel node is updated in
+// place when the caller's pool pointers change.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "mont_common.hpp"
+#include "mont_ragged.hpp"
+
+namespace mont {
+
+constexpr int RAGGED_U = 4;  // 16-byte chunks in flight per lane
+
+template <int W>
+struct WC {
+    static constexpr int v = W == 16 ? 0 : W == 32 ? 1 : 2;
+};
+
+template <int W, int V, int OP>
+__device__ __forceinline__ void tile_map(const KCtx &c, const DPools &P, uint64_t g0, uint64_t g1, uint32_t cnt)
+{
+    using R = Red<W, V>;
+    using El = typename R::E;
+    using TT = typename R::TT;
+    constexpr int E = 16 / (int)sizeof(El);
+    constexpr int wc = WC<W>::v;
+    const R red(c);
+    const El *pa = (const El *)P.in0[wc];
+    // indexed by g like pa; (g1 - g0) is a multiple of E so 16-byte chunks stay aligned
+    const El *pb = (const El *)P.in1[wc] + (int64_t)(g1 - g0);
+    const TT *pt = (const TT *)P.in0[wc];
+    El *po = (El *)P.out[wc];
+
+    const uint32_t head = (uint32_t)std::min<uint64_t>(cnt, (E - g0 % E) % E);
+    if (threadIdx.x < head) {
+        const uint64_t g = g0 + threadIdx.x;
+        if constexpr (OP == 0)
+            po[g] = red.mul(pa[g], pb[g]);
+        else
+            po[g] = red.redc(pt[g]);
+    }
+    const uint64_t gv = g0 + head;  // multiple of E: 16-byte aligned for aligned pools
+    const uint32_t rest = cnt - head;
+    const uint32_t nv = rest / E;
+    for (uint32_t c0 = threadIdx.x; c0 < nv; c0 += BLOCK * RAGGED_U) {
+        El a[RAGGED_U][E], b[RAGGED_U][E];
+        TT t[RAGGED_U][E];
+#pragma unroll
+        for (int u = 0; u < RAGGED_U; ++u) {
+            const uint32_t ci = c0 + u * BLOCK;
+            if (ci < nv) {
+                const uint64_t g = gv + (uint64_t)ci * E;
+                if constexpr (OP == 0) {
+                    load_chunk<El, E, false>(pa + g, a[u]);
+                    load_chunk<El, E, false>(pb + g, b[u]);
+                } else {
+                    load_chunk<TT, E, false>(pt + g, t[u]);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RAGGED_U; ++u) {
+            const uint32_t ci = c0 + u * BLOCK;
+            if (ci < nv) {
+                El o[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    if constexpr (OP == 0)
+                        o[e] = red.mul(a[u][e], b[u][e]);
+                    else
+                        o[e] = red.redc(t[u][e]);
+                }
+                store_chunk<El, E, false>(po + gv + (uint64_t)ci * E, o);
+            }
+        }
+    }
+    const uint32_t tail = rest - nv * E;
+    if (threadIdx.x < tail) {
+        const uint64_t g = gv + (uint64_t)nv * E + threadIdx.x;
+        if constexpr (OP == 0)
+            po[g] = red.mul(pa[g], pb[g]);
+        else
+            po[g] = red.redc(pt[g]);
+    }
+}
+
+template <int W>
+__device__ __forceinline__ void tile_pow(const KCtx &c, const DPools &P, uint64_t g0, uint64_t g1, uint32_t cnt)
+{
+    using R = Red<W, CLASSIC>;
+    using El = typename R::E;
+    constexpr int wc = WC<W>::v;
+    const R red(c);
+    const El r2 = (El)c.r2, one = (El)c.rmodn;
+    const El *px = (const El *)P.in0[wc];
+    const uint64_t *pe = (const uint64_t *)P.in1[wc] + (int64_t)(g1 - g0);
+    El *po = (El *)P.out[wc];
+    for (uint32_t i = threadIdx.x; i < cnt; i += BLOCK) {
+        const uint64_t g = g0 + i;
+        const El y = pow_one(red, px[g], pe[g], r2, one);
+        po[g] = red.redc(WideT<W>::of(y));
+    }
+}
+
+template <int W, int OP>
+__device__ __forceinline__ void tile_variant(uint32_t variant, const KCtx &c, const DPools &P, uint64_t g0,
+                                             uint64_t g1, uint32_t cnt)
+{
+    switch (variant) {
+    case CLASSIC:
+        tile_map<W, CLASSIC, OP>(c, P, g0, g1, cnt);
+        break;
+    case SIGNED:
+        tile_map<W, SIGNED, OP>(c, P, g0, g1, cnt);
+        break;
+    case PLANTARD:
+        tile_map<W, PLANTARD, OP>(c, P, g0, g1, cnt);
+        break;
+    case SIGNED_PLANTARD:
+        tile_map<W, SIGNED_PLANTARD, OP>(c, P, g0, g1, cnt);
+        break;
+    default:
+        tile_map<W, SIGNED_PLANTARD_ALPHA, OP>(c, P, g0, g1, cnt);
+        break;
+    }
+}
+
+template <int W>
+__device__ __forceinline__ void tile_width(uint32_t op, uint32_t variant, const KCtx &c, const DPools &P,
+                                           uint64_t g0, uint64_t g1, uint32_t cnt)
+{
+    if (op == MONT_OP_MUL)
+        tile_variant<W, 0>(variant, c, P, g0, g1, cnt);
+    else if (op == MONT_OP_REDC)
+        tile_variant<W, 1>(variant, c, P, g0, g1, cnt);
+    else
+        tile_pow<W>(c, P, g0, g1, cnt);
+}
+
+__global__ void __launch_bounds__(BLOCK)
+    k_ragged(const DSeg *__restrict__ segs, const DTile *__restrict__ tiles, uint32_t ntiles, DPools P,
+             uint32_t *__restrict__ ctr, uint32_t dynamic)
+{
+    __shared__ uint32_t s_next[2];
+    uint32_t t;
+    int buf = 0;
+    if (dynamic) {
+        if (threadIdx.x == 0)
+            s_next[0] = atomicAdd(&ctr[0], 1u);
+        __syncthreads();
+        t = s_next[0];
+    } else {
+        t = blockIdx.x;
+    }
+    while (t < ntiles) {
+        t = __builtin_amdgcn_readfirstlane(t);
+        if (dynamic && threadIdx.x == 0)
+            s_next[buf ^ 1] = atomicAdd(&ctr[0], 1u);  // fetch the next tile while this one runs
+        const DTile td = tiles[t];
+        const DSeg &sd = segs[td.seg];
+        const uint64_t g0 = sd.off + td.start;
+        const uint64_t g1 = sd.off1 + td.start;
+        const uint32_t wc = sd.wc;
+        if (wc == 0)
+            tile_width<16>(sd.op, sd.variant, sd.c, P, g0, g1, td.cnt);
+        else if (wc == 1)
+            tile_width<32>(sd.op, sd.variant, sd.c, P, g0, g1, td.cnt);
+        else
+            tile_width<64>(sd.op, sd.variant, sd.c, P, g0, g1, td.cnt);
+        if (dynamic) {
+            __syncthreads();  // s_next[buf^1] written; everyone done with s_next[buf]
+            buf ^= 1;
+            t = s_next[buf];
+        } else {
+            t += gridDim.x;
+        }
+    }
+    if (dynamic) {
+        // Every workgroup has made its last counter increment before it gets
+        // here; the last one to arrive resets both counters for the next run.
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            const uint32_t d = atomicAdd(&ctr[1], 1u);
+            if (d == gridDim.x - 1) {
+                atomicExch(&ctr[0], 0u);
+                atomicExch(&ctr[1], 0u);
+            }
+        }
+    }
+}
+
+}  // namespace mont
+
+using namespace mont;
+
+// ------------------------------------------------------------------ host
+
+struct mont_batch {
+    int dev = 0;
+    std::vector<mont_ctx_t> ctxs;
+    std::vector<mont_seg_t> segs;
+    std::vector<DSeg> hsegs;
+    DSeg *dsegs = nullptr;
+    DTile *dtiles = nullptr;
+    uint32_t *dctr = nullptr;
+    size_t tiles_cap = 0;
+    uint32_t ntiles = 0;
+    uint64_t elements = 0;
+    uint32_t tile_base = 8192;   // 32-bit streaming tile (elements)
+    uint32_t pow_tile = 1024;
+    uint32_t blocks_per_cu = 8;
+    uint32_t grid = 0;
+    uint32_t flags = 0;
+    uint32_t op_mask = 0;
+    bool tuned = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t node = nullptr;
+    DPools last{};
+    uint32_t last_grid = 0, last_dyn = 0;
+};
+
+namespace mont {
+
+static uint32_t tile_elems(const mont_batch &b, uint32_t wc, uint32_t op)
+{
+    if (op == MONT_OP_POW)
+        return b.pow_tile;
+    // equal output bytes per tile: 16-bit tiles have twice the elements of 32-bit ones
+    return wc == 0 ? b.tile_base * 2 : wc == 1 ? b.tile_base : b.tile_base / 2;
+}
+
+static mont_status_t build_tiles(mont_batch &b, hipStream_t s)
+{
+    std::vector<DTile> pow_tiles, map_tiles;
+    for (uint32_t i = 0; i < b.segs.size(); ++i) {
+        const mont_seg_t &sg = b.segs[i];
+        const uint32_t wc = b.hsegs[i].wc;
+        const uint64_t te = tile_elems(b, wc, sg.op);
+        for (uint64_t st = 0; st < sg.n; st += te) {
+            DTile t;
+            t.seg = i;
+            t.start = st;
+            t.cnt = (uint32_t)std::min<uint64_t>(te, sg.n - st);
+            (sg.op == MONT_OP_POW ? pow_tiles : map_tiles).push_back(t);
+        }
+    }
+    // the heaviest tiles (exponentiation) first, so a dynamic schedule ends level
+    std::vector<DTile> all;
+    all.reserve(pow_tiles.size() + map_tiles.size());
+    all.insert(all.end(), pow_tiles.begin(), pow_tiles.end());
+    all.insert(all.end(), map_tiles.begin(), map_tiles.end());
+    if (all.size() >= 0xffffffffull)
+        return fail(MONT_E_INVAL, "too many tiles");
+    if (all.size() > b.tiles_cap) {
+        if (b.dtiles)
+            (void)hipFree(b.dtiles);
+        b.dtiles = nullptr;
+        const size_t cap = std::max<size_t>(all.size(), 1);
+        if (hipMalloc(&b.dtiles, cap * sizeof(DTile)) != hipSuccess)
+            return fail(MONT_E_NOMEM, "tile table of %zu entries", cap);
+        b.tiles_cap = cap;
+    }
+    b.ntiles = (uint32_t)all.size();
+    if (!all.empty()) {
+        hipError_t e = hipMemcpyAsync(b.dtiles, all.data(), all.size() * sizeof(DTile), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "tile table upload");
+        e = hipStreamSynchronize(s);  // the host vector dies here
+        if (e != hipSuccess)
+            return hip_fail(e, "tile table upload");
+    }
+    const uint64_t g = (uint64_t)device_cus() * b.blocks_per_cu;
+    b.grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, b.ntiles));
+    return MONT_OK;
+}
+
+static DPools to_dpools(const mont_pools_t &p)
+{
+    DPools d;
+    for (int i = 0; i < 3; ++i) {
+        d.in0[i] = p.in0[i];
+        d.in1[i] = p.in1[i];
+        d.out[i] = p.out[i];
+    }
+    return d;
+}
+
+static mont_status_t check_pools(const mont_batch &b, const mont_pools_t *p)
+{
+    if (!p)
+        return fail(MONT_E_INVAL, "null pools");
+    for (size_t i = 0; i < b.segs.size(); ++i) {
+        const mont_seg_t &sg = b.segs[i];
+        if (!sg.n)
+            continue;
+        const uint32_t wc = b.hsegs[i].wc;
+        if (!p->in0[wc] || !p->out[wc] || (sg.op != MONT_OP_REDC && !p->in1[wc]))
+            return fail(MONT_E_INVAL, "segment %zu: pool for width class %u is NULL", i, wc);
+    }
+    for (int wc = 0; wc < 3; ++wc) {
+        const uintptr_t a = (uintptr_t)p->in0[wc] | (uintptr_t)p->in1[wc] | (uintptr_t)p->out[wc];
+        if (a & 15u)
+            return fail(MONT_E_INVAL, "pool pointers must be 16-byte aligned");
+    }
+    return MONT_OK;
+}
+
+void *ragged_kernel_ptr() { return (void *)k_ragged; }
+
+hipError_t launch_ragged(const DSeg *segs, const DTile *tiles, uint32_t ntiles, const DPools &P, uint32_t *ctr,
+                         uint32_t dyn, uint32_t grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ragged, dim3(grid), dim3(BLOCK), 0, s, segs, tiles, ntiles, P, ctr, dyn);
+    return hipGetLastError();
+}
+
+static mont_status_t launch_direct(mont_batch &b, const DPools &P, hipStream_t s, uint32_t dyn)
+{
+    const hipError_t e = launch_ragged(b.dsegs, b.dtiles, b.ntiles, P, b.dctr, dyn, b.grid, s);
+    return e == hipSuccess ? MONT_OK : hip_fail(e, "ragged launch");
+}
+
+static mont_status_t launch_graph(mont_batch &b, const DPools &P, hipStream_t s, uint32_t dyn)
+{
+    DPools Pc = P;
+    DSeg *segs = b.dsegs;
+    DTile *tiles = b.dtiles;
+    uint32_t nt = b.ntiles;
+    uint32_t *ctr = b.dctr;
+    void *args[] = {&segs, &tiles, &nt, &Pc, &ctr, &dyn};
+    hipKernelNodeParams kp{};
+    kp.func = ragged_kernel_ptr();
+    kp.gridDim = dim3(b.grid);
+    kp.blockDim = dim3(BLOCK);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipError_t e;
+    if (!b.exec) {
+        e = hipGraphCreate(&b.graph, 0);
+        if (e == hipSuccess)
+            e = hipGraphAddKernelNode(&b.node, b.graph, nullptr, 0, &kp);
+        if (e == hipSuccess)
+            e = hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0);
+        if (e != hipSuccess)
+            return hip_fail(e, "ragged graph build");
+    } else if (std::memcmp(&b.last, &P, sizeof P) != 0 || b.last_grid != b.grid || b.last_dyn != dyn) {
+        e = hipGraphExecKernelNodeSetParams(b.exec, b.node, &kp);
+        if (e != hipSuccess)
+            return hip_fail(e, "ragged graph update");
+    }
+    b.last = P;
+    b.last_grid = b.grid;
+    b.last_dyn = dyn;
+    e = hipGraphLaunch(b.exec, s);
+    return e == hipSuccess ? MONT_OK : hip_fail(e, "ragged graph launch");
+}
+
+static mont_status_t run_once(mont_batch &b, const DPools &P, hipStream_t s)
+{
+    if (b.ntiles == 0)
+        return MONT_OK;
+    const uint32_t dyn = (b.flags & MONT_BATCH_DYNAMIC) ? 1u : 0u;
+    return (b.flags & MONT_BATCH_GRAPH) ? launch_graph(b, P, s, dyn) : launch_direct(b, P, s, dyn);
+}
+
+// Tuning: tile size x workgroups per CU x schedule, timed with HIP events.
+struct RaggedTune {
+    uint32_t tile_base, blocks_per_cu, dynamic;
+};
+static std::mutex g_rt_mu;
+static std::unordered_map<std::string, RaggedTune> g_rt_cache;
+
+static std::string tune_key(const mont_batch &b)
+{
+    uint64_t ops[3] = {0, 0, 0};
+    for (const auto &sg : b.segs)
+        ops[sg.op] += sg.n;
+    char k[160];
+    int lg = 0;
+    while ((b.elements >> lg) > 1)
+        ++lg;
+    snprintf(k, sizeof k, "ragged:nseg=%zu:log2n=%d:mul=%d:redc=%d:pow=%d", b.segs.size() >= 1024 ? 1024 : b.segs.size(),
+             lg, ops[0] > 0, ops[1] > 0, ops[2] > 0);
+    return k;
+}
+
+static mont_status_t tune(mont_batch &b, const DPools &P, hipStream_t s)
+{
+    const std::string key = tune_key(b);
+    {
+        std::lock_guard<std::mutex> g(g_rt_mu);
+        auto it = g_rt_cache.find(key);
+        if (it != g_rt_cache.end()) {
+            b.tile_base = it->second.tile_base;
+            b.blocks_per_cu = it->second.blocks_per_cu;
+            b.flags = (b.flags & ~MONT_BATCH_DYNAMIC) | (it->second.dynamic ? MONT_BATCH_DYNAMIC : 0u);
+            return build_tiles(b, s);
+        }
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(MONT_E_DEVICE, "event create");
+    const uint32_t tiles[] = {4096, 8192, 16384, 32768};
+    const uint32_t bpcs[] = {4, 8, 16};
+    float best = 1e30f;
+    RaggedTune bt{b.tile_base, b.blocks_per_cu, (b.flags & MONT_BATCH_DYNAMIC) ? 1u : 0u};
+    const uint32_t saved_flags = b.flags;
+    b.flags &= ~MONT_BATCH_GRAPH;  // time direct launches
+    mont_status_t rc = MONT_OK;
+    for (uint32_t tb : tiles) {
+        b.tile_base = tb;
+        b.pow_tile = 1024;
+        for (uint32_t bpc : bpcs) {
+            b.blocks_per_cu = bpc;
+            if ((rc = build_tiles(b, s)))
+                goto done;
+            for (uint32_t dyn = 0; dyn < 2; ++dyn) {
+                b.flags = (b.flags & ~MONT_BATCH_DYNAMIC) | (dyn ? MONT_BATCH_DYNAMIC : 0u);
+                if ((rc = run_once(b, P, s)))  // warm
+                    goto done;
+                (void)hipEventRecord(e0, s);
+                for (int r = 0; r < 3; ++r)
+                    if ((rc = run_once(b, P, s)))
+                        goto done;
+                (void)hipEventRecord(e1, s);
+                if (hipEventSynchronize(e1) != hipSuccess) {
+                    rc = fail(MONT_E_DEVICE, "tuning run failed");
+                    goto done;
+                }
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best) {
+                    best = ms;
+                    bt = {tb, bpc, dyn};
+                }
+            }
+        }
+    }
+done:
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b.flags = (saved_flags & ~MONT_BATCH_DYNAMIC) | (bt.dynamic ? MONT_BATCH_DYNAMIC : 0u);
+    if (rc)
+        return rc;
+    b.tile_base = bt.tile_base;
+    b.blocks_per_cu = bt.blocks_per_cu;
+    {
+        std::lock_guard<std::mutex> g(g_rt_mu);
+        g_rt_cache[key] = bt;
+    }
+    return build_tiles(b, s);
+}
+
+}  // namespace mont
+
+extern "C" {
+
+mont_status_t mont_batch_create(const mont_ctx_t *ctxs, uint32_t nctx, const mont_seg_t *segs, uint32_t nseg,
+                                uint32_t flags, mont_batch_t **out, void *stream)
+{
+    if (!out)
+        return fail(MONT_E_INVAL, "null output handle");
+    *out = nullptr;
+    if ((nctx && !ctxs) || (nseg && !segs))
+        return fail(MONT_E_INVAL, "null table");
+    for (uint32_t i = 0; i < nctx; ++i) {
+        mont_status_t rc = check_ctx(&ctxs[i]);
+        if (rc)
+            return fail(rc, "context %u: %s", i, mont_last_error());
+    }
+    mont_batch *b = new (std::nothrow) mont_batch;
+    if (!b)
+        return fail(MONT_E_NOMEM, "batch");
+    b->ctxs.assign(ctxs, ctxs + nctx);
+    b->segs.assign(segs, segs + nseg);
+    b->flags = flags;
+    b->hsegs.resize(nseg);
+    for (uint32_t i = 0; i < nseg; ++i) {
+        const mont_seg_t &sg = segs[i];
+        mont_status_t rc = MONT_OK;
+        if (sg.ctx >= nctx)
+            rc = fail(MONT_E_INVAL, "segment %u: context index %u out of range", i, sg.ctx);
+        else if (sg.op > MONT_OP_POW)
+            rc = fail(MONT_E_INVAL, "segment %u: unknown op %u", i, (unsigned)sg.op);
+        else if (sg.op == MONT_OP_POW && sg.variant != MONT_CLASSIC)
+            rc = fail(MONT_E_UNSUPPORTED, "segment %u: exponentiation uses the classic variant", i);
+        else if (sg.n >= (1ull << 40) || sg.off >= (1ull << 48) || sg.off1 >= (1ull << 48))
+            rc = fail(MONT_E_INVAL, "segment %u: size or offset too large", i);
+        else if (sg.op == MONT_OP_MUL && ((sg.off1 - sg.off) & (uint64_t)(128 / ctxs[sg.ctx].w - 1)) != 0)
+            rc = fail(MONT_E_INVAL, "segment %u: off1 - off must be a multiple of %u", i, 128 / ctxs[sg.ctx].w);
+        else {
+            rc = check_variant(&ctxs[sg.ctx], sg.variant);
+            if (rc)
+                rc = fail(rc, "segment %u: %s", i, mont_last_error());
+        }
+        if (rc) {
+            delete b;
+            return rc;
+        }
+        DSeg &d = b->hsegs[i];
+        std::memset(&d, 0, sizeof d);
+        d.c = to_kctx(ctxs[sg.ctx]);
+        d.off = sg.off;
+        d.off1 = sg.off1;
+        d.op = sg.op;
+        d.variant = sg.variant;
+        d.wc = (uint32_t)width_class(ctxs[sg.ctx].w);
+        b->elements += sg.n;
+        b->op_mask |= 1u << sg.op;
+    }
+    (void)hipGetDevice(&b->dev);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMalloc(&b->dsegs, std::max<size_t>(nseg, 1) * sizeof(DSeg));
+    if (e == hipSuccess)
+        e = hipMalloc(&b->dctr, 64);
+    if (e != hipSuccess) {
+        mont_batch_destroy(b);
+        return fail(MONT_E_NOMEM, "batch tables");
+    }
+    if (nseg)
+        e = hipMemcpyAsync(b->dsegs, b->hsegs.data(), nseg * sizeof(DSeg), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(b->dctr, 0, 64, s);
+    if (e != hipSuccess) {
+        mont_batch_destroy(b);
+        return hip_fail(e, "batch upload");
+    }
+    mont_status_t rc = build_tiles(*b, s);
+    if (rc) {
+        mont_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return MONT_OK;
+}
+
+mont_status_t mont_batch_run(mont_batch_t *b, const mont_pools_t *pools, void *stream)
+{
+    if (!b)
+        return fail(MONT_E_INVAL, "null batch");
+    mont_status_t rc = check_pools(*b, pools);
+    if (rc)
+        return rc;
+    const DPools P = to_dpools(*pools);
+    hipStream_t s = (hipStream_t)stream;
+    if ((b->flags & MONT_BATCH_TUNE) && !b->tuned) {
+        rc = tune(*b, P, s);
+        if (rc)
+            return rc;
+        b->tuned = true;
+    }
+    return run_once(*b, P, s);
+}
+
+static mont_status_t run_only(mont_batch_t *b, const mont_pools_t *pools, void *stream, uint32_t op)
+{
+    if (!b)
+        return fail(MONT_E_INVAL, "null batch");
+    if (b->op_mask & ~(1u << op))
+        return fail(MONT_E_INVAL, "batch holds segments of another operation");
+    return mont_batch_run(b, pools, stream);
+}
+
+mont_status_t mont_mul_ragged(mont_batch_t *b, const mont_pools_t *p, void *s) { return run_only(b, p, s, MONT_OP_MUL); }
+mont_status_t mont_redc_ragged(mont_batch_t *b, const mont_pools_t *p, void *s) { return run_only(b, p, s, MONT_OP_REDC); }
+mont_status_t mont_pow_ragged(mont_batch_t *b, const mont_pools_t *p, void *s) { return run_only(b, p, s, MONT_OP_POW); }
+
+mont_status_t mont_batch_run_pervector(mont_batch_t *b, const mont_pools_t *pools, void *stream)
+{
+    if (!b)
+        return fail(MONT_E_INVAL, "null batch");
+    mont_status_t rc = check_pools(*b, pools);
+    if (rc)
+        return rc;
+    static const size_t esz[3] = {2, 4, 8};
+    for (size_t i = 0; i < b->segs.size(); ++i) {
+        const mont_seg_t &sg = b->segs[i];
+        if (!sg.n)
+            continue;
+        const mont_ctx_t *c = &b->ctxs[sg.ctx];
+        const uint32_t wc = b->hsegs[i].wc;
+        const size_t es = esz[wc];
+        const char *i0 = (const char *)pools->in0[wc];
+        const char *i1 = (const char *)pools->in1[wc];
+        char *o = (char *)pools->out[wc];
+        if (sg.op == MONT_OP_MUL)
+            rc = mont_mul(c, i0 + sg.off * es, i1 + sg.off1 * es, o + sg.off * es, sg.n,
+                          (mont_variant_t)sg.variant, stream);
+        else if (sg.op == MONT_OP_REDC)
+            rc = mont_redc(c, i0 + sg.off * 2 * es, o + sg.off * es, sg.n, (mont_variant_t)sg.variant, stream);
+        else
+            rc = mont_pow(c, i0 + sg.off * es, (const uint64_t *)i1 + sg.off1, o + sg.off * es, sg.n, stream);
+        if (rc)
+            return rc;
+    }
+    return MONT_OK;
+}
+
+mont_status_t mont_batch_info(const mont_batch_t *b, mont_batch_info_t *info)
+{
+    if (!b || !info)
+        return fail(MONT_E_INVAL, "null argument");
+    info->ntiles = b->ntiles;
+    info->elements = b->elements;
+    info->tile_elems = b->tile_base;
+    info->grid = b->grid;
+    info->block = BLOCK;
+    info->flags = b->flags;
+    return MONT_OK;
+}
+
+void mont_batch_destroy(mont_batch_t *b)
+{
+    if (!b)
+        return;
+    if (b->exec)
+        (void)hipGraphExecDestroy(b->exec);
+    if (b->graph)
+        (void)hipGraphDestroy(b->graph);
+    if (b->dsegs)
+        (void)hipFree(b->dsegs);
+    if (b->dtiles)
+        (void)hipFree(b->dtiles);
+    if (b->dctr)
+        (void)hipFree(b->dctr);
+    delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,38 @@
+// Descriptors of the persistent ragged-batch kernel, shared by the batch API
+// and the serving loop.
+#pragma once
+
+#include "mont_kernels.hpp"
+
+namespace mont {
+
+struct DSeg {
+    KCtx c;          // 64 B
+    uint64_t off;    // element offset of in0 / out in the pools of its width
+    uint64_t off1;   // element offset of in1 (b as w-bit elements; exponents as uint64)
+    uint32_t op;
+    uint32_t variant;
+    uint32_t wc;     // width class 0/1/2 = 16/32/64 bits
+    uint32_t pad;
+};
+static_assert(sizeof(DSeg) == 96, "segment descriptor layout");
+
+struct DTile {
+    uint32_t seg;
+    uint32_t cnt;
+    uint64_t start;  // element index inside the segment
+};
+
+struct DPools {
+    const void *in0[3];
+    const void *in1[3];
+    void *out[3];
+};
+
+// One persistent launch over `ntiles` tiles (ctr: two zeroed uint32 that the
+// kernel leaves zeroed again when dyn = 1).
+hipError_t launch_ragged(const DSeg *segs, const DTile *tiles, uint32_t ntiles, const DPools &P, uint32_t *ctr,
+                         uint32_t dyn, uint32_t grid, hipStream_t s);
+void *ragged_kernel_ptr();
+
+}  // namespace mont

@@ -1,0 +1,492 @@
+// Serving loop: the scheduler core (mont_sched.hpp) driven by a service
+// thread, with a GPU backend that runs each batch as one persistent ragged
+// launch on its own HIP stream.
+//
+// Device layout per word-size class c (32-bit, 64-bit residues), for an
+// arena of cap element slots:
+//   in0[c]  cap * es bytes   first operand a / base x
+//   in1[c]  cap * 8 bytes    second operand b (es bytes at slot*8) or the
+//                            exponent (8 bytes at slot*8)
+//   out[c]  cap * es bytes   result
+// so one slot index addresses all three, and a job's slots never alias
+// another job's.  Each stream slot owns pinned host staging for its
+// segment/tile tables, device copies of them, a self-resetting tile counter
+// and a completion event; a slot is reused only after its event fired.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "mont_common.hpp"
+#include "mont_ragged.hpp"
+#include "mont_sched.hpp"
+
+namespace mont {
+
+static double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct ServeSlot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    DSeg *hsegs = nullptr, *dsegs = nullptr;
+    DTile *htiles = nullptr, *dtiles = nullptr;
+    uint32_t *dctr = nullptr;
+    size_t seg_cap = 0, tile_cap = 0;
+};
+
+class GpuBackend : public mont_sched::Backend {
+  public:
+    int dev = 0;
+    uint64_t cap[2] = {0, 0};
+    void *in0[2] = {nullptr, nullptr}, *in1[2] = {nullptr, nullptr}, *out[2] = {nullptr, nullptr};
+    std::vector<ServeSlot> slot;
+    uint32_t tile_base = 8192, pow_tile = 1024, grid_max = 0;
+    std::unordered_map<uint64_t, mont_ctx_t> ctx_cache[2];
+    std::vector<DTile> tiles;  // scratch for building a batch's tile table
+
+    mont_status_t init(const mont_server_cfg_t &c, uint32_t nslots, uint64_t budget)
+    {
+        (void)hipGetDevice(&dev);
+        // bytes per slot: 32-bit class 4 + 8 + 4, 64-bit class 8 + 8 + 8
+        cap[0] = (budget / 2) / 16 / mont_sched::ALIGN * mont_sched::ALIGN;
+        cap[1] = (budget / 2) / 24 / mont_sched::ALIGN * mont_sched::ALIGN;
+        const size_t es[2] = {4, 8};
+        for (int k = 0; k < 2; ++k) {
+            if (hipMalloc(&in0[k], cap[k] * es[k]) != hipSuccess || hipMalloc(&in1[k], cap[k] * 8) != hipSuccess ||
+                hipMalloc(&out[k], cap[k] * es[k]) != hipSuccess)
+                return fail(MONT_E_NOMEM, "serving arena of %llu bytes", (unsigned long long)budget);
+        }
+        if (c.tile_elems)
+            tile_base = c.tile_elems;
+        grid_max = (uint32_t)device_cus() * 8;
+        slot.resize(nslots);
+        const size_t max_jobs = c.max_batch_jobs;
+        for (ServeSlot &s : slot) {
+            hipError_t e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
+            if (e == hipSuccess)
+                e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+            if (e == hipSuccess)
+                e = hipMalloc(&s.dctr, 64);
+            if (e == hipSuccess)
+                e = hipMemset(s.dctr, 0, 64);
+            if (e != hipSuccess)
+                return hip_fail(e, "serving slot");
+            mont_status_t rc = reserve(s, max_jobs, max_jobs * 64);
+            if (rc)
+                return rc;
+        }
+        return MONT_OK;
+    }
+
+    mont_status_t reserve(ServeSlot &s, size_t nseg, size_t ntile)
+    {
+        if (nseg > s.seg_cap) {
+            if (s.hsegs)
+                (void)hipHostFree(s.hsegs);
+            if (s.dsegs)
+                (void)hipFree(s.dsegs);
+            s.hsegs = nullptr;
+            s.dsegs = nullptr;
+            if (hipHostMalloc((void **)&s.hsegs, nseg * sizeof(DSeg), hipHostMallocDefault) != hipSuccess ||
+                hipMalloc(&s.dsegs, nseg * sizeof(DSeg)) != hipSuccess)
+                return fail(MONT_E_NOMEM, "segment tables");
+            s.seg_cap = nseg;
+        }
+        if (ntile > s.tile_cap) {
+            if (s.htiles)
+                (void)hipHostFree(s.htiles);
+            if (s.dtiles)
+                (void)hipFree(s.dtiles);
+            s.htiles = nullptr;
+            s.dtiles = nullptr;
+            if (hipHostMalloc((void **)&s.htiles, ntile * sizeof(DTile), hipHostMallocDefault) != hipSuccess ||
+                hipMalloc(&s.dtiles, ntile * sizeof(DTile)) != hipSuccess)
+                return fail(MONT_E_NOMEM, "tile tables");
+            s.tile_cap = ntile;
+        }
+        return MONT_OK;
+    }
+
+    ~GpuBackend() override
+    {
+        for (ServeSlot &s : slot) {
+            if (s.stream)
+                (void)hipStreamSynchronize(s.stream);
+            if (s.done)
+                (void)hipEventDestroy(s.done);
+            if (s.stream)
+                (void)hipStreamDestroy(s.stream);
+            if (s.hsegs)
+                (void)hipHostFree(s.hsegs);
+            if (s.htiles)
+                (void)hipHostFree(s.htiles);
+            if (s.dsegs)
+                (void)hipFree(s.dsegs);
+            if (s.dtiles)
+                (void)hipFree(s.dtiles);
+            if (s.dctr)
+                (void)hipFree(s.dctr);
+        }
+        for (int k = 0; k < 2; ++k) {
+            if (in0[k])
+                (void)hipFree(in0[k]);
+            if (in1[k])
+                (void)hipFree(in1[k]);
+            if (out[k])
+                (void)hipFree(out[k]);
+        }
+    }
+
+    int slots() const override { return (int)slot.size(); }
+    double now() override { return now_s(); }
+
+    const mont_ctx_t *ctx_of(uint64_t N, uint32_t w)
+    {
+        auto &m = ctx_cache[w == 64 ? 1 : 0];
+        auto it = m.find(N);
+        if (it != m.end())
+            return &it->second;
+        mont_ctx_t c;
+        if (setup_ctx(N, w, &c) != MONT_OK)
+            return nullptr;
+        return &m.emplace(N, c).first->second;
+    }
+
+    int launch(int si, const std::vector<mont_sched::Job *> &jobs) override
+    {
+        ServeSlot &s = slot[si];
+        tiles.clear();
+        for (uint32_t i = 0; i < jobs.size(); ++i) {
+            const mont_sched::Job &j = *jobs[i];
+            const uint64_t te = j.op == mont_sched::OP_POW ? pow_tile : (j.cls == 0 ? tile_base : tile_base / 2);
+            for (uint64_t st = 0; st < j.n; st += te)
+                tiles.push_back({i, (uint32_t)std::min<uint64_t>(te, j.n - st), st});
+        }
+        if (reserve(s, jobs.size(), tiles.size()))
+            return -1;
+        const size_t es[2] = {4, 8};
+        for (uint32_t i = 0; i < jobs.size(); ++i) {
+            const mont_sched::Job &j = *jobs[i];
+            const mont_ctx_t *c = ctx_of(j.N, j.w);
+            if (!c)
+                return -1;
+            DSeg &d = s.hsegs[i];
+            std::memset(&d, 0, sizeof d);
+            d.c = to_kctx(*c);
+            d.off = j.off;
+            // in1 slot = 8 bytes: exponents index uint64 at off, products index w-bit b at off * 8 / es
+            d.off1 = j.op == mont_sched::OP_POW ? j.off : j.off * (8 / es[j.cls]);
+            d.op = j.op == mont_sched::OP_POW ? MONT_OP_POW : MONT_OP_MUL;
+            d.variant = CLASSIC;
+            d.wc = j.cls == 0 ? 1 : 2;
+        }
+        std::memcpy(s.htiles, tiles.data(), tiles.size() * sizeof(DTile));
+        hipError_t e = hipSuccess;
+        for (const mont_sched::Job *jp : jobs) {
+            const mont_sched::Job &j = *jp;
+            const size_t b = es[j.cls];
+            char *a0 = (char *)in0[j.cls] + j.off * b;
+            char *a1 = (char *)in1[j.cls] + j.off * 8;
+            const size_t n1 = j.op == mont_sched::OP_POW ? 8 * j.n : b * j.n;
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(a0, j.in0, b * j.n, hipMemcpyHostToDevice, s.stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(a1, j.in1, n1, hipMemcpyHostToDevice, s.stream);
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s.dsegs, s.hsegs, jobs.size() * sizeof(DSeg), hipMemcpyHostToDevice, s.stream);
+        if (e == hipSuccess && !tiles.empty())
+            e = hipMemcpyAsync(s.dtiles, s.htiles, tiles.size() * sizeof(DTile), hipMemcpyHostToDevice, s.stream);
+        if (e == hipSuccess && !tiles.empty()) {
+            DPools P{};
+            P.in0[1] = in0[0];
+            P.in1[1] = in1[0];
+            P.out[1] = out[0];
+            P.in0[2] = in0[1];
+            P.in1[2] = in1[1];
+            P.out[2] = out[1];
+            const uint32_t grid = (uint32_t)std::max<size_t>(1, std::min<size_t>(tiles.size(), grid_max));
+            e = launch_ragged(s.dsegs, s.dtiles, (uint32_t)tiles.size(), P, s.dctr, 1u, grid, s.stream);
+        }
+        for (const mont_sched::Job *jp : jobs) {
+            const mont_sched::Job &j = *jp;
+            const size_t b = es[j.cls];
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(j.out, (char *)out[j.cls] + j.off * b, b * j.n, hipMemcpyDeviceToHost, s.stream);
+        }
+        if (e == hipSuccess)
+            e = hipEventRecord(s.done, s.stream);
+        if (e != hipSuccess) {
+            hip_fail(e, "serving batch");
+            return -1;
+        }
+        return 0;
+    }
+
+    int poll(int si) override
+    {
+        const hipError_t e = hipEventQuery(slot[si].done);
+        if (e == hipSuccess)
+            return 1;
+        if (e == hipErrorNotReady)
+            return 0;
+        return -1;
+    }
+};
+
+}  // namespace mont
+
+using namespace mont;
+
+struct mont_server {
+    GpuBackend *be = nullptr;
+    mont_sched::Scheduler *sched = nullptr;
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::vector<mont_sched::Job> inbox;
+    std::deque<mont_sched::Completion> outbox;
+    bool stop = false;
+    uint64_t accepted = 0, finished = 0, rejected = 0;
+    mont_sched::Stats last{};
+    uint64_t cap[2] = {0, 0};
+    int dev = 0;
+};
+
+static void service(mont_server *S)
+{
+    (void)hipSetDevice(S->dev);
+    std::vector<mont_sched::Job> local;
+    std::vector<mont_sched::Completion> comp(1024);
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            if (S->inbox.empty() && S->sched->idle() && S->sched->pending_completions() == 0) {
+                if (S->stop)
+                    break;
+                S->cv_work.wait(lk, [S] { return S->stop || !S->inbox.empty(); });
+            }
+            local.swap(S->inbox);
+        }
+        for (auto &j : local)
+            S->sched->submit(j);
+        local.clear();
+        const bool did = S->sched->step();
+        size_t k;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            while ((k = S->sched->take(comp.data(), comp.size())) > 0) {
+                S->outbox.insert(S->outbox.end(), comp.begin(), comp.begin() + k);
+                S->finished += k;
+            }
+            S->last = S->sched->stats();
+        }
+        S->cv_done.notify_all();
+        if (!did && S->sched->device_busy())
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
+
+static bool job_ok(const mont_server *S, const mont_job_t *j, mont_status_t *rc)
+{
+    if (!j || (j->w != 32 && j->w != 64) || (j->op != MONT_OP_MUL && j->op != MONT_OP_POW) || j->N < 3 ||
+        !(j->N & 1u) || (j->w == 32 && (j->N >> 32)) || (j->n && (!j->in0 || !j->in1 || !j->out))) {
+        *rc = fail(MONT_E_INVAL, "malformed job");
+        return false;
+    }
+    if (mont_sched::Arena::span(j->n) > S->cap[j->w == 64 ? 1 : 0]) {
+        *rc = fail(MONT_E_DOMAIN, "job of %llu elements exceeds the device budget", (unsigned long long)j->n);
+        return false;
+    }
+    return true;
+}
+
+static mont_sched::Job to_job(const mont_job_t *j, double t)
+{
+    mont_sched::Job x;
+    x.id = j->id;
+    x.N = j->N;
+    x.w = j->w;
+    x.op = j->op == MONT_OP_POW ? mont_sched::OP_POW : mont_sched::OP_MUL;
+    x.n = j->n;
+    x.in0 = j->in0;
+    x.in1 = j->in1;
+    x.out = j->out;
+    x.t_submit = t;
+    return x;
+}
+
+extern "C" {
+
+double mont_serve_now(void) { return now_s(); }
+
+mont_status_t mont_serve_create(const mont_server_cfg_t *cfg, mont_server_t **out)
+{
+    if (!out)
+        return fail(MONT_E_INVAL, "null handle");
+    *out = nullptr;
+    mont_server_cfg_t c{};
+    if (cfg)
+        c = *cfg;
+    if (!c.hbm_budget_bytes)
+        c.hbm_budget_bytes = 8ull << 30;
+    if (!c.max_jobs_in_flight)
+        c.max_jobs_in_flight = 4096;
+    if (!c.streams)
+        c.streams = 3;
+    if (!c.max_batch_jobs)
+        c.max_batch_jobs = 512;
+    if (c.streams > 16 || c.tile_elems % 256 || c.tile_elems > (1u << 20))
+        return fail(MONT_E_INVAL, "streams <= 16 and tile_elems a multiple of 256 up to 2^20");
+    mont_server *S = new (std::nothrow) mont_server;
+    if (!S)
+        return fail(MONT_E_NOMEM, "server");
+    S->be = new (std::nothrow) GpuBackend;
+    mont_status_t rc = S->be ? S->be->init(c, c.streams, c.hbm_budget_bytes) : MONT_E_NOMEM;
+    if (rc) {
+        delete S->be;
+        delete S;
+        return rc;
+    }
+    S->dev = S->be->dev;
+    S->cap[0] = S->be->cap[0];
+    S->cap[1] = S->be->cap[1];
+    mont_sched::Config sc;
+    sc.cap[0] = S->cap[0];
+    sc.cap[1] = S->cap[1];
+    sc.max_in_flight = c.max_jobs_in_flight;
+    sc.max_batch_jobs = c.max_batch_jobs;
+    S->sched = new mont_sched::Scheduler(sc, S->be);
+    S->th = std::thread(service, S);
+    *out = S;
+    return MONT_OK;
+}
+
+mont_status_t mont_serve_submit(mont_server_t *S, const mont_job_t *job)
+{
+    if (!S)
+        return fail(MONT_E_INVAL, "null server");
+    mont_status_t rc;
+    if (!job_ok(S, job, &rc)) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        ++S->rejected;
+        return rc;
+    }
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->inbox.push_back(to_job(job, now_s()));
+        ++S->accepted;
+    }
+    S->cv_work.notify_one();
+    return MONT_OK;
+}
+
+int64_t mont_serve_submit_timed(mont_server_t *S, const mont_job_t *jobs, const double *arrival_s, uint64_t n)
+{
+    if (!S || (n && (!jobs || !arrival_s)))
+        return fail(MONT_E_INVAL, "null argument");
+    const double t0 = now_s();
+    int64_t ok = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        const double due = t0 + arrival_s[i];
+        for (;;) {
+            const double left = due - now_s();
+            if (left <= 0)
+                break;
+            if (left > 200e-6)
+                std::this_thread::sleep_for(std::chrono::duration<double>(left - 150e-6));
+            else
+                std::this_thread::yield();
+        }
+        if (mont_serve_submit(S, &jobs[i]) == MONT_OK)
+            ++ok;
+    }
+    return ok;
+}
+
+int64_t mont_serve_poll(mont_server_t *S, mont_completion_t *out, uint32_t max, int32_t wait_ms)
+{
+    if (!S || (max && !out))
+        return fail(MONT_E_INVAL, "null argument");
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (S->outbox.empty() && wait_ms > 0)
+        S->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), [S] { return !S->outbox.empty(); });
+    uint32_t k = 0;
+    while (k < max && !S->outbox.empty()) {
+        const mont_sched::Completion &c = S->outbox.front();
+        out[k].id = c.id;
+        out[k].status = c.status;
+        out[k].reserved = 0;
+        out[k].t_submit = c.t_submit;
+        out[k].t_admit = c.t_admit;
+        out[k].t_launch = c.t_launch;
+        out[k].t_done = c.t_done;
+        S->outbox.pop_front();
+        ++k;
+    }
+    return k;
+}
+
+mont_status_t mont_serve_drain(mont_server_t *S, int32_t timeout_ms)
+{
+    if (!S)
+        return fail(MONT_E_INVAL, "null server");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto done = [S] { return S->finished >= S->accepted; };
+    if (timeout_ms < 0) {
+        S->cv_done.wait(lk, done);
+        return MONT_OK;
+    }
+    return S->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), done)
+               ? MONT_OK
+               : fail(MONT_E_BUSY, "jobs still in flight");
+}
+
+mont_status_t mont_serve_stats(const mont_server_t *S, mont_server_stats_t *st)
+{
+    if (!S || !st)
+        return fail(MONT_E_INVAL, "null argument");
+    mont_server *M = const_cast<mont_server *>(S);
+    std::lock_guard<std::mutex> lk(M->mu);
+    const mont_sched::Stats &x = M->last;
+    st->submitted = M->accepted + M->rejected;
+    st->completed = x.completed;
+    st->rejected = M->rejected;
+    st->launches = x.launches;
+    st->jobs_launched = x.jobs_launched;
+    st->queued = x.queued + M->inbox.size();
+    st->staged = x.staged;
+    st->in_flight = x.in_flight;
+    st->bytes_in_use = x.used_slots[0] * 16 + x.used_slots[1] * 24;
+    st->peak_bytes_in_use = x.peak_slots[0] * 16 + x.peak_slots[1] * 24;
+    return MONT_OK;
+}
+
+void mont_serve_destroy(mont_server_t *S)
+{
+    if (!S)
+        return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv_work.notify_all();
+    if (S->th.joinable())
+        S->th.join();
+    delete S->sched;
+    delete S->be;
+    delete S;
+}
+
+}  // extern "C"
