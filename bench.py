@@ -42,7 +42,11 @@ def parse():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--quick", action="store_true", help="headline only (no secondary measurements)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--sections", default=None,
+                   help="comma list of secondary measurements to run (default: all unless --quick): "
+                        "copy,r32,r16,pow,ragged,serving")
     p.add_argument("--ragged-segments", type=int, default=4096)
+    p.add_argument("--serve-jobs", type=int, default=100_000)
     return p.parse_args()
 
 
@@ -157,9 +161,11 @@ def main():
     del a, b, out
     torch.cuda.empty_cache()
 
-    extra = {}
-    if not args.quick:
-        extra = secondary(torch, mg, inp, args)
+    if args.sections is not None:
+        sections = [x for x in args.sections.split(",") if x]
+    else:
+        sections = [] if args.quick else list(SECTIONS)
+    extra = secondary(torch, mg, inp, args, sections) if sections else {}
 
     line = {
         "metric": "Gmodmul/s & % HBM peak (64-bit REDC mul); ragged-batch vs per-call speedup",
@@ -184,74 +190,118 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def secondary(torch, mg, inp, args):
-    dev = torch.device("cuda:0")
-    ex = {}
+def copy_ceiling(torch):
+    """Plain streams of known size over 2 GiB arrays: torch's device copy (the
+    counter-scaling reference) and the library's 2-read/1-write reference
+    kernel (the product kernels' access pattern with no arithmetic)."""
+    import paper_2402_00675_amd as mg
 
-    # practical HBM ceiling: a plain device-to-device copy of 2 x 2 GiB
-    src = torch.empty(1 << 28, dtype=torch.int64, device=dev)
+    src = torch.empty(1 << 28, dtype=torch.int64, device="cuda:0")
     dst = torch.empty_like(src)
     _, ms = timed(lambda: dst.copy_(src), torch, 10, 3)
-    ex["copy_ceiling_GBs"] = round(2 * src.numel() * 8 / (ms * 1e-3) / 1e9, 1)
-    log("copy ceiling: %.0f GB/s" % ex["copy_ceiling_GBs"])
-    del src, dst
+    copy = round(2 * src.numel() * 8 / (ms * 1e-3) / 1e9, 1)
+    src2 = torch.empty_like(src)
+    _, ms = timed(lambda: mg.stream_ref(src, src2, dst), torch, 10, 3)
+    ref = round(3 * src.numel() * 8 / (ms * 1e-3) / 1e9, 1)
+    log("copy: %.0f GB/s, 2-read/1-write reference: %.0f GB/s" % (copy, ref))
+    return {"torch_copy_GBs": copy, "ref_2r1w_GBs": ref}
 
-    # 32-bit workload: N = 8380417, 2^26 residues, four variants
-    w2 = inp.R32Workload()
-    c32 = mg.setup(w2.N, 32)
-    r32 = {}
-    for signed in (False, True):
-        ah, bh = w2.operands(signed)
+
+SECTIONS = ("copy", "r32", "r16", "pow", "ragged", "serving")
+
+
+def secondary(torch, mg, inp, args, sections):
+    dev = torch.device("cuda:0")
+    ex = {}
+    if "copy" in sections:
+        ex["hbm_ceiling"] = copy_ceiling(torch)
+
+    if "r32" in sections:
+        # 32-bit workload: N = 8380417, 2^26 residues, the variants at R = 2^32 (Plantard family 2^64)
+        w2 = inp.R32Workload()
+        c32 = mg.setup(w2.N, 32)
+        r32 = {}
+        for signed in (False, True):
+            ah, bh = w2.operands(signed)
+            a = torch.from_numpy(ah).to(dev)
+            b = torch.from_numpy(bh).to(dev)
+            o = torch.empty_like(a)
+            for v in (["signed", "signed_plantard", "signed_plantard_alpha"] if signed else ["classic", "plantard"]):
+                _, ms = timed(lambda: mg.mul(c32, a, b, out=o, variant=v), torch, 20, 5)
+                gms = w2.n / (ms * 1e-3) / 1e9
+                r32[v] = {"Gmodmul_s": round(gms, 1), "GB_s": round(12 * gms, 1),
+                          "frac_hbm": round(12 * gms / HBM_PEAK_GBS, 4)}
+                log("r32 %s: %.1f Gmodmul/s" % (v, gms))
+            del a, b, o
+        ex["r32_mul"] = r32
+
+    if "r16" in sections:
+        # 16-bit workload: N = 3329, 2^20 residues + the exhaustive REDC sweep
+        w1 = inp.R16Workload()
+        c16 = mg.setup(w1.N, 16)
+        ah, bh = w1.operands()
         a = torch.from_numpy(ah).to(dev)
         b = torch.from_numpy(bh).to(dev)
         o = torch.empty_like(a)
-        for v in (["signed", "signed_plantard", "signed_plantard_alpha"] if signed else ["classic", "plantard"]):
-            _, ms = timed(lambda: mg.mul(c32, a, b, out=o, variant=v), torch, 20, 5)
-            gms = w2.n / (ms * 1e-3) / 1e9
-            r32[v] = {"Gmodmul_s": round(gms, 1), "GB_s": round(12 * gms, 1),
-                      "frac_hbm": round(12 * gms / HBM_PEAK_GBS, 4)}
-            log("r32 %s: %.1f Gmodmul/s" % (v, gms))
-        del a, b, o
-    ex["r32_mul"] = r32
+        _, ms = timed(lambda: mg.mul(c16, a, b, out=o), torch, 200, 20)
+        ex["r16_mul"] = {"us": round(ms * 1e3, 2), "Gmodmul_s": round(w1.n / (ms * 1e-3) / 1e9, 1)}
+        total = w1.N << 16
+        ro = torch.empty(total, dtype=torch.uint16, device=dev)
+        _, ms = timed(lambda: mg.redc_range(c16, 0, total, out=ro), torch, 10, 2)
+        ex["r16_exhaustive_redc"] = {"T": total, "us": round(ms * 1e3, 1),
+                                     "GB_s_written": round(2 * total / (ms * 1e-3) / 1e9, 1)}
+        log("r16: mul %s, exhaustive %s" % (ex["r16_mul"], ex["r16_exhaustive_redc"]))
+        del a, b, o, ro
 
-    # 16-bit workload: N = 3329, 2^20 residues + the exhaustive REDC sweep
-    w1 = inp.R16Workload()
-    c16 = mg.setup(w1.N, 16)
-    ah, bh = w1.operands()
-    a = torch.from_numpy(ah).to(dev)
-    b = torch.from_numpy(bh).to(dev)
-    o = torch.empty_like(a)
-    _, ms = timed(lambda: mg.mul(c16, a, b, out=o), torch, 200, 20)
-    ex["r16_mul"] = {"us": round(ms * 1e3, 2), "Gmodmul_s": round(w1.n / (ms * 1e-3) / 1e9, 1)}
-    total = w1.N << 16
-    ro = torch.empty(total, dtype=torch.uint16, device=dev)
-    _, ms = timed(lambda: mg.redc_range(c16, 0, total, out=ro), torch, 10, 2)
-    ex["r16_exhaustive_redc"] = {"T": total, "us": round(ms * 1e3, 1),
-                                 "GB_s_written": round(2 * total / (ms * 1e-3) / 1e9, 1)}
-    log("r16: mul %s, exhaustive %s" % (ex["r16_mul"], ex["r16_exhaustive_redc"]))
-    del a, b, o, ro
+    if "pow" in sections:
+        # exponentiation: 2^22 elements, 31- and 62-bit odd moduli, uniform 64-bit exponents
+        g = inp.rng(inp.W_SERVE, 7)
+        pw = {}
+        for bits, w in ((31, 32), (62, 64)):
+            N = inp.odd_modulus(g, bits)
+            n = 1 << 22
+            dt = np.uint32 if w == 32 else np.uint64
+            x = torch.from_numpy(inp.uniform_residues(g, N, n, dt)).to(dev)
+            e = torch.from_numpy(inp.u64_uniform(g, n)).to(dev)
+            o = torch.empty_like(x)
+            c = mg.setup(N, w)
+            _, ms = timed(lambda: mg.pow(c, x, e, out=o), torch, 5, 2)
+            rate = n / (ms * 1e-3) / 1e9
+            pw["w%d" % w] = {"Gpow_s": round(rate, 3), "ms": round(ms, 3),
+                             "Gmontmul_s": round(rate * 97, 1)}  # 3 + 31 windows x 3 + 1 products
+            log("pow w%d: %.3f Gpow/s" % (w, rate))
+        ex["pow"] = pw
 
-    # exponentiation: 2^22 elements, 31- and 62-bit odd moduli, uniform 64-bit exponents
-    g = inp.rng(inp.W_SERVE, 7)
-    pw = {}
-    for bits, w in ((31, 32), (62, 64)):
-        N = inp.odd_modulus(g, bits)
-        n = 1 << 22
-        dt = np.uint32 if w == 32 else np.uint64
-        x = torch.from_numpy(inp.uniform_residues(g, N, n, dt)).to(dev)
-        e = torch.from_numpy(inp.u64_uniform(g, n)).to(dev)
-        o = torch.empty_like(x)
-        c = mg.setup(N, w)
-        _, ms = timed(lambda: mg.pow(c, x, e, out=o), torch, 5, 2)
-        rate = n / (ms * 1e-3) / 1e9
-        pw["w%d" % w] = {"Gpow_s": round(rate, 3), "ms": round(ms, 3),
-                         "Gmontmul_s": round(rate * 97, 1)}  # 3 + 32 windows x 3 + 1 REDC products
-        log("pow w%d: %.3f Gpow/s" % (w, rate))
-    ex["pow"] = pw
-
-    # ragged batch
-    ex["ragged"] = ragged(torch, mg, inp, args.ragged_segments)
+    if "ragged" in sections:
+        ex["ragged"] = ragged(torch, mg, inp, args.ragged_segments)
+    if "serving" in sections and args.serve_jobs:
+        ex["serving"] = serving(torch, mg, args.serve_jobs)
     return ex
+
+
+def serving(torch, mg, njobs):
+    """Poisson stream of jobs through the continuous-batching loop."""
+    from paper_2402_00675_amd import serve
+
+    stream = serve.JobStream(torch, njobs)
+    nel = stream.elements()
+    log("serving: %d jobs, %d elements" % (njobs, nel))
+    srv = mg.Server(hbm_budget_bytes=8 << 30, streams=3, max_batch_jobs=512)
+    try:
+        sat = serve.summarize(serve.replay(srv, stream, np.zeros(njobs)), nel)
+        log("serving saturation: %s" % sat)
+        res = {"jobs": njobs, "elements": nel, "mix": "60% mul / 40% pow (uniform 64-bit e), lengths "
+               "log-uniform [2^8, 2^18], odd 31/62-bit moduli", "saturation": sat}
+        for f in (0.5, 0.8, 0.95):
+            rate = f * sat["jobs_per_s"]
+            r = serve.summarize(serve.replay(srv, stream, stream.gaps_unit / rate), nel)
+            r["offered_jobs_per_s"] = round(rate, 1)
+            res["load_%.2f" % f] = r
+            log("serving at %.2f x saturation: %s" % (f, r))
+        res["server"] = srv.stats()
+    finally:
+        srv.close()
+    return res
 
 
 def ragged(torch, mg, inp, nseg):
@@ -259,14 +309,14 @@ def ragged(torch, mg, inp, nseg):
     wl = inp.RaggedWorkload(nseg=nseg)
     lens, wide, mods = wl.segments()
     offs, (a32, b32), (a64, b64) = wl.operands(lens, wide, mods)
-    log("ragged: %d segments, %d elements (%d x u32, %d x u64)" % (nseg, int(lens.sum()), a32.size, a64.size))
+    log("ragged: %d segments, %d elements" % (nseg, int(lens.sum())))
     ctxs = [mg.setup(N, 64 if wd else 32) for N, wd in zip(mods, wide)]
     segs = [(i, mg.OP_MUL, "classic", int(n), int(o), int(o)) for i, (n, o) in enumerate(zip(lens, offs))]
     d = {k: torch.from_numpy(v).to(dev) for k, v in (("a32", a32), ("b32", b32), ("a64", a64), ("b64", b64))}
     o32 = torch.empty_like(d["a32"])
     o64 = torch.empty_like(d["a64"])
     P = mg.pools([None, d["a32"], d["a64"]], [None, d["b32"], d["b64"]], [None, o32, o64])
-    nbytes = 12 * a32.size + 24 * a64.size
+    nbytes = 12 * int(sum(n for n, wd in zip(lens, wide) if not wd)) + 24 * int(sum(n for n, wd in zip(lens, wide) if wd))
     res = {"segments": nseg, "elements": int(lens.sum()), "bytes": nbytes}
     for name, flags in (("persistent_graph", mg.BATCH_GRAPH | mg.BATCH_TUNE),):
         bt = mg.Batch(ctxs, segs, flags=flags)

@@ -344,6 +344,19 @@ double mont_serve_now(void);
 void mont_serve_destroy(mont_server_t *s);
 
 /* --------------------------------------------------------------------------
+ * Measurement aid.
+ */
+
+/*
+ * mont_stream_ref -- out = a XOR b over `bytes` bytes (a multiple of 16, all
+ * three pointers 16-byte aligned device memory): the access pattern and
+ * launch shape of mont_mul with no arithmetic, so its bandwidth is the
+ * practical HBM ceiling for a 2-read/1-write stream.  Not part of the
+ * paper's method.
+ */
+mont_status_t mont_stream_ref(const void *a, const void *b, void *out, size_t bytes, void *stream);
+
+/* --------------------------------------------------------------------------
  * Misc.
  */
 const char *mont_last_error(void);

@@ -16,5 +16,5 @@ Operations (all in HIP kernels of libmont.so, called through its C ABI):
 from ._lib import (  # noqa: F401
     BATCH_DYNAMIC, BATCH_GRAPH, BATCH_TUNE, CLASSIC, OP_MUL, OP_POW, OP_REDC, PLANTARD, SIGNED,
     SIGNED_PLANTARD, SIGNED_PLANTARD_ALPHA, VARIANTS, Batch, Ctx, MontError, elem_dtype, get_launch,
-    header_functions, load, mul, mul_rns, pools, pow, redc, redc_range, set_launch, setup, tune_mul,
+    Server, header_functions, load, mul, mul_rns, pools, pow, redc, redc_range, set_launch, setup, stream_ref, tune_mul,
 )

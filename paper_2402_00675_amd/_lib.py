@@ -92,6 +92,7 @@ def load():
         "mont_tune_mul": (i32, [P(CtxStruct), vp, vp, vp, sz, i32, P(LaunchStruct), vp]),
         "mont_set_launch": (i32, [u32, u32, i32, P(LaunchStruct)]),
         "mont_get_launch": (i32, [u32, u32, i32, P(LaunchStruct)]),
+        "mont_stream_ref": (i32, [vp, vp, vp, sz, vp]),
         "mont_last_error": (ctypes.c_char_p, []),
         "mont_version": (u32, []),
     }
@@ -242,7 +243,15 @@ def redc_range(ctx: Ctx, T0: int, n: int, out=None, variant="classic", stream=No
     return out
 
 
-def set_launch(op: int, w: int, variant, unroll=2, nontemporal=0, blocks_per_cu=0):
+def stream_ref(a, b, out, stream=None):
+    """out = a XOR b (reference 2-read/1-write stream, no arithmetic)."""
+    nbytes = a.numel() * a.element_size()
+    check(load().mont_stream_ref(_dev(a, "a", 1, nbytes), _dev(b, "b", 1, nbytes), _dev(out, "out", 1, nbytes),
+                                 nbytes, _stream(stream)))
+    return out
+
+
+def set_launch(op: int, w: int, variant, unroll=1, nontemporal=1, blocks_per_cu=0):
     L = LaunchStruct(unroll, nontemporal, blocks_per_cu)
     check(load().mont_set_launch(op, w, variant_id(variant), ctypes.byref(L)))
 
@@ -322,3 +331,134 @@ class Batch:
 def as_numpy_u64(t) -> np.ndarray:
     """Copies a CUDA tensor to host numpy, keeping unsigned dtypes."""
     return t.cpu().numpy()
+
+
+# ------------------------------------------------------------------- serving
+
+
+class ServerCfgStruct(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_jobs_in_flight", ctypes.c_uint32),
+                ("streams", ctypes.c_uint32), ("max_batch_jobs", ctypes.c_uint32), ("tile_elems", ctypes.c_uint32)]
+
+
+class JobStruct(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("N", ctypes.c_uint64), ("w", ctypes.c_uint32), ("op", ctypes.c_uint32),
+                ("n", ctypes.c_uint64), ("in0", ctypes.c_void_p), ("in1", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+class CompletionStruct(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int32), ("reserved", ctypes.c_uint32),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_launch", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class ServerStatsStruct(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in ("submitted", "completed", "rejected", "launches", "jobs_launched",
+                                                 "queued", "staged", "in_flight", "bytes_in_use",
+                                                 "peak_bytes_in_use")]
+
+
+_SERVE_SIG = {
+    "mont_serve_create": (ctypes.c_int32, [ctypes.POINTER(ServerCfgStruct), ctypes.POINTER(ctypes.c_void_p)]),
+    "mont_serve_submit": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(JobStruct)]),
+    "mont_serve_submit_timed": (ctypes.c_int64, [ctypes.c_void_p, ctypes.POINTER(JobStruct),
+                                                 ctypes.POINTER(ctypes.c_double), ctypes.c_uint64]),
+    "mont_serve_poll": (ctypes.c_int64, [ctypes.c_void_p, ctypes.POINTER(CompletionStruct), ctypes.c_uint32,
+                                         ctypes.c_int32]),
+    "mont_serve_drain": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "mont_serve_stats": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ServerStatsStruct)]),
+    "mont_serve_now": (ctypes.c_double, []),
+    "mont_serve_destroy": (None, [ctypes.c_void_p]),
+}
+
+
+def _serve_lib():
+    lib = load()
+    if not getattr(lib, "_serve_sig_done", False):
+        for name, (res, args) in _SERVE_SIG.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        lib._serve_sig_done = True
+    return lib
+
+
+def host_ptr(x) -> int:
+    """Address of a host buffer: a numpy array or a CPU (ideally pinned) torch tensor."""
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("host buffers must be contiguous")
+        return x.ctypes.data
+    if getattr(x, "device", None) is not None and x.device.type == "cpu":
+        return x.data_ptr()
+    raise TypeError("serving jobs take host buffers (numpy arrays or CPU tensors)")
+
+
+class Server:
+    """The continuous-batching request loop (mont_serve_*)."""
+
+    def __init__(self, hbm_budget_bytes=8 << 30, max_jobs_in_flight=4096, streams=3, max_batch_jobs=512,
+                 tile_elems=0):
+        lib = _serve_lib()
+        cfg = ServerCfgStruct(hbm_budget_bytes, max_jobs_in_flight, streams, max_batch_jobs, tile_elems)
+        self.h = ctypes.c_void_p()
+        check(lib.mont_serve_create(ctypes.byref(cfg), ctypes.byref(self.h)))
+        self._keep = {}
+
+    @staticmethod
+    def job(id_, N, w, op, n, in0, in1, out) -> JobStruct:
+        return JobStruct(id_, N, w, op, n, host_ptr(in0), host_ptr(in1), host_ptr(out))
+
+    def submit(self, id_, N, w, op, in0, in1, out):
+        n = len(in0)
+        j = self.job(id_, N, w, op, n, in0, in1, out)
+        self._keep[id_] = (in0, in1, out)
+        check(_serve_lib().mont_serve_submit(self.h, ctypes.byref(j)))
+
+    def submit_struct(self, j: JobStruct):
+        """Queues a prepared JobStruct (its host buffers are the caller's to keep alive)."""
+        check(_serve_lib().mont_serve_submit(self.h, ctypes.byref(j)))
+
+    def submit_timed(self, jobs: "ctypes.Array", arrival_s: np.ndarray) -> int:
+        """Blocking: submits jobs[i] at arrival_s[i] seconds from now (call it from a thread)."""
+        t = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        k = _serve_lib().mont_serve_submit_timed(self.h, jobs, t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                 len(t))
+        if k < 0:
+            check(int(k))
+        return int(k)
+
+    def poll(self, max_n=4096, wait_ms=0):
+        buf = (CompletionStruct * max_n)()
+        k = _serve_lib().mont_serve_poll(self.h, buf, max_n, wait_ms)
+        if k < 0:
+            check(int(k))
+        out = []
+        for i in range(k):
+            c = buf[i]
+            self._keep.pop(c.id, None)
+            out.append((c.id, c.status, c.t_submit, c.t_admit, c.t_launch, c.t_done))
+        return out
+
+    def drain(self, timeout_ms=-1):
+        check(_serve_lib().mont_serve_drain(self.h, timeout_ms))
+
+    def stats(self):
+        s = ServerStatsStruct()
+        check(_serve_lib().mont_serve_stats(self.h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStatsStruct._fields_}
+
+    @staticmethod
+    def now() -> float:
+        return _serve_lib().mont_serve_now()
+
+    def close(self):
+        if self.h:
+            _serve_lib().mont_serve_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

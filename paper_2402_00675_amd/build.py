@@ -25,6 +25,7 @@ SOURCES = [
     "mont_k32.hip",
     "mont_k64.hip",
     "mont_ragged.hip",
+    "mont_ref.hip",
     "mont_capi.cpp",
     "mont_setup.cpp",
     "mont_serve.cpp",

@@ -320,6 +320,23 @@ struct Red<64, CLASSIC> {
         const u128v p = sqr_64(a);
         return reduce(p.lo, p.hi);
     }
+    // (T + mN)/R without the final subtraction: for N < 2^62 and inputs below
+    // 2N the result is below 2N (the sum T + mN < 2RN never leaves 128 bits).
+    __device__ __forceinline__ E reduce_lazy(uint64_t tl, uint64_t th) const
+    {
+        const uint64_t m = tl * np;
+        return th + mulhi_64(m, N) + (tl != 0u);
+    }
+    __device__ __forceinline__ E mul_lazy(E a, E b) const
+    {
+        const u128v p = mul_64x64(a, b);
+        return reduce_lazy(p.lo, p.hi);
+    }
+    __device__ __forceinline__ E sqr_lazy(E a) const
+    {
+        const u128v p = sqr_64(a);
+        return reduce_lazy(p.lo, p.hi);
+    }
 };
 
 template <>

@@ -81,6 +81,11 @@ static void launch_defaults()
         for (auto &b : a)
             for (auto &l : b)
                 l = Launch{};
+    // exponentiation is ALU-bound: two independent elements per lane hide the
+    // latency of the dependent multiply chains
+    for (auto &b : g_launch[2])
+        for (auto &l : b)
+            l.unroll = 2;
     g_launch_init = true;
 }
 

@@ -103,10 +103,19 @@ hipError_t launch_pow(const KCtx &c, const void *x, const uint64_t *e, void *out
     L.blocks_per_cu = blocks_per_cu;
     const int U = unroll == 2 ? 2 : 1;
     dim3 grid((unsigned)grid_x(n, U, 1, L));
-    if (U == 2)
-        hipLaunchKernelGGL((k_pow<W, 2>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
-    else
-        hipLaunchKernelGGL((k_pow<W, 1>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
+    // lazy ladder (no per-product subtraction) when 4N <= R: 64-bit words with N < 2^62
+    const bool lazy = W == 64 && c.N < (1ull << 62);
+    if (lazy) {
+        if (U == 2)
+            hipLaunchKernelGGL((k_pow<W, 2, W == 64>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
+        else
+            hipLaunchKernelGGL((k_pow<W, 1, W == 64>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
+    } else {
+        if (U == 2)
+            hipLaunchKernelGGL((k_pow<W, 2, false>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
+        else
+            hipLaunchKernelGGL((k_pow<W, 1, false>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
+    }
     return hipGetLastError();
 }
 

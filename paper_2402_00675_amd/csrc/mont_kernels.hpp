@@ -21,9 +21,13 @@ struct KTab {
     KCtx c[NR];
 };
 
+// Launch shape of the streaming kernels.  The default (one 16-byte chunk per
+// lane, non-temporal loads and stores, one pass over the data) was the
+// fastest measured on MI355X for the 2-read/1-write pattern at HBM-resident
+// sizes; grid-stride loops over a CU-multiple grid were 10-20% slower.
 struct Launch {
-    int unroll = 2;        // 1, 2, 4
-    int nontemporal = 0;   // 0 / 1
+    int unroll = 1;        // 1, 2, 4
+    int nontemporal = 1;   // 0 / 1
     int blocks_per_cu = 0; // 0: one pass
 };
 
@@ -110,6 +114,17 @@ __device__ __forceinline__ void store_chunk(X *p, const X (&v)[E])
 
 // ------------------------------------------------------------------ kernels
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup i runs on
+// XCD i mod 8).  Renumbering them so that each XCD walks one contiguous eighth
+// of the index space keeps each XCD's traffic in a compact address window;
+// it is a bijection whenever the grid is a multiple of 8 (else the identity).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t g)
+{
+    if (g % 8u)
+        return b;
+    return (b % 8u) * (g / 8u) + b / 8u;
+}
+
 // out[i] = red.mul(a[i], b[i]) (OP 0) or red.redc(T[i]) (OP 1), per row.
 template <int W, int V, int OP, int E, int U, bool NT, int NR>
 __global__ void __launch_bounds__(BLOCK)
@@ -128,7 +143,8 @@ __global__ void __launch_bounds__(BLOCK)
 
     const uint64_t nchunk = n / E;
     const uint64_t step = (uint64_t)gridDim.x * (BLOCK * U);
-    for (uint64_t base = (uint64_t)blockIdx.x * (BLOCK * U) + threadIdx.x; base < nchunk; base += step) {
+    const uint32_t bx = xcd_block(blockIdx.x, gridDim.x);
+    for (uint64_t base = (uint64_t)bx * (BLOCK * U) + threadIdx.x; base < nchunk; base += step) {
         El a[U][E], b[U][E];
         TT t[U][E];
 #pragma unroll
@@ -161,7 +177,7 @@ __global__ void __launch_bounds__(BLOCK)
     }
     if constexpr (E > 1) {
         // the last n mod E elements of the row
-        if (blockIdx.x == 0 && threadIdx.x < (unsigned)E) {
+        if (bx == 0 && threadIdx.x < (unsigned)E) {
             const uint64_t i = nchunk * E + threadIdx.x;
             if (i < n) {
                 if constexpr (OP == 0)
@@ -197,28 +213,52 @@ __device__ __forceinline__ El sel4(uint32_t d, El t0, El t1, El t2, El t3)
     return (d & 2u) ? hi : lo;
 }
 
+// Montgomery products with the final subtraction dropped ("lazy"): for
+// 4N <= R and inputs below 2N, (T + mN)/R < 4N^2/R + N <= 2N, so every result
+// stays below 2N and is a valid input again.  Only the classic 64-bit form
+// provides them; they are used when N < 2^62.
+template <class R, bool LAZY>
+struct Ladder {
+    __device__ __forceinline__ static typename R::E mul(const R &r, typename R::E a, typename R::E b)
+    {
+        if constexpr (LAZY)
+            return r.mul_lazy(a, b);
+        else
+            return r.mul(a, b);
+    }
+    __device__ __forceinline__ static typename R::E sqr(const R &r, typename R::E a)
+    {
+        if constexpr (LAZY)
+            return r.sqr_lazy(a);
+        else
+            return r.sqr(a);
+    }
+};
+
 // x^e mod N: Montgomery form x R = REDC(x * (R^2 mod N)), a left-to-right
 // 2-bit fixed-window ladder of Montgomery products (every lane runs the same
-// 32 windows: no divergence), and REDC back to an ordinary residue.
-template <class R>
+// 32 windows: no divergence), and REDC back to an ordinary residue; the
+// returned Montgomery-form value is below 2N (LAZY) or below N.
+template <class R, bool LAZY = false>
 __device__ __forceinline__ typename R::E pow_one(const R &red, typename R::E x, uint64_t k,
                                                  typename R::E r2, typename R::E one)
 {
     using El = typename R::E;
-    const El x1 = red.mul(x, r2);
-    const El x2 = red.sqr(x1);
-    const El x3 = red.mul(x2, x1);
+    using L = Ladder<R, LAZY>;
+    const El x1 = L::mul(red, x, r2);
+    const El x2 = L::sqr(red, x1);
+    const El x3 = L::mul(red, x2, x1);
     El y = sel4<El>((uint32_t)(k >> 62), one, x1, x2, x3);
 #pragma unroll 4
     for (int s = 60; s >= 0; s -= 2) {
-        y = red.sqr(y);
-        y = red.sqr(y);
-        y = red.mul(y, sel4<El>((uint32_t)(k >> s) & 3u, one, x1, x2, x3));
+        y = L::sqr(red, y);
+        y = L::sqr(red, y);
+        y = L::mul(red, y, sel4<El>((uint32_t)(k >> s) & 3u, one, x1, x2, x3));
     }
     return y;
 }
 
-template <int W, int U>
+template <int W, int U, bool LAZY>
 __global__ void __launch_bounds__(BLOCK)
     k_pow(KCtx c, const void *__restrict__ xin, const uint64_t *__restrict__ ein, void *__restrict__ out, uint64_t n)
 {
@@ -241,7 +281,7 @@ __global__ void __launch_bounds__(BLOCK)
         El y[U];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            y[u] = pow_one(red, x[u], k[u], r2, one);
+            y[u] = pow_one<R, LAZY>(red, x[u], k[u], r2, one);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint64_t i = base + (uint64_t)u * BLOCK;

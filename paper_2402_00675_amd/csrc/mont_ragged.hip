@@ -37,7 +37,7 @@ struct WC {
     static constexpr int v = W == 16 ? 0 : W == 32 ? 1 : 2;
 };
 
-template <int W, int V, int OP>
+template <int W, int V, int OP, bool NT>
 __device__ __forceinline__ void tile_map(const KCtx &c, const DPools &P, uint64_t g0, uint64_t g1, uint32_t cnt)
 {
     using R = Red<W, V>;
@@ -72,10 +72,10 @@ __device__ __forceinline__ void tile_map(const KCtx &c, const DPools &P, uint64_
             if (ci < nv) {
                 const uint64_t g = gv + (uint64_t)ci * E;
                 if constexpr (OP == 0) {
-                    load_chunk<El, E, false>(pa + g, a[u]);
-                    load_chunk<El, E, false>(pb + g, b[u]);
+                    load_chunk<El, E, NT>(pa + g, a[u]);
+                    load_chunk<El, E, NT>(pb + g, b[u]);
                 } else {
-                    load_chunk<TT, E, false>(pt + g, t[u]);
+                    load_chunk<TT, E, NT>(pt + g, t[u]);
                 }
             }
         }
@@ -91,7 +91,7 @@ __device__ __forceinline__ void tile_map(const KCtx &c, const DPools &P, uint64_
                     else
                         o[e] = red.redc(t[u][e]);
                 }
-                store_chunk<El, E, false>(po + gv + (uint64_t)ci * E, o);
+                store_chunk<El, E, NT>(po + gv + (uint64_t)ci * E, o);
             }
         }
     }
@@ -116,48 +116,50 @@ __device__ __forceinline__ void tile_pow(const KCtx &c, const DPools &P, uint64_
     const El *px = (const El *)P.in0[wc];
     const uint64_t *pe = (const uint64_t *)P.in1[wc] + (int64_t)(g1 - g0);
     El *po = (El *)P.out[wc];
+    const bool lazy = W == 64 && c.N < (1ull << 62);  // wave-uniform
     for (uint32_t i = threadIdx.x; i < cnt; i += BLOCK) {
         const uint64_t g = g0 + i;
-        const El y = pow_one(red, px[g], pe[g], r2, one);
+        const El y = lazy ? pow_one<R, W == 64>(red, px[g], pe[g], r2, one) : pow_one<R, false>(red, px[g], pe[g], r2, one);
         po[g] = red.redc(WideT<W>::of(y));
     }
 }
 
-template <int W, int OP>
+template <int W, int OP, bool NT>
 __device__ __forceinline__ void tile_variant(uint32_t variant, const KCtx &c, const DPools &P, uint64_t g0,
                                              uint64_t g1, uint32_t cnt)
 {
     switch (variant) {
     case CLASSIC:
-        tile_map<W, CLASSIC, OP>(c, P, g0, g1, cnt);
+        tile_map<W, CLASSIC, OP, NT>(c, P, g0, g1, cnt);
         break;
     case SIGNED:
-        tile_map<W, SIGNED, OP>(c, P, g0, g1, cnt);
+        tile_map<W, SIGNED, OP, NT>(c, P, g0, g1, cnt);
         break;
     case PLANTARD:
-        tile_map<W, PLANTARD, OP>(c, P, g0, g1, cnt);
+        tile_map<W, PLANTARD, OP, NT>(c, P, g0, g1, cnt);
         break;
     case SIGNED_PLANTARD:
-        tile_map<W, SIGNED_PLANTARD, OP>(c, P, g0, g1, cnt);
+        tile_map<W, SIGNED_PLANTARD, OP, NT>(c, P, g0, g1, cnt);
         break;
     default:
-        tile_map<W, SIGNED_PLANTARD_ALPHA, OP>(c, P, g0, g1, cnt);
+        tile_map<W, SIGNED_PLANTARD_ALPHA, OP, NT>(c, P, g0, g1, cnt);
         break;
     }
 }
 
-template <int W>
+template <int W, bool NT>
 __device__ __forceinline__ void tile_width(uint32_t op, uint32_t variant, const KCtx &c, const DPools &P,
                                            uint64_t g0, uint64_t g1, uint32_t cnt)
 {
     if (op == MONT_OP_MUL)
-        tile_variant<W, 0>(variant, c, P, g0, g1, cnt);
+        tile_variant<W, 0, NT>(variant, c, P, g0, g1, cnt);
     else if (op == MONT_OP_REDC)
-        tile_variant<W, 1>(variant, c, P, g0, g1, cnt);
+        tile_variant<W, 1, NT>(variant, c, P, g0, g1, cnt);
     else
         tile_pow<W>(c, P, g0, g1, cnt);
 }
 
+template <bool NT>
 __global__ void __launch_bounds__(BLOCK)
     k_ragged(const DSeg *__restrict__ segs, const DTile *__restrict__ tiles, uint32_t ntiles, DPools P,
              uint32_t *__restrict__ ctr, uint32_t dynamic)
@@ -171,7 +173,7 @@ __global__ void __launch_bounds__(BLOCK)
         __syncthreads();
         t = s_next[0];
     } else {
-        t = blockIdx.x;
+        t = xcd_block(blockIdx.x, gridDim.x);
     }
     while (t < ntiles) {
         t = __builtin_amdgcn_readfirstlane(t);
@@ -183,11 +185,11 @@ __global__ void __launch_bounds__(BLOCK)
         const uint64_t g1 = sd.off1 + td.start;
         const uint32_t wc = sd.wc;
         if (wc == 0)
-            tile_width<16>(sd.op, sd.variant, sd.c, P, g0, g1, td.cnt);
+            tile_width<16, NT>(sd.op, sd.variant, sd.c, P, g0, g1, td.cnt);
         else if (wc == 1)
-            tile_width<32>(sd.op, sd.variant, sd.c, P, g0, g1, td.cnt);
+            tile_width<32, NT>(sd.op, sd.variant, sd.c, P, g0, g1, td.cnt);
         else
-            tile_width<64>(sd.op, sd.variant, sd.c, P, g0, g1, td.cnt);
+            tile_width<64, NT>(sd.op, sd.variant, sd.c, P, g0, g1, td.cnt);
         if (dynamic) {
             __syncthreads();  // s_next[buf^1] written; everyone done with s_next[buf]
             buf ^= 1;
@@ -228,9 +230,9 @@ struct mont_batch {
     size_t tiles_cap = 0;
     uint32_t ntiles = 0;
     uint64_t elements = 0;
-    uint32_t tile_base = 8192;   // 32-bit streaming tile (elements)
+    uint32_t tile_base = 4096;   // 32-bit streaming tile (elements)
     uint32_t pow_tile = 1024;
-    uint32_t blocks_per_cu = 8;
+    uint32_t blocks_per_cu = 0;  // 0: one workgroup per tile (one pass), else a persistent grid
     uint32_t grid = 0;
     uint32_t flags = 0;
     uint32_t op_mask = 0;
@@ -238,8 +240,11 @@ struct mont_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t node = nullptr;
+    bool nt = true;              // non-temporal loads/stores
     DPools last{};
-    uint32_t last_grid = 0, last_dyn = 0;
+    uint32_t last_grid = 0, last_dyn = 0, last_ntiles = 0;
+    bool last_nt = true;
+    DTile *last_tiles = nullptr;
 };
 
 namespace mont {
@@ -292,7 +297,7 @@ static mont_status_t build_tiles(mont_batch &b, hipStream_t s)
         if (e != hipSuccess)
             return hip_fail(e, "tile table upload");
     }
-    const uint64_t g = (uint64_t)device_cus() * b.blocks_per_cu;
+    const uint64_t g = b.blocks_per_cu ? (uint64_t)device_cus() * b.blocks_per_cu : (uint64_t)b.ntiles;
     b.grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, b.ntiles));
     return MONT_OK;
 }
@@ -328,18 +333,21 @@ static mont_status_t check_pools(const mont_batch &b, const mont_pools_t *p)
     return MONT_OK;
 }
 
-void *ragged_kernel_ptr() { return (void *)k_ragged; }
+void *ragged_kernel_ptr(bool nt) { return nt ? (void *)k_ragged<true> : (void *)k_ragged<false>; }
 
 hipError_t launch_ragged(const DSeg *segs, const DTile *tiles, uint32_t ntiles, const DPools &P, uint32_t *ctr,
-                         uint32_t dyn, uint32_t grid, hipStream_t s)
+                         uint32_t dyn, uint32_t grid, bool nt, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ragged, dim3(grid), dim3(BLOCK), 0, s, segs, tiles, ntiles, P, ctr, dyn);
+    if (nt)
+        hipLaunchKernelGGL(k_ragged<true>, dim3(grid), dim3(BLOCK), 0, s, segs, tiles, ntiles, P, ctr, dyn);
+    else
+        hipLaunchKernelGGL(k_ragged<false>, dim3(grid), dim3(BLOCK), 0, s, segs, tiles, ntiles, P, ctr, dyn);
     return hipGetLastError();
 }
 
 static mont_status_t launch_direct(mont_batch &b, const DPools &P, hipStream_t s, uint32_t dyn)
 {
-    const hipError_t e = launch_ragged(b.dsegs, b.dtiles, b.ntiles, P, b.dctr, dyn, b.grid, s);
+    const hipError_t e = launch_ragged(b.dsegs, b.dtiles, b.ntiles, P, b.dctr, dyn, b.grid, b.nt, s);
     return e == hipSuccess ? MONT_OK : hip_fail(e, "ragged launch");
 }
 
@@ -352,7 +360,7 @@ static mont_status_t launch_graph(mont_batch &b, const DPools &P, hipStream_t s,
     uint32_t *ctr = b.dctr;
     void *args[] = {&segs, &tiles, &nt, &Pc, &ctr, &dyn};
     hipKernelNodeParams kp{};
-    kp.func = ragged_kernel_ptr();
+    kp.func = ragged_kernel_ptr(b.nt);
     kp.gridDim = dim3(b.grid);
     kp.blockDim = dim3(BLOCK);
     kp.sharedMemBytes = 0;
@@ -367,7 +375,8 @@ static mont_status_t launch_graph(mont_batch &b, const DPools &P, hipStream_t s,
             e = hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0);
         if (e != hipSuccess)
             return hip_fail(e, "ragged graph build");
-    } else if (std::memcmp(&b.last, &P, sizeof P) != 0 || b.last_grid != b.grid || b.last_dyn != dyn) {
+    } else if (std::memcmp(&b.last, &P, sizeof P) != 0 || b.last_grid != b.grid || b.last_dyn != dyn ||
+               b.last_nt != b.nt || b.last_ntiles != b.ntiles || b.last_tiles != b.dtiles) {
         e = hipGraphExecKernelNodeSetParams(b.exec, b.node, &kp);
         if (e != hipSuccess)
             return hip_fail(e, "ragged graph update");
@@ -375,6 +384,9 @@ static mont_status_t launch_graph(mont_batch &b, const DPools &P, hipStream_t s,
     b.last = P;
     b.last_grid = b.grid;
     b.last_dyn = dyn;
+    b.last_nt = b.nt;
+    b.last_ntiles = b.ntiles;
+    b.last_tiles = b.dtiles;
     e = hipGraphLaunch(b.exec, s);
     return e == hipSuccess ? MONT_OK : hip_fail(e, "ragged graph launch");
 }
@@ -389,7 +401,7 @@ static mont_status_t run_once(mont_batch &b, const DPools &P, hipStream_t s)
 
 // Tuning: tile size x workgroups per CU x schedule, timed with HIP events.
 struct RaggedTune {
-    uint32_t tile_base, blocks_per_cu, dynamic;
+    uint32_t tile_base, blocks_per_cu, dynamic, nt;
 };
 static std::mutex g_rt_mu;
 static std::unordered_map<std::string, RaggedTune> g_rt_cache;
@@ -417,6 +429,7 @@ static mont_status_t tune(mont_batch &b, const DPools &P, hipStream_t s)
         if (it != g_rt_cache.end()) {
             b.tile_base = it->second.tile_base;
             b.blocks_per_cu = it->second.blocks_per_cu;
+            b.nt = it->second.nt != 0;
             b.flags = (b.flags & ~MONT_BATCH_DYNAMIC) | (it->second.dynamic ? MONT_BATCH_DYNAMIC : 0u);
             return build_tiles(b, s);
         }
@@ -424,10 +437,10 @@ static mont_status_t tune(mont_batch &b, const DPools &P, hipStream_t s)
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(MONT_E_DEVICE, "event create");
-    const uint32_t tiles[] = {4096, 8192, 16384, 32768};
-    const uint32_t bpcs[] = {4, 8, 16};
+    const uint32_t tiles[] = {1024, 2048, 4096, 8192, 16384};
+    const uint32_t bpcs[] = {0, 4, 8, 16};
     float best = 1e30f;
-    RaggedTune bt{b.tile_base, b.blocks_per_cu, (b.flags & MONT_BATCH_DYNAMIC) ? 1u : 0u};
+    RaggedTune bt{b.tile_base, b.blocks_per_cu, (b.flags & MONT_BATCH_DYNAMIC) ? 1u : 0u, b.nt ? 1u : 0u};
     const uint32_t saved_flags = b.flags;
     b.flags &= ~MONT_BATCH_GRAPH;  // time direct launches
     mont_status_t rc = MONT_OK;
@@ -438,8 +451,12 @@ static mont_status_t tune(mont_batch &b, const DPools &P, hipStream_t s)
             b.blocks_per_cu = bpc;
             if ((rc = build_tiles(b, s)))
                 goto done;
-            for (uint32_t dyn = 0; dyn < 2; ++dyn) {
+            for (uint32_t v = 0; v < 4; ++v) {
+                const uint32_t dyn = v & 1u, nt = v >> 1;
+                if (dyn && !bpc)
+                    continue;  // one workgroup per tile: nothing to balance
                 b.flags = (b.flags & ~MONT_BATCH_DYNAMIC) | (dyn ? MONT_BATCH_DYNAMIC : 0u);
+                b.nt = nt != 0;
                 if ((rc = run_once(b, P, s)))  // warm
                     goto done;
                 (void)hipEventRecord(e0, s);
@@ -455,7 +472,7 @@ static mont_status_t tune(mont_batch &b, const DPools &P, hipStream_t s)
                 (void)hipEventElapsedTime(&ms, e0, e1);
                 if (ms < best) {
                     best = ms;
-                    bt = {tb, bpc, dyn};
+                    bt = {tb, bpc, dyn, nt};
                 }
             }
         }
@@ -468,6 +485,7 @@ done:
         return rc;
     b.tile_base = bt.tile_base;
     b.blocks_per_cu = bt.blocks_per_cu;
+    b.nt = bt.nt != 0;
     {
         std::lock_guard<std::mutex> g(g_rt_mu);
         g_rt_cache[key] = bt;

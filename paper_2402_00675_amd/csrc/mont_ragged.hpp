@@ -31,8 +31,9 @@ struct DPools {
 
 // One persistent launch over `ntiles` tiles (ctr: two zeroed uint32 that the
 // kernel leaves zeroed again when dyn = 1).
+// nt selects non-temporal loads and stores.
 hipError_t launch_ragged(const DSeg *segs, const DTile *tiles, uint32_t ntiles, const DPools &P, uint32_t *ctr,
-                         uint32_t dyn, uint32_t grid, hipStream_t s);
-void *ragged_kernel_ptr();
+                         uint32_t dyn, uint32_t grid, bool nt, hipStream_t s);
+void *ragged_kernel_ptr(bool nt);
 
 }  // namespace mont

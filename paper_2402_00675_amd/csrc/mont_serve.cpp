@@ -217,7 +217,7 @@ class GpuBackend : public mont_sched::Backend {
             P.in1[2] = in1[1];
             P.out[2] = out[1];
             const uint32_t grid = (uint32_t)std::max<size_t>(1, std::min<size_t>(tiles.size(), grid_max));
-            e = launch_ragged(s.dsegs, s.dtiles, (uint32_t)tiles.size(), P, s.dctr, 1u, grid, s.stream);
+            e = launch_ragged(s.dsegs, s.dtiles, (uint32_t)tiles.size(), P, s.dctr, 1u, grid, true, s.stream);
         }
         for (const mont_sched::Job *jp : jobs) {
             const mont_sched::Job &j = *jp;

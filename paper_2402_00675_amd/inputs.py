@@ -175,14 +175,18 @@ class RaggedWorkload:
         return lens, wide, mods
 
     def operands(self, lens, wide, mods, rep: int = 0):
-        """Operands packed into one uint32 pool and one uint64 pool, in segment order."""
+        """Operands packed into one uint32 pool and one uint64 pool, in segment
+        order, each vector starting on a 16-byte boundary (so a per-vector
+        launch can use 16-byte accesses too)."""
         g = rng(W_RAGGED, rep + 1)
-        n32 = int(sum(int(n) for n, wd in zip(lens, wide) if not wd))
-        n64 = int(sum(int(n) for n, wd in zip(lens, wide) if wd))
-        a32 = np.empty(n32, np.uint32)
-        b32 = np.empty(n32, np.uint32)
-        a64 = np.empty(n64, np.uint64)
-        b64 = np.empty(n64, np.uint64)
+        pad32 = [(int(n) + 3) // 4 * 4 for n, wd in zip(lens, wide) if not wd]
+        pad64 = [(int(n) + 1) // 2 * 2 for n, wd in zip(lens, wide) if wd]
+        n32 = int(sum(pad32))
+        n64 = int(sum(pad64))
+        a32 = np.zeros(n32, np.uint32)
+        b32 = np.zeros(n32, np.uint32)
+        a64 = np.zeros(n64, np.uint64)
+        b64 = np.zeros(n64, np.uint64)
         offs = []
         o32 = o64 = 0
         for n, wd, N in zip(lens, wide, mods):
@@ -191,12 +195,12 @@ class RaggedWorkload:
                 a64[o64:o64 + n] = g.integers(0, N, size=n, dtype=np.uint64)
                 b64[o64:o64 + n] = g.integers(0, N, size=n, dtype=np.uint64)
                 offs.append(o64)
-                o64 += n
+                o64 += (n + 1) // 2 * 2
             else:
                 a32[o32:o32 + n] = g.integers(0, N, size=n, dtype=np.uint64).astype(np.uint32)
                 b32[o32:o32 + n] = g.integers(0, N, size=n, dtype=np.uint64).astype(np.uint32)
                 offs.append(o32)
-                o32 += n
+                o32 += (n + 3) // 4 * 4
         return np.array(offs, np.int64), (a32, b32), (a64, b64)
 
 

@@ -1,0 +1,139 @@
+"""Driver of the continuous-batching request loop (mont_serve_* in libmont.so).
+
+The loop itself is native (a service thread in the library).  This module
+builds a job stream (Poisson arrivals, mixed products and exponentiations,
+log-uniform lengths, each job with its own odd 31- or 62-bit modulus),
+replays it against a Server with native-clock arrivals, and summarises the
+completions as latency percentiles and throughput.
+
+Host staging: jobs read their operands from pinned host pools (values below
+every modulus of their class: [0, 2^30) for 31-bit and [0, 2^61) for 62-bit
+moduli; exponents uniform over 64 bits) at a seeded offset per job, and write
+results into pinned result buffers.  With ``distinct_outputs=False`` all jobs
+of a class share one result buffer (a sink), which keeps host memory bounded
+for 10^5-job streams while still copying every result back.
+"""
+from __future__ import annotations
+
+import threading
+
+import numpy as np
+
+from . import _lib
+from . import inputs as inp
+
+POOL_SLACK = 1 << 16
+
+
+def _pinned(torch, n, dtype):
+    return torch.empty(n, dtype=dtype, pin_memory=True)
+
+
+class JobStream:
+    """Jobs of one stream with their host buffers (kept alive here)."""
+
+    def __init__(self, torch, njobs, seed_rep=0, distinct_outputs=False, hi=None):
+        wl = inp.ServeWorkload()
+        if hi is not None:
+            wl.hi = hi
+        t, ops, lens, wide, mods, seeds = wl.jobs(rate_per_s=1.0, rep=seed_rep, njobs=njobs)
+        self.gaps_unit = t            # arrival times for rate 1 job/s
+        self.ops, self.lens, self.wide, self.mods = ops, lens, wide, mods
+        self.njobs = njobs
+        g = inp.rng(inp.W_SERVE, 100 + seed_rep)
+        P = int(wl.hi) + POOL_SLACK
+        self.pool = {
+            32: (_pinned(torch, P, torch.uint32), _pinned(torch, P, torch.uint32)),
+            64: (_pinned(torch, P, torch.uint64), _pinned(torch, P, torch.uint64)),
+        }
+        self.pool[32][0].numpy()[:] = g.integers(0, 1 << 30, size=P, dtype=np.uint64).astype(np.uint32)
+        self.pool[32][1].numpy()[:] = g.integers(0, 1 << 30, size=P, dtype=np.uint64).astype(np.uint32)
+        self.pool[64][0].numpy()[:] = g.integers(0, 1 << 61, size=P, dtype=np.uint64)
+        self.pool[64][1].numpy()[:] = g.integers(0, 1 << 61, size=P, dtype=np.uint64)
+        self.exps = _pinned(torch, P, torch.uint64)
+        self.exps.numpy()[:] = inp.u64_uniform(g, P)
+        offs = (seeds % POOL_SLACK).astype(np.int64)
+        self.offs = offs
+        self.jobs = (_lib.JobStruct * njobs)()
+        self.outs = {}
+        if not distinct_outputs:
+            self.sink = {32: _pinned(torch, P, torch.uint32), 64: _pinned(torch, P, torch.uint64)}
+        esz = {32: 4, 64: 8}
+        for i in range(njobs):
+            w = 64 if wide[i] else 32
+            n = int(lens[i])
+            o = int(offs[i])
+            x, b = self.pool[w]
+            in0 = x.data_ptr() + o * esz[w]
+            if ops[i] == 0:
+                op, in1 = _lib.OP_MUL, b.data_ptr() + o * esz[w]
+            else:
+                op, in1 = _lib.OP_POW, self.exps.data_ptr() + o * 8
+            if distinct_outputs:
+                out_t = _pinned(torch, n, torch.uint32 if w == 32 else torch.uint64)
+                self.outs[i] = out_t
+                out = out_t.data_ptr()
+            else:
+                out = self.sink[w].data_ptr()
+            j = self.jobs[i]
+            j.id, j.N, j.w, j.op, j.n, j.in0, j.in1, j.out = i, mods[i], w, op, n, in0, in1, out
+
+    def elements(self) -> int:
+        return int(self.lens.sum())
+
+    def inputs_of(self, i):
+        """Host copies of job i's operands (for checking)."""
+        w = 64 if self.wide[i] else 32
+        n, o = int(self.lens[i]), int(self.offs[i])
+        x = self.pool[w][0].numpy()[o:o + n].copy()
+        if self.ops[i] == 0:
+            return x, self.pool[w][1].numpy()[o:o + n].copy()
+        return x, self.exps.numpy()[o:o + n].copy()
+
+
+def replay(server: "_lib.Server", stream: JobStream, arrivals: np.ndarray, poll_ms=20, timeout_s=600.0):
+    """Submits the stream at the given arrival times; returns completions (id order)."""
+    done = []
+    res = {}
+
+    def feeder():
+        try:
+            res["accepted"] = server.submit_timed(stream.jobs, arrivals)
+        except Exception as e:  # reported below
+            res["error"] = e
+
+    th = threading.Thread(target=feeder)
+    t0 = server.now()
+    th.start()
+    while True:
+        done.extend(server.poll(8192, poll_ms))
+        if "error" in res:
+            break
+        if not th.is_alive() and len(done) >= res.get("accepted", stream.njobs):
+            break
+        if server.now() - t0 > timeout_s:
+            raise TimeoutError("serving replay did not finish in %.0f s" % timeout_s)
+    th.join()
+    if "error" in res:
+        raise res["error"]
+    done.sort()
+    return done
+
+
+def summarize(done, nelems: int):
+    c = np.array([(d[2], d[3], d[4], d[5]) for d in done])
+    status = np.array([d[1] for d in done])
+    lat = (c[:, 3] - c[:, 0]) * 1e3
+    span = c[:, 3].max() - c[:, 0].min()
+    return {
+        "jobs": len(done),
+        "failed": int(np.count_nonzero(status)),
+        "p50_ms": round(float(np.percentile(lat, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "p999_ms": round(float(np.percentile(lat, 99.9)), 3),
+        "max_ms": round(float(lat.max()), 3),
+        "queue_p50_ms": round(float(np.percentile((c[:, 1] - c[:, 0]) * 1e3, 50)), 3),
+        "jobs_per_s": round(len(done) / span, 1),
+        "Gelem_per_s": round(nelems / span / 1e9, 3),
+        "span_s": round(float(span), 3),
+    }
