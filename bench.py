@@ -44,7 +44,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--sections", default=None,
                    help="comma list of secondary measurements to run (default: all unless --quick): "
-                        "copy,r32,r16,pow,ragged,serving")
+                        "copy,r32,const,crt,ntt,r16,pow,ragged,serving")
     p.add_argument("--ragged-segments", type=int, default=4096)
     p.add_argument("--serve-jobs", type=int, default=100_000)
     return p.parse_args()
@@ -207,7 +207,7 @@ def copy_ceiling(torch):
     return {"torch_copy_GBs": copy, "ref_2r1w_GBs": ref}
 
 
-SECTIONS = ("copy", "r32", "r16", "pow", "ragged", "serving")
+SECTIONS = ("copy", "r32", "const", "crt", "ntt", "r16", "pow", "ragged", "serving")
 
 
 def secondary(torch, mg, inp, args, sections):
@@ -234,6 +234,57 @@ def secondary(torch, mg, inp, args, sections):
                 log("r32 %s: %.1f Gmodmul/s" % (v, gms))
             del a, b, o
         ex["r32_mul"] = r32
+
+    if "const" in sections:
+        # product by a fixed operand (precomputed b N^-1): 32-bit workload, one read + one write per product
+        w2 = inp.R32Workload()
+        c32 = mg.setup(w2.N, 32)
+        cst = {}
+        for signed in (False, True):
+            ah, _ = w2.operands(signed)
+            a = torch.from_numpy(ah).to(dev)
+            o = torch.empty_like(a)
+            b = int(ah[12345])
+            for v in (["signed", "signed_plantard"] if signed else ["classic", "plantard"]):
+                _, ms = timed(lambda: mg.mul_const(c32, a, b, out=o, variant=v), torch, 20, 5)
+                gms = w2.n / (ms * 1e-3) / 1e9
+                cst[v] = {"Gmodmul_s": round(gms, 1), "GB_s": round(8 * gms, 1),
+                          "frac_hbm": round(8 * gms / HBM_PEAK_GBS, 4)}
+                log("r32 const %s: %.1f Gmodmul/s" % (v, gms))
+            del a, o
+        ex["r32_mul_const"] = cst
+
+    if "crt" in sections:
+        # integers from the 64-bit RNS rows: 2^25 elements of 8 residues -> 8-word integers
+        wl = inp.RNS64Workload()
+        ah, _ = wl.operands()
+        r = torch.from_numpy(ah).to(dev)
+        ctxs = [mg.setup(N, 64) for N in wl.moduli]
+        o = torch.empty((wl.n, wl.k), dtype=torch.uint64, device=dev)
+        _, ms = timed(lambda: mg.crt(ctxs, r, out=o), torch, 10, 2)
+        ex["crt"] = {"k": wl.k, "elements": wl.n, "ms": round(ms, 3),
+                     "Gelem_s": round(wl.n / (ms * 1e-3) / 1e9, 3),
+                     "GB_s": round(2 * 8 * wl.k * wl.n / (ms * 1e-3) / 1e9, 1)}
+        log("crt: %s" % ex["crt"])
+        del r, o
+
+    if "ntt" in sections:
+        # 2^18 transforms of length 256 over N = 8380417 (2^26 coefficients, the 32-bit workload's size)
+        N, log2n, batch = 8380417, 8, 1 << 18
+        n = 1 << log2n
+        c32 = mg.setup(N, 32)
+        root = next(w for w in (pow(g, (N - 1) // n, N) for g in range(2, 100)) if pow(w, n // 2, N) == N - 1)
+        d = torch.from_numpy(inp.uniform_residues(inp.rng(inp.W_R32, 9), N, batch * n, np.uint32)).to(dev)
+        d = d.view(batch, n)
+        res = {"N": N, "n": n, "batch": batch}
+        for v in ("classic", "plantard"):
+            _, ms = timed(lambda: mg.ntt(c32, d, root, variant=v), torch, 10, 2)
+            res[v] = {"ms": round(ms, 3), "Gcoef_s": round(batch * n / (ms * 1e-3) / 1e9, 1),
+                      "Gbutterfly_s": round(batch * n // 2 * log2n / (ms * 1e-3) / 1e9, 1),
+                      "GB_s": round(8 * batch * n / (ms * 1e-3) / 1e9, 1)}
+            log("ntt %s: %s" % (v, res[v]))
+        ex["ntt"] = res
+        del d
 
     if "r16" in sections:
         # 16-bit workload: N = 3329, 2^20 residues + the exhaustive REDC sweep

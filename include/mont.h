@@ -135,6 +135,18 @@ mont_status_t mont_mul(const mont_ctx_t *ctx, const void *a, const void *b, void
                        mont_variant_t variant, void *stream);
 
 /*
+ * mont_mul_const -- out[i] = REDC_variant(a[i] * b) for one fixed operand b
+ * (a w-bit residue; two's complement for the signed variants), bit-identical
+ * to mont_mul with b broadcast.  The quotient digit m = T N^{-1} is formed as
+ * a (b N^{-1}) from a constant precomputed on the host, so the Plantard forms
+ * never form the product a b: the saving Section 3.2 credits to Plantard's
+ * algorithm (a 2w x w multiplication becomes w x w).  MONT_E_DOMAIN when b is
+ * outside [0, N) (unsigned variants) or |b| >= N (signed variants).
+ */
+mont_status_t mont_mul_const(const mont_ctx_t *ctx, const void *a, uint64_t b, void *out, size_t n,
+                             mont_variant_t variant, void *stream);
+
+/*
  * mont_mul_rns -- the Montgomery product over k residue rows ("limbs"), row
  * j reduced with ctxs[j] (all of one word size w).  a, b, out are limb-major
  * [k][ld] arrays; the first n entries of each row are processed.
@@ -143,6 +155,37 @@ mont_status_t mont_mul(const mont_ctx_t *ctx, const void *a, const void *b, void
 #define MONT_RNS_MAX 32
 mont_status_t mont_mul_rns(const mont_ctx_t *ctxs, uint32_t k, const void *a, const void *b, void *out, size_t n,
                            size_t ld, mont_variant_t variant, void *stream);
+
+/*
+ * mont_crt -- integer reconstruction from residue rows: for pairwise coprime
+ * odd moduli N_j = ctxs[j].N (64-bit word contexts, 1 <= k <= 16) and
+ * residues x[j][i] in [0, N_j) (limb-major [k][ld], uint64), writes the
+ * unique X_i in [0, N_0 ... N_{k-1}) with X_i = x[j][i] (mod N_j) as k
+ * little-endian uint64 words at out[i*k .. i*k + k) (out 16-byte aligned).
+ * The multi-modulus Chinese Remainder Theorem (Section 2 derives the two-
+ * modulus case from Theorem 2.1), computed by Garner's mixed-radix
+ * conversion with Montgomery products.  MONT_E_DOMAIN if two moduli share a
+ * factor; MONT_E_UNSUPPORTED for contexts that are not 64-bit.
+ */
+#define MONT_CRT_MAX 16
+mont_status_t mont_crt(const mont_ctx_t *ctxs, uint32_t k, const void *res, size_t n, size_t ld, void *out,
+                       void *stream);
+
+/*
+ * mont_ntt -- in-place number-theoretic transforms of `batch` polynomials of
+ * n = 2^log2n residues in [0, N) (1 <= log2n <= 12), stored contiguously,
+ * natural order in and out:
+ *   forward  X_k = sum_j x_j root^(j k) mod N,
+ *   inverse  x_j = n^{-1} sum_k X_k root^(-j k) mod N   (inverse != 0),
+ * for a root with root^(n/2) = -1 (mod N) (else MONT_E_DOMAIN).  The
+ * butterflies multiply by twiddles with the classic Montgomery product
+ * (MONT_CLASSIC) or with Plantard's product by a fixed operand
+ * (MONT_PLANTARD, Section 3.2); other variants return MONT_E_UNSUPPORTED.
+ * Twiddle tables are built once per (N, root, n, variant, direction) and
+ * kept in library-owned device memory for the life of the process.
+ */
+mont_status_t mont_ntt(const mont_ctx_t *ctx, void *data, size_t batch, uint32_t log2n, uint64_t root, int inverse,
+                       mont_variant_t variant, void *stream);
 
 /*
  * mont_pow -- out[i] = x[i]^e[i] mod N for residues x[i] in [0, N) and

@@ -73,6 +73,8 @@ def _load():
         lib.orc_redc_i64.argtypes = [i32, u32, u32, u64, vp, vp, sz]
         lib.orc_pow.argtypes = [u32, u64, vp, vp, vp, sz]
         lib.orc_mulmod.argtypes = [u32, u64, vp, vp, vp, sz]
+        lib.orc_dft.argtypes = [u32, u64, vp, u64, u32, i32, vp]
+        lib.orc_dft.restype = i32
         lib.orc_inv_mod.argtypes = [u64, u64]
         lib.orc_inv_mod.restype = u64
         lib.orc_last_bad_index.restype = ctypes.c_int64
@@ -152,6 +154,18 @@ def mulmod(w: int, N: int, a: np.ndarray, b: np.ndarray) -> np.ndarray:
     b = np.ascontiguousarray(b)
     out = np.empty_like(a)
     _check(_load().orc_mulmod(w, N, _ptr(a), _ptr(b), _ptr(out), a.shape[0]), "mulmod")
+    return out
+
+
+def dft(w: int, N: int, x: np.ndarray, root: int, inverse: bool = False) -> np.ndarray:
+    """Transform of one vector by the definition: X_k = sum_j x_j root^(j k) mod N (forward), or
+    x_j = n^{-1} sum_k X_k root^(-j k) mod N (inverse); len(x) a power of two."""
+    x = np.ascontiguousarray(x)
+    n = x.shape[0]
+    log2n = n.bit_length() - 1
+    assert 1 << log2n == n
+    out = np.empty_like(x)
+    _check(_load().orc_dft(w, N, _ptr(x), root, log2n, 1 if inverse else 0, _ptr(out)), "dft")
     return out
 
 
@@ -235,3 +249,20 @@ def sigpredc2_steps(T: int, N: int, n: int, alpha: int) -> dict:
     return {"R": R, "ninv_mods": ninv_t, "m": m, "r": r, "exact": exact,
             "mN_minus_T_over_2n": (m * N - T) >> n,
             "q_alpha0_times_N": ((m >> n) + 1) * N}
+
+
+def crt(residues, moduli):
+    """The integers X in [0, prod N_j) with X = r_j (mod N_j), from the CRT formula
+    X = sum_j r_j M_j (M_j^{-1} mod N_j) mod M, M = prod N_j, M_j = M / N_j
+    (for two moduli this is eq. (qin1): T = r1 R^{-1} R + r2 N^{-1} N mod NR).
+    residues: k sequences of equal length (Python ints); returns a list."""
+    M = 1
+    for N in moduli:
+        M *= N
+    coef = []
+    for N in moduli:
+        Mj = M // N
+        coef.append(Mj * _egcd_inverse(Mj % N, N))
+    k = len(moduli)
+    n = len(residues[0])
+    return [sum(int(residues[j][i]) * coef[j] for j in range(k)) % M for i in range(n)]

@@ -44,6 +44,7 @@
  */
 #include <stddef.h>
 #include <stdint.h>
+#include <stdlib.h>
 
 typedef __int128 i128;
 typedef unsigned __int128 u128;
@@ -415,5 +416,50 @@ int orc_mulmod(unsigned cw, uint64_t N, const void *a, const void *b, void *out,
         u128 p = (u128)(uint64_t)load_elem(a, i, cw, 0) * (uint64_t)load_elem(b, i, cw, 0);
         store_elem(out, i, cw, (uint64_t)(p % N));
     }
+    return ORC_OK;
+}
+
+/*
+ * Discrete Fourier transform over Z_N by its definition (O(n^2)):
+ * forward X_k = sum_j x_j w^(j k) mod N; inverse x_j = n^{-1} sum_k X_k w^(-j k)
+ * mod N with w^{-1} = w^(n-1) when w^n = 1.  x and out are n residues of
+ * container width cw (unsigned).  Returns ORC_EARG when n^{-1} or w^{-1}
+ * does not exist.
+ */
+int orc_dft(unsigned cw, uint64_t N, const void *x, uint64_t w, unsigned log2n, int inverse, void *out)
+{
+    if ((cw != 16 && cw != 32 && cw != 64) || N < 3 || log2n > 20)
+        return ORC_EARG;
+    const uint64_t n = 1ull << log2n;
+    uint64_t wi = w % N;
+    if (inverse) {
+        wi = orc_inv_mod(wi, N);
+        if (!wi)
+            return ORC_EARG;
+    }
+    /* powers w^m for m < n */
+    uint64_t *powers = (uint64_t *)malloc(n * sizeof(uint64_t));
+    if (!powers)
+        return ORC_EARG;
+    powers[0] = 1 % N;
+    for (uint64_t m = 1; m < n; ++m)
+        powers[m] = (uint64_t)(((u128)powers[m - 1] * wi) % N);
+    uint64_t ninv = 1;
+    if (inverse) {
+        ninv = orc_inv_mod(n % N, N);
+        if (!ninv) {
+            free(powers);
+            return ORC_EARG;
+        }
+    }
+    for (uint64_t k = 0; k < n; ++k) {
+        u128 acc = 0;
+        for (uint64_t j = 0; j < n; ++j) {
+            const uint64_t xj = (uint64_t)load_elem(x, j, cw, 0);
+            acc = (acc + (u128)xj * powers[(j * k) & (n - 1)]) % N;
+        }
+        store_elem(out, k, cw, (uint64_t)((acc * ninv) % N));
+    }
+    free(powers);
     return ORC_OK;
 }

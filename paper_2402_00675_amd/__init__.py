@@ -7,7 +7,10 @@ Operations (all in HIP kernels of libmont.so, called through its C ABI):
                                   Plantard (Algorithm 2), signed Plantard
                                   (Algorithm 3), Huang's variant with alpha >= 1
                                   (Algorithm 4), at 16/32/64-bit words
+* ``mul_const``                   the product by one fixed operand (precomputed b N^{-1})
 * ``mul_rns``                     the product over residue-number-system rows
+* ``crt``                         integers from residue rows (multi-modulus CRT)
+* ``ntt``                         batched number-theoretic transforms (Montgomery or Plantard twiddles)
 * ``pow``                         x^e mod N through the Montgomery representation
 * ``redc_range``                  REDC over a generated range of T
 * ``Batch``                       ragged batches in one persistent launch
@@ -16,5 +19,5 @@ Operations (all in HIP kernels of libmont.so, called through its C ABI):
 from ._lib import (  # noqa: F401
     BATCH_DYNAMIC, BATCH_GRAPH, BATCH_TUNE, CLASSIC, OP_MUL, OP_POW, OP_REDC, PLANTARD, SIGNED,
     SIGNED_PLANTARD, SIGNED_PLANTARD_ALPHA, VARIANTS, Batch, Ctx, MontError, elem_dtype, get_launch,
-    Server, header_functions, load, mul, mul_rns, pools, pow, redc, redc_range, set_launch, setup, stream_ref, tune_mul,
+    Server, crt, header_functions, load, mul, mul_const, mul_rns, ntt, pools, pow, redc, redc_range, set_launch, setup, stream_ref, tune_mul,
 )

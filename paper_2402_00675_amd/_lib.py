@@ -79,6 +79,9 @@ def load():
         "mont_redc": (i32, [P(CtxStruct), vp, vp, sz, i32, vp]),
         "mont_mul": (i32, [P(CtxStruct), vp, vp, vp, sz, i32, vp]),
         "mont_mul_rns": (i32, [P(CtxStruct), u32, vp, vp, vp, sz, sz, i32, vp]),
+        "mont_mul_const": (i32, [P(CtxStruct), vp, u64, vp, sz, i32, vp]),
+        "mont_crt": (i32, [P(CtxStruct), u32, vp, sz, sz, vp, vp]),
+        "mont_ntt": (i32, [P(CtxStruct), vp, sz, u32, u64, i32, i32, vp]),
         "mont_pow": (i32, [P(CtxStruct), vp, vp, vp, sz, vp]),
         "mont_redc_range": (i32, [P(CtxStruct), u64, vp, sz, i32, vp]),
         "mont_batch_create": (i32, [P(CtxStruct), u32, P(SegStruct), u32, u32, P(vp), vp]),
@@ -201,6 +204,17 @@ def mul(ctx: Ctx, a, b, out=None, variant="classic", stream=None):
     return out
 
 
+def mul_const(ctx: Ctx, a, b: int, out=None, variant="classic", stream=None):
+    """out[i] = REDC(a[i] * b) for a fixed operand b (a Python int, negative allowed for signed variants)."""
+    n = a.numel()
+    eb = _ELEM_BYTES[ctx.w]
+    if out is None:
+        out = _torch().empty(n, dtype=elem_dtype(ctx.w, variant), device=a.device)
+    check(load().mont_mul_const(ctypes.byref(ctx.s), _dev(a, "a", eb, n), b & (2**64 - 1),
+                                _dev(out, "out", eb, n), n, variant_id(variant), _stream(stream)))
+    return out
+
+
 def redc(ctx: Ctx, T, n: int | None = None, out=None, variant="classic", stream=None):
     eb = _ELEM_BYTES[ctx.w]
     if n is None:
@@ -222,6 +236,28 @@ def mul_rns(ctxs, a, b, out=None, n: int | None = None, variant="classic", strea
     check(load().mont_mul_rns(arr, k, _dev(a, "a", eb, k * ld), _dev(b, "b", eb, k * ld),
                               _dev(out, "out", eb, k * ld), n, ld, variant_id(variant), _stream(stream)))
     return out
+
+
+def crt(ctxs, res, out=None, n: int | None = None, stream=None):
+    """Integers X (k little-endian uint64 words each) from residue rows res[k][ld]."""
+    k, ld = res.shape
+    n = ld if n is None else n
+    arr = (CtxStruct * k)(*[c.s for c in ctxs])
+    if out is None:
+        out = _torch().empty((n, k), dtype=_torch().uint64, device=res.device)
+    check(load().mont_crt(arr, k, _dev(res, "res", 8, k * ld), n, ld, _dev(out, "out", 8 * k, n), _stream(stream)))
+    return out
+
+
+def ntt(ctx: Ctx, data, root: int, inverse=False, variant="classic", stream=None):
+    """In-place transform of every row of data [batch][n] (n a power of two, <= 4096)."""
+    batch, n = data.shape
+    log2n = n.bit_length() - 1
+    if 1 << log2n != n:
+        raise ValueError("row length must be a power of two")
+    check(load().mont_ntt(ctypes.byref(ctx.s), _dev(data, "data", _ELEM_BYTES[ctx.w], batch * n), batch, log2n,
+                          root, 1 if inverse else 0, variant_id(variant), _stream(stream)))
+    return data
 
 
 def pow(ctx: Ctx, x, e, out=None, stream=None):  # noqa: A001

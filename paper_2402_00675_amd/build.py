@@ -26,6 +26,8 @@ SOURCES = [
     "mont_k64.hip",
     "mont_ragged.hip",
     "mont_ref.hip",
+    "mont_crt.hip",
+    "mont_ntt.hip",
     "mont_capi.cpp",
     "mont_setup.cpp",
     "mont_serve.cpp",

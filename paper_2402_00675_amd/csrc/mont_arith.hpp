@@ -56,6 +56,17 @@ struct KCtx {
     uint32_t w;
 };
 
+// Precomputed constants of a product by a fixed operand b (mont_mul_const).
+// classic: b1 = b N' mod 2^w; signed: b1 = b N^{-1} mod 2^w; Plantard family:
+// (b1, b2) = b N^{-1} mod 2^(2w) as (low, high) 64-bit words, b taken as a
+// 2w-bit two's complement for the signed forms.  With them the quotient
+// digit m = T N^{-1} mod R = a (b N^{-1}) mod R is formed from a alone.
+struct KConst {
+    uint64_t b;
+    uint64_t b1;
+    uint64_t b2;
+};
+
 struct u128v {
     uint64_t lo, hi;
 };
@@ -128,6 +139,13 @@ struct Red<16, CLASSIC> {
     }
     __device__ __forceinline__ E mul(E a, E b) const { return redc((uint32_t)a * (uint32_t)b); }
     __device__ __forceinline__ E sqr(E a) const { return mul(a, a); }
+    __device__ __forceinline__ E mul_const(E a, const KConst &k) const
+    {
+        const uint32_t T = (uint32_t)a * (uint32_t)k.b;
+        const uint32_t m = ((uint32_t)a * (uint32_t)k.b1) & 0xffffu;   // (T mod R) N' mod R
+        const uint32_t t = (T >> 16) + ((m * N) >> 16) + ((T & 0xffffu) != 0u);
+        return (E)(t >= N ? t - N : t);
+    }
 };
 
 template <>
@@ -146,6 +164,12 @@ struct Red<16, SIGNED> {
         return (E)(a1 - t);
     }
     __device__ __forceinline__ E mul(E a, E b) const { return redc((int32_t)a * (int32_t)b); }
+    __device__ __forceinline__ E mul_const(E a, const KConst &k) const
+    {
+        const int32_t T = (int32_t)a * (int32_t)(int16_t)k.b;
+        const int32_t m0 = (int32_t)(int16_t)(uint16_t)((uint32_t)(int32_t)a * (uint32_t)k.b1);
+        return (E)((T >> 16) - ((m0 * N) >> 16));
+    }
 };
 
 template <>
@@ -161,6 +185,11 @@ struct Red<16, PLANTARD> {
         return (E)((q * N) >> 16);
     }
     __device__ __forceinline__ E mul(E a, E b) const { return redc((uint32_t)a * (uint32_t)b); }
+    __device__ __forceinline__ E mul_const(E a, const KConst &k) const
+    {
+        const uint32_t m = (uint32_t)a * (uint32_t)k.b1;   // a (b N^{-1}) mod 2^32: no product a b
+        return (E)((((m >> 16) + 1u) * N) >> 16);
+    }
 };
 
 template <>
@@ -178,6 +207,13 @@ struct Red<16, SIGNED_PLANTARD> {
         return (E)((p >> 16) + ((p >> 15) & 1));              // round(q N / 2^16)
     }
     __device__ __forceinline__ E mul(E a, E b) const { return redc((int32_t)a * (int32_t)b); }
+    __device__ __forceinline__ E mul_const(E a, const KConst &k) const
+    {
+        const int32_t m = (int32_t)((uint32_t)(int32_t)a * (uint32_t)k.b1);
+        const int32_t q = (m >> 16) + ((m >> 15) & 1);
+        const int32_t p = q * N;
+        return (E)((p >> 16) + ((p >> 15) & 1));
+    }
 };
 
 template <>
@@ -195,6 +231,11 @@ struct Red<16, SIGNED_PLANTARD_ALPHA> {
         return (E)(p >> 16);
     }
     __device__ __forceinline__ E mul(E a, E b) const { return redc((int32_t)a * (int32_t)b); }
+    __device__ __forceinline__ E mul_const(E a, const KConst &k) const
+    {
+        const int32_t m = (int32_t)((uint32_t)(int32_t)a * (uint32_t)k.b1);
+        return (E)(((m >> 16) * N + (N << alpha)) >> 16);
+    }
 };
 
 // ---------------------------------------------------------- w = 32
@@ -214,6 +255,14 @@ struct Red<32, CLASSIC> {
     }
     __device__ __forceinline__ E mul(E a, E b) const { return redc((uint64_t)a * b); }
     __device__ __forceinline__ E sqr(E a) const { return mul(a, a); }
+    __device__ __forceinline__ E mul_const(E a, const KConst &k) const
+    {
+        const uint64_t T = (uint64_t)a * (uint32_t)k.b;
+        const uint32_t tl = (uint32_t)T, th = (uint32_t)(T >> 32);
+        const uint32_t m = a * (uint32_t)k.b1;
+        const uint64_t t = (uint64_t)th + __umulhi(m, N) + (tl != 0u);
+        return t >= N ? (uint32_t)(t - N) : (uint32_t)t;
+    }
 };
 
 template <>
@@ -231,6 +280,12 @@ struct Red<32, SIGNED> {
         return a1 - __mulhi(m0, N);
     }
     __device__ __forceinline__ E mul(E a, E b) const { return redc((int64_t)a * b); }
+    __device__ __forceinline__ E mul_const(E a, const KConst &k) const
+    {
+        const int64_t T = (int64_t)a * (int32_t)(uint32_t)k.b;
+        const int32_t m0 = (int32_t)((uint32_t)a * (uint32_t)k.b1);
+        return (int32_t)(T >> 32) - __mulhi(m0, N);
+    }
 };
 
 template <>
@@ -247,6 +302,12 @@ struct Red<32, PLANTARD> {
         return __umulhi(mh + 1u, N);
     }
     __device__ __forceinline__ E mul(E a, E b) const { return redc((uint64_t)a * b); }
+    __device__ __forceinline__ E mul_const(E a, const KConst &k) const
+    {
+        const uint32_t bl = (uint32_t)k.b1, bh = (uint32_t)(k.b1 >> 32);
+        const uint32_t mh = __umulhi(a, bl) + a * bh;   // floor((a (b N^{-1}) mod 2^64) / 2^32)
+        return __umulhi(mh + 1u, N);
+    }
 };
 
 template <>
@@ -267,6 +328,13 @@ struct Red<32, SIGNED_PLANTARD> {
         return (int32_t)(p >> 32) + (int32_t)((uint32_t)p >> 31);   // round(q N / 2^32)
     }
     __device__ __forceinline__ E mul(E a, E b) const { return redc((int64_t)a * b); }
+    __device__ __forceinline__ E mul_const(E a, const KConst &k) const
+    {
+        const uint64_t m = (uint64_t)(int64_t)a * k.b1;  // a (b N^{-1}) mod 2^64, two's complement
+        const int32_t q = (int32_t)(uint32_t)(m >> 32) + (int32_t)((uint32_t)m >> 31);
+        const int64_t p = (int64_t)q * N;
+        return (int32_t)(p >> 32) + (int32_t)((uint32_t)p >> 31);
+    }
 };
 
 template <>
@@ -285,6 +353,12 @@ struct Red<32, SIGNED_PLANTARD_ALPHA> {
         return (int32_t)(p >> 32);
     }
     __device__ __forceinline__ E mul(E a, E b) const { return redc((int64_t)a * b); }
+    __device__ __forceinline__ E mul_const(E a, const KConst &k) const
+    {
+        const uint64_t m = (uint64_t)(int64_t)a * k.b1;
+        const int64_t p = (int64_t)(int32_t)(uint32_t)(m >> 32) * N + ((int64_t)N << alpha);
+        return (int32_t)(p >> 32);
+    }
 };
 
 // ---------------------------------------------------------- w = 64
@@ -337,6 +411,15 @@ struct Red<64, CLASSIC> {
         const u128v p = sqr_64(a);
         return reduce_lazy(p.lo, p.hi);
     }
+    __device__ __forceinline__ E mul_const(E a, const KConst &k) const
+    {
+        const u128v p = mul_64x64(a, k.b);
+        const uint64_t m = a * k.b1;
+        const uint64_t s = p.hi + mulhi_64(m, N);
+        const uint64_t t = s + (p.lo != 0u);
+        const bool carry = (s < p.hi) | (t < s);
+        return (carry | (t >= N)) ? t - N : t;
+    }
 };
 
 template <>
@@ -357,6 +440,12 @@ struct Red<64, SIGNED> {
         const u128v p = mul_s64(a, b);
         return reduce(p.lo, p.hi);
     }
+    __device__ __forceinline__ E mul_const(E a, const KConst &k) const
+    {
+        const u128v p = mul_s64(a, (int64_t)k.b);
+        const int64_t m0 = (int64_t)((uint64_t)a * k.b1);
+        return (int64_t)(p.hi - mul_s64_u63(m0, N).hi);
+    }
 };
 
 template <>
@@ -375,6 +464,11 @@ struct Red<64, PLANTARD> {
     {
         const u128v p = mul_64x64(a, b);
         return reduce(p.lo, p.hi);
+    }
+    __device__ __forceinline__ E mul_const(E a, const KConst &k) const
+    {
+        const uint64_t mh = mulhi_64(a, k.b1) + a * k.b2;   // floor((a (b N^{-1}) mod 2^128) / 2^64)
+        return mulhi_64(mh + 1u, N);
     }
 };
 
@@ -397,6 +491,15 @@ struct Red<64, SIGNED_PLANTARD> {
     {
         const u128v p = mul_s64(a, b);
         return reduce(p.lo, p.hi);
+    }
+    // a as a 128-bit two's complement: (a_lo, a < 0 ? 2^64 - 1 : 0)
+    __device__ __forceinline__ E mul_const(E a, const KConst &k) const
+    {
+        const u128v ml = mul_64x64((uint64_t)a, k.b1);
+        const uint64_t mh = ml.hi + (uint64_t)a * k.b2 - (a < 0 ? k.b1 : 0);
+        const int64_t q = (int64_t)mh + (int64_t)(ml.lo >> 63);
+        const u128v p = mul_s64_u63(q, N);
+        return (int64_t)(p.hi + (p.lo >> 63));
     }
 };
 
@@ -421,6 +524,15 @@ struct Red<64, SIGNED_PLANTARD_ALPHA> {
     {
         const u128v p = mul_s64(a, b);
         return reduce(p.lo, p.hi);
+    }
+    __device__ __forceinline__ E mul_const(E a, const KConst &k) const
+    {
+        const uint64_t mh = mulhi_64((uint64_t)a, k.b1) + (uint64_t)a * k.b2 - (a < 0 ? k.b1 : 0);
+        u128v p = mul_s64_u63((int64_t)mh, N);
+        const uint64_t add = N << alpha;
+        const uint64_t lo = p.lo + add;
+        p.hi += (lo < add);
+        return (int64_t)p.hi;
     }
 };
 

@@ -155,7 +155,8 @@ mont_status_t mont_set_alpha(mont_ctx_t *ctx, uint32_t alpha)
 }
 
 static mont_status_t run_map(int op, const mont_ctx_t *ctxs, uint32_t rows, const void *in0, const void *in1,
-                             void *out, size_t n, size_t ld, mont_variant_t variant, void *stream)
+                             void *out, size_t n, size_t ld, mont_variant_t variant, void *stream,
+                             const KConst *kc = nullptr)
 {
     for (uint32_t r = 0; r < rows; ++r) {
         mont_status_t rc = check_ctx(&ctxs[r]);
@@ -171,6 +172,7 @@ static mont_status_t run_map(int op, const mont_ctx_t *ctxs, uint32_t rows, cons
         return MONT_OK;
     if (!in0 || !out || (op == 0 && !in1))
         return fail(MONT_E_INVAL, "null data pointer");
+    const int op_launch = op == 2 ? 0 : op;  // the fixed-operand product shares the product's launch shape
     KCtx k[MAX_ROWS];
     for (uint32_t r = 0; r < rows; ++r)
         k[r] = to_kctx(ctxs[r]);
@@ -184,12 +186,14 @@ static mont_status_t run_map(int op, const mont_ctx_t *ctxs, uint32_t rows, cons
     a.out = out;
     a.n = n;
     a.ld = ld;
+    if (kc)
+        a.kc = *kc;
     const int wc = width_class(ctxs[0].w);
-    const Launch L = get_launch(op, wc, variant);
+    const Launch L = get_launch(op_launch, wc, variant);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = wc == 0 ? launch_map<16>(a, L, s) : wc == 1 ? launch_map<32>(a, L, s) : launch_map<64>(a, L, s);
     if (e != hipSuccess)
-        return hip_fail(e, op == 0 ? "mont_mul launch" : "mont_redc launch");
+        return hip_fail(e, op == 1 ? "mont_redc launch" : "mont_mul launch");
     return MONT_OK;
 }
 
@@ -203,6 +207,48 @@ mont_status_t mont_mul(const mont_ctx_t *ctx, const void *a, const void *b, void
                        mont_variant_t variant, void *stream)
 {
     return run_map(0, ctx, 1, a, b, out, n, n, variant, stream);
+}
+
+mont_status_t mont_mul_const(const mont_ctx_t *ctx, const void *a, uint64_t b, void *out, size_t n,
+                             mont_variant_t variant, void *stream)
+{
+    mont_status_t rc = check_ctx(ctx);
+    if (rc)
+        return rc;
+    rc = check_variant(ctx, variant);
+    if (rc)
+        return rc;
+    typedef unsigned __int128 u128;
+    const uint32_t w = ctx->w;
+    const u128 one = 1;
+    const uint64_t maskw = w == 64 ? ~0ull : (1ull << w) - 1;
+    const bool sgn = variant == MONT_SIGNED || variant == MONT_SIGNED_PLANTARD || variant == MONT_SIGNED_PLANTARD_ALPHA;
+    // b as a w-bit value: [0, N) for the unsigned variants, |b| < N (two's complement) for the signed ones
+    const uint64_t bw = b & maskw;
+    int64_t bs = (int64_t)bw;
+    if (sgn && w < 64 && (bw >> (w - 1)))
+        bs = (int64_t)(bw | ~maskw);
+    if (sgn ? (bs < 0 ? (uint64_t)(-bs) : (uint64_t)bs) >= ctx->N : bw >= ctx->N)
+        return fail(MONT_E_DOMAIN, "fixed operand outside the variant's operand range");
+    KConst k;
+    k.b = sgn ? (uint64_t)bs : bw;
+    if (variant == MONT_CLASSIC) {
+        k.b1 = (uint64_t)(((u128)bw * ctx->nprime) & maskw);
+        k.b2 = 0;
+    } else if (variant == MONT_SIGNED) {
+        k.b1 = (uint64_t)(((u128)bw * ctx->ninv) & maskw);
+        k.b2 = 0;
+    } else {
+        // b' = b N^{-1} mod 2^(2w), b sign-extended to 2w bits for the signed forms
+        const u128 bx = sgn ? (u128)(__int128)bs : (u128)bw;
+        const u128 ninv2 = ((u128)ctx->ninv2_hi << 64) | ctx->ninv2_lo;
+        u128 bp = bx * ninv2;
+        if (w < 64)
+            bp &= (one << (2 * w)) - 1;
+        k.b1 = (uint64_t)bp;  // the whole 2w-bit value for w <= 32, its low word for w = 64
+        k.b2 = w == 64 ? (uint64_t)(bp >> 64) : 0;
+    }
+    return run_map(2, ctx, 1, a, nullptr, out, n, n, variant, stream, &k);
 }
 
 mont_status_t mont_mul_rns(const mont_ctx_t *ctxs, uint32_t k, const void *a, const void *b, void *out, size_t n,

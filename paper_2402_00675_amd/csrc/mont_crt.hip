@@ -1,0 +1,185 @@
+// Reconstruction of integers from residue-number-system rows (the
+// multi-modulus Chinese Remainder Theorem; Section 2 derives the two-modulus
+// case from Qin's identity and points to the general one).
+//
+// For pairwise coprime odd moduli N_0..N_{k-1} (64-bit words) and residues
+// x_i, the unique X in [0, N_0 ... N_{k-1}) with X = x_i (mod N_i) is formed by
+// Garner's mixed-radix conversion
+//     v_0 = x_0,  v_i = ((x_i - v_0) c_{0,i} - v_1) c_{1,i} ... - v_{i-1}) c_{i-1,i}  mod N_i,
+//     c_{j,i} = N_j^{-1} mod N_i,
+//     X = v_0 + N_0 (v_1 + N_1 (v_2 + ... + N_{k-2} v_{k-1})),
+// where every modular product is a Montgomery product against the constant
+// c_{j,i} R mod N_i: REDC(t (c R)) = t c (mod N_i).  A v_j that is not yet
+// reduced modulo N_i is multiplied the same way (v_j (cR) < R N_i is inside
+// REDC's range), so (t - v_j) c = REDC(t cR) - REDC(v_j cR) needs no separate
+// reduction; when every modulus is below twice every other one, a single
+// conditional subtraction reduces v_j instead (one product per step).
+// The mixed-radix digits are then folded into k little-endian 64-bit words by
+// Horner's rule with 64x64->128 multiply-adds.  Constants are kernel
+// arguments (read with scalar loads); residues are limb-major [k][ld], the
+// result element-major [n][k] words.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "mont_common.hpp"
+
+namespace mont {
+
+constexpr int CRT_MAX = 16;
+
+struct CrtTab {
+    uint64_t N[CRT_MAX];
+    uint64_t np[CRT_MAX];
+    uint64_t cbar[CRT_MAX][CRT_MAX];  // [j][i] = (N_j^{-1} mod N_i) R mod N_i, j < i
+};
+
+template <int K, bool NARROW>
+__global__ void __launch_bounds__(BLOCK)
+    k_crt(CrtTab tab, const uint64_t *__restrict__ res, uint64_t ld, uint64_t n, uint64_t *__restrict__ out)
+{
+    const uint64_t e = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    if (e >= n)
+        return;
+    uint64_t v[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        KCtx c{};
+        c.N = tab.N[i];
+        c.nprime = tab.np[i];
+        const Red<64, CLASSIC> red(c);
+        uint64_t t = __builtin_nontemporal_load(res + (uint64_t)i * ld + e);
+#pragma unroll
+        for (int j = 0; j < i; ++j) {
+            const uint64_t cb = tab.cbar[j][i];
+            if constexpr (NARROW) {
+                const uint64_t vj = v[j] >= c.N ? v[j] - c.N : v[j];
+                const uint64_t d = t >= vj ? t - vj : t + (c.N - vj);
+                t = red.mul(d, cb);
+            } else {
+                const uint64_t a = red.mul(t, cb);
+                const uint64_t b = red.mul(v[j], cb);
+                t = a >= b ? a - b : a + (c.N - b);
+            }
+        }
+        v[i] = t;
+    }
+    uint64_t acc[K];
+    acc[0] = v[K - 1];
+#pragma unroll
+    for (int w = 1; w < K; ++w)
+        acc[w] = 0;
+#pragma unroll
+    for (int i = K - 2; i >= 0; --i) {
+        const uint64_t Ni = tab.N[i];
+        uint64_t carry = v[i];
+        // acc holds K - 1 - i words; acc * N_i + v_i fills K - i words
+#pragma unroll
+        for (int w = 0; w < K - 1 - i; ++w) {
+            const u128v p = mul_64x64(acc[w], Ni);
+            const uint64_t lo = p.lo + carry;
+            carry = p.hi + (lo < carry);
+            acc[w] = lo;
+        }
+        acc[K - 1 - i] = carry;
+    }
+    uint64_t *o = out + e * K;
+    if constexpr (K % 2 == 0) {
+#pragma unroll
+        for (int w = 0; w < K; w += 2) {
+            u32x4 q;
+            q.x = (uint32_t)acc[w];
+            q.y = (uint32_t)(acc[w] >> 32);
+            q.z = (uint32_t)acc[w + 1];
+            q.w = (uint32_t)(acc[w + 1] >> 32);
+            __builtin_nontemporal_store(q, (u32x4 *)(o + w));
+        }
+    } else {
+#pragma unroll
+        for (int w = 0; w < K; ++w)
+            o[w] = acc[w];
+    }
+}
+
+template <int K>
+static void go_crt(const CrtTab &t, bool narrow, const uint64_t *res, uint64_t ld, uint64_t n, uint64_t *out,
+                   hipStream_t s)
+{
+    const unsigned grid = (unsigned)((n + BLOCK - 1) / BLOCK);
+    if (narrow)
+        hipLaunchKernelGGL((k_crt<K, true>), dim3(grid), dim3(BLOCK), 0, s, t, res, ld, n, out);
+    else
+        hipLaunchKernelGGL((k_crt<K, false>), dim3(grid), dim3(BLOCK), 0, s, t, res, ld, n, out);
+}
+
+typedef unsigned __int128 u128;
+
+// a^{-1} mod m (m odd, gcd 1) by the extended Euclidean algorithm; 0 if none.
+static uint64_t inv_mod(uint64_t a, uint64_t m)
+{
+    __int128 r0 = m, r1 = a % m, s0 = 0, s1 = 1;
+    while (r1) {
+        const __int128 q = r0 / r1, r2 = r0 - q * r1, s2 = s0 - q * s1;
+        r0 = r1;
+        r1 = r2;
+        s0 = s1;
+        s1 = s2;
+    }
+    if (r0 != 1)
+        return 0;
+    return (uint64_t)(s0 < 0 ? s0 + m : s0);
+}
+
+}  // namespace mont
+
+using namespace mont;
+
+extern "C" mont_status_t mont_crt(const mont_ctx_t *ctxs, uint32_t k, const void *res, size_t n, size_t ld,
+                                  void *out, void *stream)
+{
+    if (!ctxs || k < 1 || k > CRT_MAX)
+        return fail(MONT_E_INVAL, "need 1 <= k <= %d moduli", CRT_MAX);
+    for (uint32_t i = 0; i < k; ++i) {
+        mont_status_t rc = check_ctx(&ctxs[i]);
+        if (rc)
+            return rc;
+        if (ctxs[i].w != 64)
+            return fail(MONT_E_UNSUPPORTED, "mont_crt takes 64-bit word contexts");
+    }
+    if (n > ld)
+        return fail(MONT_E_INVAL, "n > ld");
+    CrtTab t{};
+    uint64_t lo = ~0ull, hi = 0;
+    for (uint32_t i = 0; i < k; ++i) {
+        t.N[i] = ctxs[i].N;
+        t.np[i] = ctxs[i].nprime;
+        lo = std::min(lo, ctxs[i].N);
+        hi = std::max(hi, ctxs[i].N);
+        for (uint32_t j = 0; j < i; ++j) {
+            const uint64_t c = inv_mod(ctxs[j].N % ctxs[i].N, ctxs[i].N);
+            if (!c)
+                return fail(MONT_E_DOMAIN, "moduli %u and %u are not coprime", j, i);
+            t.cbar[j][i] = (uint64_t)(((u128)c * ctxs[i].r_mod_n) % ctxs[i].N);  // c R mod N_i
+        }
+    }
+    if (n == 0)
+        return MONT_OK;
+    if (!res || !out || ((uintptr_t)out & 15u))
+        return fail(MONT_E_INVAL, "null residues or output not 16-byte aligned");
+    const bool narrow = (u128)hi < 2 * (u128)lo;  // every v_j < 2 N_i: one conditional subtraction reduces it
+    if ((n + BLOCK - 1) / BLOCK > 0x7fffffffull)
+        return fail(MONT_E_INVAL, "too many elements");
+    hipStream_t s = (hipStream_t)stream;
+    const uint64_t *r = (const uint64_t *)res;
+    uint64_t *o = (uint64_t *)out;
+    switch (k) {
+#define C(K)                                \
+    case K:                                 \
+        go_crt<K>(t, narrow, r, ld, n, o, s); \
+        break;
+        C(1) C(2) C(3) C(4) C(5) C(6) C(7) C(8) C(9) C(10) C(11) C(12) C(13) C(14) C(15) C(16)
+#undef C
+    }
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MONT_OK : hip_fail(e, "mont_crt launch");
+}

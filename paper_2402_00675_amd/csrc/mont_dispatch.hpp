@@ -18,13 +18,13 @@ hipError_t go_map(const MapArgs &a, dim3 grid, hipStream_t s)
         KTab<1> t;
         t.c[0] = a.ctx[0];
         hipLaunchKernelGGL((k_map<W, V, OP, E, U, NT, 1>), grid, dim3(BLOCK), 0, s, t, a.in0, a.in1, a.out, a.n,
-                           a.ld);
+                           a.ld, a.kc);
     } else if constexpr (OP == 0) {
         KTab<MAX_ROWS> t{};
         for (int r = 0; r < a.rows; ++r)
             t.c[r] = a.ctx[r];
         hipLaunchKernelGGL((k_map<W, V, OP, E, U, NT, MAX_ROWS>), grid, dim3(BLOCK), 0, s, t, a.in0, a.in1,
-                           a.out, a.n, a.ld);
+                           a.out, a.n, a.ld, a.kc);
     } else {
         return hipErrorInvalidValue;
     }
@@ -48,7 +48,7 @@ hipError_t launch_map_v(const MapArgs &a, const Launch &L, hipStream_t s)
     using R = Red<W, V>;
     using El = typename R::E;
     constexpr int E = 16 / (int)sizeof(El);
-    const bool vec = aligned16(a.in0) && (OP == 1 || aligned16(a.in1)) && aligned16(a.out) &&
+    const bool vec = aligned16(a.in0) && (OP != 0 || aligned16(a.in1)) && aligned16(a.out) &&
                      (a.rows == 1 || (a.ld * sizeof(El)) % 16 == 0);
     if (!vec) {
         dim3 grid((unsigned)grid_x(a.n, 1, a.rows, L), (unsigned)a.rows);
@@ -92,7 +92,8 @@ hipError_t launch_map_op(const MapArgs &a, const Launch &L, hipStream_t s)
 template <int W>
 hipError_t launch_map(const MapArgs &a, const Launch &L, hipStream_t s)
 {
-    return a.op == 0 ? launch_map_op<W, 0>(a, L, s) : launch_map_op<W, 1>(a, L, s);
+    return a.op == 0 ? launch_map_op<W, 0>(a, L, s) : a.op == 1 ? launch_map_op<W, 1>(a, L, s)
+                                                              : launch_map_op<W, 2>(a, L, s);
 }
 
 template <int W>

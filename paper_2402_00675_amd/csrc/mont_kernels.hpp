@@ -32,13 +32,14 @@ struct Launch {
 };
 
 struct MapArgs {
-    int op;        // 0 mul, 1 redc
+    int op;        // 0 mul, 1 redc, 2 mul by the fixed operand in kc
     int variant;
     int rows;      // >= 1
     const KCtx *ctx;  // rows entries (host)
     const void *in0, *in1;
     void *out;
     uint64_t n, ld;   // per row: n elements, row stride ld elements
+    KConst kc{};      // op 2 only
 };
 
 // ------------------------------------------------------------ memory helpers
@@ -125,11 +126,12 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t g)
     return (b % 8u) * (g / 8u) + b / 8u;
 }
 
-// out[i] = red.mul(a[i], b[i]) (OP 0) or red.redc(T[i]) (OP 1), per row.
+// out[i] = red.mul(a[i], b[i]) (OP 0), red.redc(T[i]) (OP 1) or
+// red.mul_const(a[i], kc) (OP 2), per row.
 template <int W, int V, int OP, int E, int U, bool NT, int NR>
 __global__ void __launch_bounds__(BLOCK)
     k_map(KTab<NR> tab, const void *__restrict__ in0, const void *__restrict__ in1, void *__restrict__ out,
-          uint64_t n, uint64_t ld)
+          uint64_t n, uint64_t ld, KConst kc)
 {
     using R = Red<W, V>;
     using El = typename R::E;
@@ -154,6 +156,8 @@ __global__ void __launch_bounds__(BLOCK)
                 if constexpr (OP == 0) {
                     load_chunk<El, E, NT>(pa + i * E, a[u]);
                     load_chunk<El, E, NT>(pb + i * E, b[u]);
+                } else if constexpr (OP == 2) {
+                    load_chunk<El, E, NT>(pa + i * E, a[u]);
                 } else {
                     load_chunk<TT, E, NT>(pt + i * E, t[u]);
                 }
@@ -168,6 +172,8 @@ __global__ void __launch_bounds__(BLOCK)
                 for (int e = 0; e < E; ++e) {
                     if constexpr (OP == 0)
                         o[e] = red.mul(a[u][e], b[u][e]);
+                    else if constexpr (OP == 2)
+                        o[e] = red.mul_const(a[u][e], kc);
                     else
                         o[e] = red.redc(t[u][e]);
                 }
@@ -182,6 +188,8 @@ __global__ void __launch_bounds__(BLOCK)
             if (i < n) {
                 if constexpr (OP == 0)
                     po[i] = red.mul(pa[i], pb[i]);
+                else if constexpr (OP == 2)
+                    po[i] = red.mul_const(pa[i], kc);
                 else
                     po[i] = red.redc(pt[i]);
             }

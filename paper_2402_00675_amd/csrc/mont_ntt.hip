@@ -1,0 +1,234 @@
+// Batched number-theoretic transforms whose butterflies use the library's
+// reductions (the application that motivates Montgomery-type algorithms in
+// Sections 1 and 3).
+//
+// Forward:  X_k = sum_j x_j w^(j k) mod N,  inverse: x_j = n^{-1} sum_k X_k w^(-j k) mod N,
+// for a root w with w^(n/2) = -1 (mod N), n = 2^log2n <= 4096, on `batch`
+// polynomials of n residues in [0, N) stored contiguously (natural order in
+// and out, in place).
+//
+// One workgroup transforms one polynomial: coefficients are loaded into LDS
+// in bit-reversed order, log2(n) radix-2 Cooley-Tukey stages run with a
+// barrier between stages (each lane owns n/2/blockDim butterflies per stage),
+// and the result is written back (scaled by n^{-1} for the inverse).  The
+// twiddle product is a product by a fixed operand:
+//   classic  -- Montgomery product with w^k R mod N;
+//   Plantard -- Plantard product with b = -w^k 2^(2w) mod N through the
+//               precomputed b N^{-1} mod 2^(2w) (mont_mul_const), so the
+//               product never forms a b (Section 3.2's operand saving).
+// Twiddles are computed once per (N, w, root, n, variant, direction) on the
+// host and kept in library-owned device memory.
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "mont_common.hpp"
+
+namespace mont {
+
+template <class R, int V>
+__device__ __forceinline__ typename R::E tw_mul(const R &red, typename R::E a, const KConst &w)
+{
+    if constexpr (V == CLASSIC)
+        return red.mul(a, (typename R::E)w.b);
+    else
+        return red.mul_const(a, w);
+}
+
+template <class El>
+__device__ __forceinline__ El add_mod(El u, El t, El N)
+{
+    const El s = u + t;
+    return (s < u || s >= N) ? (El)(s - N) : s;  // s < u: the sum wrapped (N > 2^(w-1))
+}
+
+template <class El>
+__device__ __forceinline__ El sub_mod(El u, El t, El N)
+{
+    return u >= t ? (El)(u - t) : (El)(u + (N - t));
+}
+
+template <int W, int V>
+__global__ void __launch_bounds__(BLOCK)
+    k_ntt(KCtx c, void *__restrict__ data, uint32_t log2n, const KConst *__restrict__ tw, KConst scale,
+          uint32_t do_scale)
+{
+    using R = Red<W, V>;
+    using El = typename R::E;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    El *s = (El *)lds_raw;
+    const R red(c);
+    const El N = (El)c.N;
+    const uint32_t n = 1u << log2n;
+    El *x = (El *)data + (uint64_t)blockIdx.x * n;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
+        s[__brev(i) >> (32 - log2n)] = x[i];
+    __syncthreads();
+    for (uint32_t lh = 0; lh < log2n; ++lh) {
+        const uint32_t len = 1u << lh;
+        for (uint32_t b = threadIdx.x; b < n / 2; b += blockDim.x) {
+            const uint32_t j = b & (len - 1);
+            const uint32_t i0 = ((b >> lh) << (lh + 1)) + j;
+            const uint32_t i1 = i0 + len;
+            const El t = tw_mul<R, V>(red, s[i1], tw[j << (log2n - 1 - lh)]);
+            const El u = s[i0];
+            s[i0] = add_mod<El>(u, t, N);
+            s[i1] = sub_mod<El>(u, t, N);
+        }
+        __syncthreads();
+    }
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
+        x[i] = do_scale ? tw_mul<R, V>(red, s[i], scale) : s[i];
+}
+
+typedef unsigned __int128 u128;
+
+static uint64_t mulmod(uint64_t a, uint64_t b, uint64_t N) { return (uint64_t)(((u128)a * b) % N); }
+
+static uint64_t powmod(uint64_t a, uint64_t e, uint64_t N)
+{
+    uint64_t r = 1 % N;
+    a %= N;
+    while (e) {
+        if (e & 1)
+            r = mulmod(r, a, N);
+        a = mulmod(a, a, N);
+        e >>= 1;
+    }
+    return r;
+}
+
+// The fixed-operand constants that make tw_mul(a, .) = a v mod N.
+static KConst twiddle_const(const mont_ctx_t &c, int variant, uint64_t v)
+{
+    KConst k{};
+    const uint32_t w = c.w;
+    if (variant == CLASSIC) {
+        k.b = mulmod(v, c.r_mod_n, c.N);  // v R mod N: REDC(a (v R)) = a v
+        return k;
+    }
+    // Plantard returns -a b 2^(-2w): take b = -v 2^(2w) mod N
+    const uint64_t r2w = c.r2_mod_n;  // 2^(2w) mod N
+    const uint64_t bv = mulmod(v, r2w, c.N);
+    const uint64_t b = bv ? c.N - bv : 0;
+    const u128 ninv2 = ((u128)c.ninv2_hi << 64) | c.ninv2_lo;
+    u128 bp = (u128)b * ninv2;
+    if (w < 64)
+        bp &= ((u128)1 << (2 * w)) - 1;
+    k.b = b;
+    k.b1 = (uint64_t)bp;
+    k.b2 = w == 64 ? (uint64_t)(bp >> 64) : 0;
+    return k;
+}
+
+struct TwKey {
+    uint64_t N, root;
+    uint32_t w, log2n;
+    int variant, inverse;
+    bool operator<(const TwKey &o) const
+    {
+        return std::tie(N, root, w, log2n, variant, inverse) < std::tie(o.N, o.root, o.w, o.log2n, o.variant, o.inverse);
+    }
+};
+
+struct TwEntry {
+    KConst *dev = nullptr;
+    KConst scale{};
+};
+
+static std::mutex g_tw_mu;
+static std::map<std::pair<int, TwKey>, TwEntry> g_tw;  // (device, key)
+
+static mont_status_t twiddles(const mont_ctx_t &c, int variant, uint64_t root, uint32_t log2n, int inverse,
+                              TwEntry *out)
+{
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const TwKey key{c.N, root, c.w, log2n, variant, inverse};
+    std::lock_guard<std::mutex> g(g_tw_mu);
+    auto it = g_tw.find({dev, key});
+    if (it != g_tw.end()) {
+        *out = it->second;
+        return MONT_OK;
+    }
+    const uint32_t n = 1u << log2n;
+    const uint64_t w = inverse ? powmod(root, n - 1, c.N) : root % c.N;  // root^{-1} = root^(n-1)
+    std::vector<KConst> h(n / 2);
+    uint64_t p = 1 % c.N;
+    for (uint32_t k = 0; k < n / 2; ++k) {
+        h[k] = twiddle_const(c, variant, p);
+        p = mulmod(p, w, c.N);
+    }
+    TwEntry e;
+    // n^{-1} mod N: N odd, so (N + 1)/2 is 2^{-1}
+    const uint64_t half = (uint64_t)(((u128)c.N + 1) / 2);
+    e.scale = twiddle_const(c, variant, powmod(half, log2n, c.N));
+    if (hipMalloc(&e.dev, h.size() * sizeof(KConst)) != hipSuccess)
+        return fail(MONT_E_NOMEM, "twiddle table");
+    const hipError_t err = hipMemcpy(e.dev, h.data(), h.size() * sizeof(KConst), hipMemcpyHostToDevice);
+    if (err != hipSuccess) {
+        (void)hipFree(e.dev);
+        return hip_fail(err, "twiddle upload");
+    }
+    g_tw[{dev, key}] = e;
+    *out = e;
+    return MONT_OK;
+}
+
+template <int W>
+static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, uint32_t log2n, const TwEntry &t,
+                         int inverse, hipStream_t s)
+{
+    using El = typename Red<W, CLASSIC>::E;
+    const uint32_t n = 1u << log2n;
+    const unsigned block = (unsigned)std::min<uint32_t>(BLOCK, std::max<uint32_t>(n / 2, 64));
+    const size_t lds = (size_t)n * sizeof(El);
+    if (variant == CLASSIC)
+        hipLaunchKernelGGL((k_ntt<W, CLASSIC>), dim3((unsigned)batch), dim3(block), lds, s, k, data, log2n, t.dev,
+                           t.scale, (uint32_t)inverse);
+    else
+        hipLaunchKernelGGL((k_ntt<W, PLANTARD>), dim3((unsigned)batch), dim3(block), lds, s, k, data, log2n,
+                           t.dev, t.scale, (uint32_t)inverse);
+    return hipGetLastError();
+}
+
+}  // namespace mont
+
+using namespace mont;
+
+extern "C" mont_status_t mont_ntt(const mont_ctx_t *ctx, void *data, size_t batch, uint32_t log2n, uint64_t root,
+                                  int inverse, mont_variant_t variant, void *stream)
+{
+    mont_status_t rc = check_ctx(ctx);
+    if (rc)
+        return rc;
+    if (variant != MONT_CLASSIC && variant != MONT_PLANTARD)
+        return fail(MONT_E_UNSUPPORTED, "mont_ntt uses the classic or the Plantard twiddle product");
+    rc = check_variant(ctx, variant);
+    if (rc)
+        return rc;
+    if (log2n < 1 || log2n > 12)
+        return fail(MONT_E_INVAL, "transform length 2^log2n with 1 <= log2n <= 12");
+    const uint64_t N = ctx->N;
+    if (root % N == 0 || powmod(root, 1ull << (log2n - 1), N) != N - 1)
+        return fail(MONT_E_DOMAIN, "root^(n/2) must be -1 mod N");
+    if (batch == 0)
+        return MONT_OK;
+    if (!data)
+        return fail(MONT_E_INVAL, "null data");
+    if (batch > 0x7fffffffull)
+        return fail(MONT_E_INVAL, "batch too large");
+    TwEntry t;
+    rc = twiddles(*ctx, variant, root, log2n, inverse ? 1 : 0, &t);
+    if (rc)
+        return rc;
+    const KCtx k = to_kctx(*ctx);
+    hipStream_t s = (hipStream_t)stream;
+    const hipError_t e = ctx->w == 16   ? go_ntt<16>(k, variant, data, batch, log2n, t, inverse ? 1 : 0, s)
+                         : ctx->w == 32 ? go_ntt<32>(k, variant, data, batch, log2n, t, inverse ? 1 : 0, s)
+                                        : go_ntt<64>(k, variant, data, batch, log2n, t, inverse ? 1 : 0, s);
+    return e == hipSuccess ? MONT_OK : hip_fail(e, "mont_ntt launch");
+}

@@ -1,0 +1,102 @@
+"""Parity at the workloads' full sizes, in the launch shapes the benchmark
+times (the library defaults), every output compared with the oracle.
+
+The oracle runs on host threads over chunks; at ~10 ns per element the
+largest case (2^28 products) takes well under a second of host time.
+"""
+import concurrent.futures as cf
+import os
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import paper_2402_00675_amd as mg
+from paper_2402_00675_amd import inputs as inp
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+WORKERS = min(16, len(os.sched_getaffinity(0)))
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def chunked_equal(got, fn, n, step=1 << 22):
+    """True when got[s:e] == fn(s, e) for every chunk."""
+    def chk(s):
+        e = min(s + step, n)
+        return bool(np.array_equal(got[s:e], fn(s, e)))
+    with cf.ThreadPoolExecutor(WORKERS) as ex:
+        return all(ex.map(chk, range(0, n, step)))
+
+
+def test_r16_workload():
+    wl = inp.R16Workload()
+    a, b = wl.operands()
+    c = mg.setup(wl.N, 16)
+    got = mg.mul(c, dev(a), dev(b)).cpu().numpy()
+    assert np.array_equal(got, orc.mul("classic", 16, wl.N, a, b))
+
+
+@pytest.mark.parametrize("variant", ["classic", "plantard", "signed", "signed_plantard", "signed_plantard_alpha"])
+def test_r32_workload(variant):
+    wl = inp.R32Workload()
+    signed = variant.startswith("signed")
+    a, b = wl.operands(signed)
+    c = mg.setup(wl.N, 32)
+    got = mg.mul(c, dev(a), dev(b), variant=variant).cpu().numpy()
+    assert chunked_equal(got, lambda s, e: orc.mul(variant, 32, wl.N, a[s:e], b[s:e], alpha=1), wl.n)
+
+
+def test_rns64_workload():
+    wl = inp.RNS64Workload()
+    a, b = wl.operands()
+    ctxs = [mg.setup(N, 64) for N in wl.moduli]
+    got = mg.mul_rns(ctxs, dev(a), dev(b)).cpu().numpy()
+    for i, N in enumerate(wl.moduli):
+        assert chunked_equal(got[i], lambda s, e, i=i, N=N: orc.mul("classic", 64, N, a[i, s:e], b[i, s:e]), wl.n), i
+
+
+@pytest.mark.parametrize("flags", [mg.BATCH_GRAPH, mg.BATCH_GRAPH | mg.BATCH_TUNE])
+def test_ragged_workload(flags):
+    wl = inp.RaggedWorkload()
+    lens, wide, mods = wl.segments()
+    offs, (a32, b32), (a64, b64) = wl.operands(lens, wide, mods)
+    ctxs = [mg.setup(N, 64 if wd else 32) for N, wd in zip(mods, wide)]
+    segs = [(i, mg.OP_MUL, "classic", int(n), int(o), int(o)) for i, (n, o) in enumerate(zip(lens, offs))]
+    d = [dev(x) for x in (a32, b32, a64, b64)]
+    o32 = torch.zeros_like(d[0])
+    o64 = torch.zeros_like(d[2])
+    P = mg.pools([None, d[0], d[2]], [None, d[1], d[3]], [None, o32, o64])
+    bt = mg.Batch(ctxs, segs, flags=flags)
+    bt.run(P)
+    bt.run(P)           # a replay
+    torch.cuda.synchronize()
+    g32, g64 = o32.cpu().numpy(), o64.cpu().numpy()
+    bt.close()
+
+    def seg_ok(i):
+        n, o, wd, N = int(lens[i]), int(offs[i]), wide[i], mods[i]
+        if wd:
+            return np.array_equal(g64[o:o + n], orc.mul("classic", 64, N, a64[o:o + n], b64[o:o + n]))
+        return np.array_equal(g32[o:o + n], orc.mul("classic", 32, N, a32[o:o + n], b32[o:o + n]))
+
+    with cf.ThreadPoolExecutor(WORKERS) as ex:
+        assert all(ex.map(seg_ok, range(len(lens))))
+
+
+def test_pow_bench_shape_sampled():
+    """Exponentiation at the benchmark's size (2^22), every 61st element checked."""
+    g = inp.rng(inp.W_SERVE, 7)
+    for bits, w in ((31, 32), (62, 64)):
+        N = inp.odd_modulus(g, bits)
+        n = 1 << 22
+        dt = np.uint32 if w == 32 else np.uint64
+        x = inp.uniform_residues(g, N, n, dt)
+        e = inp.u64_uniform(g, n)
+        got = mg.pow(mg.setup(N, w), dev(x), dev(e)).cpu().numpy()
+        idx = np.arange(0, n, 61)
+        assert np.array_equal(got[idx], orc.pow(w, N, x[idx], e[idx]))

@@ -1,0 +1,77 @@
+"""Batched transforms on the GPU against the DFT definition (oracle)."""
+import numpy as np
+import pytest
+
+import oracle as orc
+import paper_2402_00675_amd as mg
+from paper_2402_00675_amd import inputs as inp
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLDILOCKS = (1 << 64) - (1 << 32) + 1   # prime, 2^32 | N - 1, N > 2^63
+
+
+def root(N, n):
+    for g in range(2, 10000):
+        w = pow(g, (N - 1) // n, N)
+        if pow(w, n // 2, N) == N - 1:
+            return w
+    raise ValueError("no root")
+
+
+def prime_1_mod(bits, log2n, seed):
+    g = np.random.default_rng(seed)
+    while True:
+        k = int(g.integers(1 << (bits - 1 - log2n), 1 << (bits - log2n), dtype=np.uint64))
+        p = k * (1 << log2n) + 1
+        if p < (1 << bits) and inp.is_prime(p):
+            return p
+
+
+CASES = [
+    (16, 12289, [1, 3, 8, 12]),
+    (16, 3329, [2, 8]),
+    (32, 8380417, [1, 4, 8, 12]),
+    (32, 2013265921, [6, 11]),
+    (64, prime_1_mod(62, 12, 1), [2, 8, 12]),
+    (64, GOLDILOCKS, [3, 9]),
+]
+DT = {16: np.uint16, 32: np.uint32, 64: np.uint64}
+
+
+@pytest.mark.parametrize("w,N,logs", CASES, ids=["w%d-N%d" % (c[0], c[1]) for c in CASES])
+def test_ntt_parity(w, N, logs):
+    c = mg.setup(N, w)
+    variants = ["classic"] + (["plantard"] if c.valid("plantard") else [])
+    g = inp.rng(93, w + N % 97)
+    for log2n in logs:
+        n = 1 << log2n
+        batch = 3 if log2n >= 11 else 17
+        wr = root(N, n)
+        x = g.integers(0, N, size=(batch, n), dtype=np.uint64).astype(DT[w])
+        x[0, :] = 0
+        x[1, :] = (N - 1)
+        want_f = np.stack([orc.dft(w, N, x[i], wr) for i in range(batch)])
+        for v in variants:
+            d = torch.from_numpy(x.copy()).cuda()
+            mg.ntt(c, d, wr, variant=v)
+            got = d.cpu().numpy()
+            assert np.array_equal(got, want_f), (v, log2n)
+            mg.ntt(c, d, wr, inverse=True, variant=v)     # round trip
+            assert np.array_equal(d.cpu().numpy(), x), (v, log2n)
+        want_i = np.stack([orc.dft(w, N, x[i], wr, inverse=True) for i in range(min(batch, 3))])
+        d = torch.from_numpy(x[:want_i.shape[0]].copy()).cuda()
+        mg.ntt(c, d, wr, inverse=True, variant=variants[-1])
+        assert np.array_equal(d.cpu().numpy(), want_i)
+
+
+def test_ntt_rejects_bad_root_and_variant():
+    c = mg.setup(12289, 16)
+    d = torch.zeros((2, 16), dtype=torch.uint16, device="cuda")
+    with pytest.raises(mg.MontError) as e:
+        mg.ntt(c, d, 1)                        # 1^(n/2) != -1
+    assert e.value.code == -2
+    with pytest.raises(mg.MontError) as e:
+        mg.ntt(c, d, root(12289, 16), variant="signed")
+    assert e.value.code == -3

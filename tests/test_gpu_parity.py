@@ -144,6 +144,25 @@ def test_redc_parity(w, N, variant):
                                                                            want[bad[0]])
 
 
+@pytest.mark.parametrize("w,N,variant", CASES, ids=["w%d-N%d-%s" % c for c in CASES])
+def test_mul_const_parity(w, N, variant):
+    """Fixed-operand product equals the product with b broadcast, for edge and random b."""
+    g = inp.rng(95, w * 7 + N % 1000)
+    n = 30_011
+    a, bs = operands(variant, w, N, n, g)
+    c = mg.setup(N, w)
+    da = dev(a)
+    h = (N - 1) // 2
+    picks = [int(bs[7]), int(bs[n // 2])] + ([0, 1, -1, h, -h] if variant in SIGNED else [0, 1, N - 1, N // 2])
+    for b in picks:
+        got = host(mg.mul_const(c, da, b, variant=variant))
+        want = orc.mul(variant, w, N, a, np.full(n, b, dtype=a.dtype), alpha=c.s.alpha)
+        assert np.array_equal(got, want), (b, np.nonzero(got != want)[0][:5])
+    with pytest.raises(mg.MontError) as e:
+        mg.mul_const(c, da, N if variant not in SIGNED else -N, variant=variant)
+    assert e.value.code == -2
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 7, 8, 9, 15, 16, 17, 255, 256, 257, 1023, 4097])
 @pytest.mark.parametrize("w", [16, 32, 64])
 def test_small_and_misaligned(w, n):
@@ -470,3 +489,58 @@ def test_ragged_empty_and_zero_length():
     sync()
     assert b.info()["ntiles"] == 0
     b.close()
+
+
+# -------------------------------------------------------------------- CRT
+
+
+def words_to_ints(w):
+    return [sum(int(x) << (64 * j) for j, x in enumerate(row)) for row in w]
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 8, 11, 16])
+@pytest.mark.parametrize("kind", ["primes60", "mixed"])
+def test_crt_parity(k, kind):
+    g = inp.rng(94, k)
+    if kind == "primes60":
+        mods = inp.random_primes(g, 60, k)          # all within a factor 2: one-subtraction path
+    else:
+        pool = [3, 5, 7, 65537, 1000000007, (1 << 61) - 1, (1 << 62) - 57, (1 << 64) - 59, 998244353,
+                4294967291, 2147483647, 18446744073709551557 - 2 * 0, 1099511627791, 127, 8191, 131071]
+        pool = sorted(set(p for p in pool if inp.is_prime(p)))
+        mods = [pool[(i * 5) % len(pool)] for i in range(len(pool))][:k]
+        mods = list(dict.fromkeys(mods))
+        while len(mods) < k:
+            q = inp.odd_modulus(g, 40)
+            if inp.is_prime(q) and q not in mods:
+                mods.append(q)
+    n = 5003
+    ld = 5008
+    res = np.zeros((k, ld), np.uint64)
+    for j, m in enumerate(mods):
+        res[j, :n] = g.integers(0, m, size=n, dtype=np.uint64)
+        res[j, :3] = [0, m - 1, 1]
+    ctxs = [mg.setup(m, 64) for m in mods]
+    got = mg.crt(ctxs, dev(res), n=n).cpu().numpy()
+    want = orc.crt([[int(x) for x in res[j, :n]] for j in range(k)], mods)
+    assert words_to_ints(got) == want
+
+
+def test_crt_rejects_common_factor():
+    ctxs = [mg.setup(15, 64), mg.setup(21, 64)]
+    res = torch.zeros((2, 16), dtype=torch.uint64, device="cuda")
+    with pytest.raises(mg.MontError) as e:
+        mg.crt(ctxs, res)
+    assert e.value.code == -2
+
+
+def test_crt_of_rns_product():
+    """RNS product followed by reconstruction equals a b R^{-1} mod N_j in every row, i.e. the CRT
+    of the per-row Montgomery products."""
+    wl = inp.RNS64Workload(n=20_000)
+    a, b = wl.operands(n=wl.n)
+    ctxs = [mg.setup(N, 64) for N in wl.moduli]
+    prod = mg.mul_rns(ctxs, dev(a), dev(b))
+    X = words_to_ints(mg.crt(ctxs, prod).cpu().numpy())
+    rows = [orc.mul("classic", 64, N, a[j], b[j]) for j, N in enumerate(wl.moduli)]
+    assert X == orc.crt([[int(x) for x in r] for r in rows], wl.moduli)

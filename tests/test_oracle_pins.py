@@ -348,3 +348,79 @@ def test_domain_rejections():
     orc.redc_small("signed_plantard", 6, 31, [-(1 << 10), 1 << 10])
     with pytest.raises(ValueError):
         orc.redc_small("classic", 8, 100, [0])                  # even N
+
+
+# --------------------------------------------------------------- CRT
+
+
+def test_crt_two_moduli_is_qin_form():
+    """For moduli (N, R), the oracle's CRT is eq. (qin1)'s T = r1 R^{-1} R + r2 N^{-1} N (mod NR)."""
+    g = np.random.default_rng(21)
+    for w in (8, 16, 32):
+        R = 1 << w
+        for N in [3, 101, R - 1] + [int(x) | 1 for x in g.integers(3, R, size=5)]:
+            c = orc.constants(N, w)
+            r1 = [int(x) for x in g.integers(0, N, size=50)]
+            r2 = [int(x) for x in g.integers(0, R, size=50)]
+            got = orc.crt([r1, r2], [N, R])
+            want = [(a * c["rinv_mod_n"] * R + b * c["ninv"] * N) % (N * R) for a, b in zip(r1, r2)]
+            assert got == want
+
+
+def test_crt_brute_force_and_properties():
+    # tiny pairwise coprime moduli: search every X in [0, M)
+    mods = [3, 5, 7, 11]
+    M = 3 * 5 * 7 * 11
+    table = {tuple(X % m for m in mods): X for X in range(M)}
+    g = np.random.default_rng(22)
+    res = [[int(x) for x in g.integers(0, m, size=200)] for m in mods]
+    got = orc.crt(res, mods)
+    assert got == [table[tuple(r[i] for r in res)] for i in range(200)]
+    # wide moduli: the defining congruences and range
+    mods = [(1 << 61) - 1, (1 << 62) - 57, 1000000007, 998244353, (1 << 64) - 59]
+    res = [[int(x) % m for x in g.integers(0, 2**63, size=100, dtype=np.uint64)] for m in mods]
+    P = 1
+    for m in mods:
+        P *= m
+    for i, X in enumerate(orc.crt(res, mods)):
+        assert 0 <= X < P and all(X % m == r[i] for m, r in zip(mods, res))
+
+
+# --------------------------------------------------------------- DFT
+
+
+def _root(N, n):
+    for g in range(2, 10000):
+        w = pow(g, (N - 1) // n, N)
+        if pow(w, n // 2, N) == N - 1:
+            return w
+    raise ValueError("no root")
+
+
+def test_dft_closed_forms_and_inverse():
+    for N, log2n in [(17, 4), (12289, 6), (8380417, 8), ((1 << 64) - (1 << 32) + 1, 5)]:
+        n = 1 << log2n
+        w = _root(N, n)
+        delta = np.zeros(n, np.uint64)
+        delta[1] = 1                                   # x = X^1  ->  X_k = w^k
+        assert [int(v) for v in orc.dft(64, N, delta, w)] == [pow(w, k, N) for k in range(n)]
+        ones = np.ones(n, np.uint64)                   # sum_j w^(jk) = n [k = 0]
+        assert [int(v) for v in orc.dft(64, N, ones, w)] == [n % N] + [0] * (n - 1)
+        g = np.random.default_rng(log2n)
+        x = g.integers(0, N, size=n, dtype=np.uint64)
+        X = orc.dft(64, N, x, w)
+        assert np.array_equal(orc.dft(64, N, X, w, inverse=True), x)
+
+
+def test_dft_convolution_theorem():
+    """DFT(a) . DFT(b) = DFT(a * b) for the cyclic convolution (brute force)."""
+    N, n = 12289, 32
+    w = _root(N, n)
+    g = np.random.default_rng(3)
+    a = [int(v) for v in g.integers(0, N, size=n)]
+    b = [int(v) for v in g.integers(0, N, size=n)]
+    conv = [sum(a[j] * b[(k - j) % n] for j in range(n)) % N for k in range(n)]
+    A = orc.dft(32, N, np.array(a, np.uint32), w)
+    B = orc.dft(32, N, np.array(b, np.uint32), w)
+    C = orc.dft(32, N, np.array(conv, np.uint32), w)
+    assert [int(x) * int(y) % N for x, y in zip(A, B)] == [int(c) for c in C]
