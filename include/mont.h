@@ -364,6 +364,7 @@ typedef struct mont_server_stats {
     uint64_t submitted, completed, rejected, launches, jobs_launched;
     uint64_t queued, staged, in_flight;
     uint64_t bytes_in_use, peak_bytes_in_use;
+    uint64_t enqueue_ns; /* service-thread time spent enqueueing batches (copies, tables, launch) */
 } mont_server_stats_t;
 
 /* Allocates the device arena and starts the service thread on the current device. */

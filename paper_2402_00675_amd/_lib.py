@@ -391,7 +391,7 @@ class CompletionStruct(ctypes.Structure):
 class ServerStatsStruct(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in ("submitted", "completed", "rejected", "launches", "jobs_launched",
                                                  "queued", "staged", "in_flight", "bytes_in_use",
-                                                 "peak_bytes_in_use")]
+                                                 "peak_bytes_in_use", "enqueue_ns")]
 
 
 _SERVE_SIG = {

@@ -163,7 +163,17 @@ class GpuBackend : public mont_sched::Backend {
         return &m.emplace(N, c).first->second;
     }
 
+    std::atomic<uint64_t> enqueue_ns{0};
+
     int launch(int si, const std::vector<mont_sched::Job *> &jobs) override
+    {
+        const double t0 = now_s();
+        const int rc = enqueue(si, jobs);
+        enqueue_ns += (uint64_t)((now_s() - t0) * 1e9);
+        return rc;
+    }
+
+    int enqueue(int si, const std::vector<mont_sched::Job *> &jobs)
     {
         ServeSlot &s = slot[si];
         tiles.clear();
@@ -470,6 +480,7 @@ mont_status_t mont_serve_stats(const mont_server_t *S, mont_server_stats_t *st)
     st->in_flight = x.in_flight;
     st->bytes_in_use = x.used_slots[0] * 16 + x.used_slots[1] * 24;
     st->peak_bytes_in_use = x.peak_slots[0] * 16 + x.peak_slots[1] * 24;
+    st->enqueue_ns = M->be->enqueue_ns.load();
     return MONT_OK;
 }
 
