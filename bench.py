@@ -337,12 +337,22 @@ def serving(torch, mg, njobs):
     stream = serve.JobStream(torch, njobs)
     nel = stream.elements()
     log("serving: %d jobs, %d elements" % (njobs, nel))
+    res_dma = {}
     srv = mg.Server(hbm_budget_bytes=8 << 30, streams=3, max_batch_jobs=512)
+    try:
+        # staging by DMA copies (buffers not declared): saturation only, for comparison
+        res_dma = serve.summarize(serve.replay(srv, stream, np.zeros(njobs)), nel)
+        log("serving saturation, DMA staging: %s" % res_dma)
+    finally:
+        srv.close()
+    srv = mg.Server(hbm_budget_bytes=8 << 30, streams=3, max_batch_jobs=512)
+    stream.declare(srv)
     try:
         sat = serve.summarize(serve.replay(srv, stream, np.zeros(njobs)), nel)
         log("serving saturation: %s" % sat)
         res = {"jobs": njobs, "elements": nel, "mix": "60% mul / 40% pow (uniform 64-bit e), lengths "
-               "log-uniform [2^8, 2^18], odd 31/62-bit moduli", "saturation": sat}
+               "log-uniform [2^8, 2^18], odd 31/62-bit moduli", "staging": "copy kernels (declared pinned host "
+               "buffers)", "saturation": sat, "saturation_dma_staging": res_dma}
         for f in (0.5, 0.8, 0.95):
             rate = f * sat["jobs_per_s"]
             r = serve.summarize(serve.replay(srv, stream, stream.gaps_unit / rate), nel)

@@ -372,6 +372,13 @@ mont_status_t mont_serve_create(const mont_server_cfg_t *cfg, mont_server_t **ou
 /* Queues one job.  MONT_E_INVAL for a malformed job, MONT_E_DOMAIN for one that
  * can never fit the budget (no completion is produced for either). */
 mont_status_t mont_serve_submit(mont_server_t *s, const mont_job_t *job);
+/* Declares [ptr, ptr + bytes) as pinned host memory mapped for the device
+ * (allocated with hipHostMalloc; verified with hipPointerGetAttributes, never
+ * registered here).  Jobs whose buffers lie in declared regions are staged by
+ * two copy kernels per batch instead of DMA copies per job.  MONT_E_INVAL for
+ * memory that is not such pinned memory, or that overlaps a declared region
+ * without being inside it.  Regions stay declared for the server's life. */
+mont_status_t mont_serve_host_region(mont_server_t *s, void *ptr, size_t bytes);
 /* Submits jobs[i] when mont_serve_now() reaches t0 + arrival_s[i] (blocking;
  * arrival_s non-decreasing, t0 = the clock at the call).  Returns the number
  * accepted, or a negative status. */

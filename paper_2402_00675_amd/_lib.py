@@ -404,6 +404,7 @@ _SERVE_SIG = {
     "mont_serve_drain": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "mont_serve_stats": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ServerStatsStruct)]),
     "mont_serve_now": (ctypes.c_double, []),
+    "mont_serve_host_region": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "mont_serve_destroy": (None, [ctypes.c_void_p]),
 }
 
@@ -450,6 +451,11 @@ class Server:
         j = self.job(id_, N, w, op, n, in0, in1, out)
         self._keep[id_] = (in0, in1, out)
         check(_serve_lib().mont_serve_submit(self.h, ctypes.byref(j)))
+
+    def host_region(self, t):
+        """Declares a pinned CPU tensor's storage as device-mapped host memory for staging kernels."""
+        check(_serve_lib().mont_serve_host_region(self.h, ctypes.c_void_p(host_ptr(t)),
+                                                  t.numel() * t.element_size()))
 
     def submit_struct(self, j: JobStruct):
         """Queues a prepared JobStruct (its host buffers are the caller's to keep alive)."""

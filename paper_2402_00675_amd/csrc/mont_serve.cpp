@@ -9,11 +9,21 @@
 //                            exponent (8 bytes at slot*8)
 //   out[c]  cap * es bytes   result
 // so one slot index addresses all three, and a job's slots never alias
-// another job's.  Each stream slot owns pinned host staging for its
-// segment/tile tables, device copies of them, a self-resetting tile counter
-// and a completion event; a slot is reused only after its event fired.
+// another job's.  Each stream slot owns pinned host staging for its tables,
+// device copies of them, a self-resetting tile counter and a completion
+// event; a slot is reused only after its event fired.
+//
+// Staging.  A job whose host buffers lie in a region the caller declared as
+// pinned, device-mapped host memory (mont_serve_host_region, verified with
+// hipPointerGetAttributes) is copied into the arena and back by two copy
+// kernels per batch that read and write host memory through its device
+// mapping: one launch for all of a batch's inputs and one for all its
+// results, instead of three DMA copies per job.  Other buffers take
+// hipMemcpyAsync.  Per batch the stream runs: DMA inputs, one table upload,
+// gather kernel, ragged kernel, scatter kernel, DMA results, event.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -36,13 +46,62 @@ static double now_s()
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
+// One host-to-device or device-to-host copy of `words` 32-bit words, run by k_xfer.
+struct XDesc {
+    const uint32_t *src;
+    uint32_t *dst;
+    uint64_t words;
+    uint64_t pad;
+};
+
+struct XTile {
+    uint32_t desc;
+    uint32_t words;
+    uint64_t start;
+};
+
+constexpr uint32_t XTILE_WORDS = 8192;  // 32 KiB per workgroup
+constexpr int XFER_U = 8;               // words in flight per lane
+
+// Copies tiles of descriptors; src or dst may be device-mapped host memory.
+__global__ void __launch_bounds__(BLOCK) k_xfer(const XDesc *__restrict__ d, const XTile *__restrict__ t,
+                                                uint32_t ntiles)
+{
+    const uint32_t ti = blockIdx.x;
+    if (ti >= ntiles)
+        return;
+    const XTile tl = t[ti];
+    const XDesc ds = d[tl.desc];
+    const uint32_t *src = ds.src + tl.start;
+    uint32_t *dst = ds.dst + tl.start;
+    for (uint32_t base = threadIdx.x; base < tl.words; base += BLOCK * XFER_U) {
+        uint32_t v[XFER_U];
+#pragma unroll
+        for (int u = 0; u < XFER_U; ++u) {
+            const uint32_t i = base + u * BLOCK;
+            if (i < tl.words)
+                v[u] = src[i];
+        }
+#pragma unroll
+        for (int u = 0; u < XFER_U; ++u) {
+            const uint32_t i = base + u * BLOCK;
+            if (i < tl.words)
+                dst[i] = v[u];
+        }
+    }
+}
+
 struct ServeSlot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    DSeg *hsegs = nullptr, *dsegs = nullptr;
-    DTile *htiles = nullptr, *dtiles = nullptr;
+    unsigned char *hstage = nullptr;  // pinned: [segs][tiles][xin desc][xin tiles][xout desc][xout tiles]
+    unsigned char *dstage = nullptr;  // device copy
+    size_t stage_cap = 0;
     uint32_t *dctr = nullptr;
-    size_t seg_cap = 0, tile_cap = 0;
+};
+
+struct HostRegion {
+    uintptr_t lo, hi, dev;
 };
 
 class GpuBackend : public mont_sched::Backend {
@@ -53,7 +112,61 @@ class GpuBackend : public mont_sched::Backend {
     std::vector<ServeSlot> slot;
     uint32_t tile_base = 8192, pow_tile = 1024, grid_max = 0;
     std::unordered_map<uint64_t, mont_ctx_t> ctx_cache[2];
-    std::vector<DTile> tiles;  // scratch for building a batch's tile table
+    // scratch for building a batch's tables
+    std::vector<DTile> tiles;
+    std::vector<XDesc> xin, xout;
+    std::vector<XTile> xtin, xtout;
+    struct Dma {
+        void *dst;
+        const void *src;
+        size_t bytes;
+    };
+    std::vector<Dma> dma_in, dma_out;
+    std::mutex reg_mu;
+    std::vector<HostRegion> regions;  // sorted by lo, disjoint
+
+    // Device address of [p, p + bytes) when it lies in one declared region.
+    uintptr_t alias(const void *p, size_t bytes)
+    {
+        const uintptr_t a = (uintptr_t)p;
+        if (a & 3u)
+            return 0;
+        auto it = std::upper_bound(regions.begin(), regions.end(), a,
+                                   [](uintptr_t v, const HostRegion &r) { return v < r.lo; });
+        if (it == regions.begin())
+            return 0;
+        --it;
+        if (a + bytes > it->hi)
+            return 0;
+        return it->dev + (a - it->lo);
+    }
+
+    mont_status_t add_region(void *p, size_t bytes)
+    {
+        if (!p || bytes == 0 || ((uintptr_t)p & 3u) || (bytes & 3u))
+            return fail(MONT_E_INVAL, "host region must be non-empty, 4-byte aligned and sized");
+        hipPointerAttribute_t a0{}, a1{};
+        const void *last = (const char *)p + bytes - 1;
+        if (hipPointerGetAttributes(&a0, p) != hipSuccess || hipPointerGetAttributes(&a1, last) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(MONT_E_INVAL, "host region is not pinned host memory");
+        }
+        if (a0.type != hipMemoryTypeHost || a1.type != hipMemoryTypeHost || !a0.devicePointer || !a1.devicePointer ||
+            (uintptr_t)a1.devicePointer - (uintptr_t)a0.devicePointer != bytes - 1)
+            return fail(MONT_E_INVAL, "host region is not device-mapped pinned host memory");
+        HostRegion r{(uintptr_t)p, (uintptr_t)p + bytes, (uintptr_t)a0.devicePointer};
+        std::lock_guard<std::mutex> g(reg_mu);
+        for (const HostRegion &q : regions)
+            if (r.lo < q.hi && q.lo < r.hi) {
+                if (r.lo >= q.lo && r.hi <= q.hi)
+                    return MONT_OK;  // already covered
+                return fail(MONT_E_INVAL, "host region overlaps a declared region");
+            }
+        regions.insert(std::upper_bound(regions.begin(), regions.end(), r,
+                                        [](const HostRegion &x, const HostRegion &y) { return x.lo < y.lo; }),
+                       r);
+        return MONT_OK;
+    }
 
     mont_status_t init(const mont_server_cfg_t &c, uint32_t nslots, uint64_t budget)
     {
@@ -82,39 +195,30 @@ class GpuBackend : public mont_sched::Backend {
                 e = hipMemset(s.dctr, 0, 64);
             if (e != hipSuccess)
                 return hip_fail(e, "serving slot");
-            mont_status_t rc = reserve(s, max_jobs, max_jobs * 64);
+            mont_status_t rc = reserve(s, max_jobs * (sizeof(DSeg) + 64 * sizeof(DTile) + 96 * sizeof(XDesc)));
             if (rc)
                 return rc;
         }
         return MONT_OK;
     }
 
-    mont_status_t reserve(ServeSlot &s, size_t nseg, size_t ntile)
+    // Grows the slot's staging buffers (only while the slot is idle).
+    mont_status_t reserve(ServeSlot &s, size_t bytes)
     {
-        if (nseg > s.seg_cap) {
-            if (s.hsegs)
-                (void)hipHostFree(s.hsegs);
-            if (s.dsegs)
-                (void)hipFree(s.dsegs);
-            s.hsegs = nullptr;
-            s.dsegs = nullptr;
-            if (hipHostMalloc((void **)&s.hsegs, nseg * sizeof(DSeg), hipHostMallocDefault) != hipSuccess ||
-                hipMalloc(&s.dsegs, nseg * sizeof(DSeg)) != hipSuccess)
-                return fail(MONT_E_NOMEM, "segment tables");
-            s.seg_cap = nseg;
-        }
-        if (ntile > s.tile_cap) {
-            if (s.htiles)
-                (void)hipHostFree(s.htiles);
-            if (s.dtiles)
-                (void)hipFree(s.dtiles);
-            s.htiles = nullptr;
-            s.dtiles = nullptr;
-            if (hipHostMalloc((void **)&s.htiles, ntile * sizeof(DTile), hipHostMallocDefault) != hipSuccess ||
-                hipMalloc(&s.dtiles, ntile * sizeof(DTile)) != hipSuccess)
-                return fail(MONT_E_NOMEM, "tile tables");
-            s.tile_cap = ntile;
-        }
+        if (bytes <= s.stage_cap)
+            return MONT_OK;
+        bytes = std::max(bytes, 2 * s.stage_cap);
+        if (s.hstage)
+            (void)hipHostFree(s.hstage);
+        if (s.dstage)
+            (void)hipFree(s.dstage);
+        s.hstage = nullptr;
+        s.dstage = nullptr;
+        s.stage_cap = 0;
+        if (hipHostMalloc((void **)&s.hstage, bytes, hipHostMallocDefault) != hipSuccess ||
+            hipMalloc(&s.dstage, bytes) != hipSuccess)
+            return fail(MONT_E_NOMEM, "batch staging tables");
+        s.stage_cap = bytes;
         return MONT_OK;
     }
 
@@ -127,14 +231,10 @@ class GpuBackend : public mont_sched::Backend {
                 (void)hipEventDestroy(s.done);
             if (s.stream)
                 (void)hipStreamDestroy(s.stream);
-            if (s.hsegs)
-                (void)hipHostFree(s.hsegs);
-            if (s.htiles)
-                (void)hipHostFree(s.htiles);
-            if (s.dsegs)
-                (void)hipFree(s.dsegs);
-            if (s.dtiles)
-                (void)hipFree(s.dtiles);
+            if (s.hstage)
+                (void)hipHostFree(s.hstage);
+            if (s.dstage)
+                (void)hipFree(s.dstage);
             if (s.dctr)
                 (void)hipFree(s.dctr);
         }
@@ -173,25 +273,76 @@ class GpuBackend : public mont_sched::Backend {
         return rc;
     }
 
+    static size_t up16(size_t x) { return (x + 15) / 16 * 16; }
+
+    static void split(std::vector<XTile> &t, uint32_t desc, uint64_t words)
+    {
+        for (uint64_t st = 0; st < words; st += XTILE_WORDS)
+            t.push_back({desc, (uint32_t)std::min<uint64_t>(XTILE_WORDS, words - st), st});
+    }
+
     int enqueue(int si, const std::vector<mont_sched::Job *> &jobs)
     {
         ServeSlot &s = slot[si];
         tiles.clear();
+        xin.clear();
+        xout.clear();
+        xtin.clear();
+        xtout.clear();
+        dma_in.clear();
+        dma_out.clear();
+        const size_t es[2] = {4, 8};
         for (uint32_t i = 0; i < jobs.size(); ++i) {
             const mont_sched::Job &j = *jobs[i];
             const uint64_t te = j.op == mont_sched::OP_POW ? pow_tile : (j.cls == 0 ? tile_base : tile_base / 2);
             for (uint64_t st = 0; st < j.n; st += te)
                 tiles.push_back({i, (uint32_t)std::min<uint64_t>(te, j.n - st), st});
         }
-        if (reserve(s, jobs.size(), tiles.size()))
+        {
+            std::lock_guard<std::mutex> g(reg_mu);
+            for (const mont_sched::Job *jp : jobs) {
+                const mont_sched::Job &j = *jp;
+                const size_t b = es[j.cls];
+                char *d0 = (char *)in0[j.cls] + j.off * b;
+                char *d1 = (char *)in1[j.cls] + j.off * 8;
+                char *dout = (char *)out[j.cls] + j.off * b;
+                const size_t n0 = b * j.n, n1 = (j.op == mont_sched::OP_POW ? 8 : b) * j.n;
+                const uintptr_t a0 = alias(j.in0, n0), a1 = alias(j.in1, n1), ao = alias(j.out, n0);
+                if (a0)
+                    xin.push_back({(const uint32_t *)a0, (uint32_t *)d0, n0 / 4, 0});
+                else
+                    dma_in.push_back({d0, j.in0, n0});
+                if (a1)
+                    xin.push_back({(const uint32_t *)a1, (uint32_t *)d1, n1 / 4, 0});
+                else
+                    dma_in.push_back({d1, j.in1, n1});
+                if (ao)
+                    xout.push_back({(const uint32_t *)dout, (uint32_t *)ao, n0 / 4, 0});
+                else
+                    dma_out.push_back({j.out, dout, n0});
+            }
+        }
+        for (uint32_t d = 0; d < xin.size(); ++d)
+            split(xtin, d, xin[d].words);
+        for (uint32_t d = 0; d < xout.size(); ++d)
+            split(xtout, d, xout[d].words);
+        // one packed table upload per batch
+        const size_t o_seg = 0;
+        const size_t o_tile = up16(o_seg + jobs.size() * sizeof(DSeg));
+        const size_t o_xin = up16(o_tile + tiles.size() * sizeof(DTile));
+        const size_t o_xtin = up16(o_xin + xin.size() * sizeof(XDesc));
+        const size_t o_xout = up16(o_xtin + xtin.size() * sizeof(XTile));
+        const size_t o_xtout = up16(o_xout + xout.size() * sizeof(XDesc));
+        const size_t total = up16(o_xtout + xtout.size() * sizeof(XTile));
+        if (reserve(s, total))
             return -1;
-        const size_t es[2] = {4, 8};
+        DSeg *hsegs = (DSeg *)(s.hstage + o_seg);
         for (uint32_t i = 0; i < jobs.size(); ++i) {
             const mont_sched::Job &j = *jobs[i];
             const mont_ctx_t *c = ctx_of(j.N, j.w);
             if (!c)
                 return -1;
-            DSeg &d = s.hsegs[i];
+            DSeg &d = hsegs[i];
             std::memset(&d, 0, sizeof d);
             d.c = to_kctx(*c);
             d.off = j.off;
@@ -201,23 +352,24 @@ class GpuBackend : public mont_sched::Backend {
             d.variant = CLASSIC;
             d.wc = j.cls == 0 ? 1 : 2;
         }
-        std::memcpy(s.htiles, tiles.data(), tiles.size() * sizeof(DTile));
+        std::memcpy(s.hstage + o_tile, tiles.data(), tiles.size() * sizeof(DTile));
+        std::memcpy(s.hstage + o_xin, xin.data(), xin.size() * sizeof(XDesc));
+        std::memcpy(s.hstage + o_xtin, xtin.data(), xtin.size() * sizeof(XTile));
+        std::memcpy(s.hstage + o_xout, xout.data(), xout.size() * sizeof(XDesc));
+        std::memcpy(s.hstage + o_xtout, xtout.data(), xtout.size() * sizeof(XTile));
+
         hipError_t e = hipSuccess;
-        for (const mont_sched::Job *jp : jobs) {
-            const mont_sched::Job &j = *jp;
-            const size_t b = es[j.cls];
-            char *a0 = (char *)in0[j.cls] + j.off * b;
-            char *a1 = (char *)in1[j.cls] + j.off * 8;
-            const size_t n1 = j.op == mont_sched::OP_POW ? 8 * j.n : b * j.n;
+        for (const Dma &m : dma_in)
             if (e == hipSuccess)
-                e = hipMemcpyAsync(a0, j.in0, b * j.n, hipMemcpyHostToDevice, s.stream);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(a1, j.in1, n1, hipMemcpyHostToDevice, s.stream);
-        }
+                e = hipMemcpyAsync(m.dst, m.src, m.bytes, hipMemcpyHostToDevice, s.stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(s.dsegs, s.hsegs, jobs.size() * sizeof(DSeg), hipMemcpyHostToDevice, s.stream);
-        if (e == hipSuccess && !tiles.empty())
-            e = hipMemcpyAsync(s.dtiles, s.htiles, tiles.size() * sizeof(DTile), hipMemcpyHostToDevice, s.stream);
+            e = hipMemcpyAsync(s.dstage, s.hstage, total, hipMemcpyHostToDevice, s.stream);
+        if (e == hipSuccess && !xtin.empty()) {
+            hipLaunchKernelGGL(k_xfer, dim3((unsigned)xtin.size()), dim3(BLOCK), 0, s.stream,
+                               (const XDesc *)(s.dstage + o_xin), (const XTile *)(s.dstage + o_xtin),
+                               (uint32_t)xtin.size());
+            e = hipGetLastError();
+        }
         if (e == hipSuccess && !tiles.empty()) {
             DPools P{};
             P.in0[1] = in0[0];
@@ -227,14 +379,18 @@ class GpuBackend : public mont_sched::Backend {
             P.in1[2] = in1[1];
             P.out[2] = out[1];
             const uint32_t grid = (uint32_t)std::max<size_t>(1, std::min<size_t>(tiles.size(), grid_max));
-            e = launch_ragged(s.dsegs, s.dtiles, (uint32_t)tiles.size(), P, s.dctr, 1u, grid, true, s.stream);
+            e = launch_ragged((const DSeg *)(s.dstage + o_seg), (const DTile *)(s.dstage + o_tile),
+                              (uint32_t)tiles.size(), P, s.dctr, 1u, grid, true, s.stream);
         }
-        for (const mont_sched::Job *jp : jobs) {
-            const mont_sched::Job &j = *jp;
-            const size_t b = es[j.cls];
+        if (e == hipSuccess && !xtout.empty()) {
+            hipLaunchKernelGGL(k_xfer, dim3((unsigned)xtout.size()), dim3(BLOCK), 0, s.stream,
+                               (const XDesc *)(s.dstage + o_xout), (const XTile *)(s.dstage + o_xtout),
+                               (uint32_t)xtout.size());
+            e = hipGetLastError();
+        }
+        for (const Dma &m : dma_out)
             if (e == hipSuccess)
-                e = hipMemcpyAsync(j.out, (char *)out[j.cls] + j.off * b, b * j.n, hipMemcpyDeviceToHost, s.stream);
-        }
+                e = hipMemcpyAsync(m.dst, m.src, m.bytes, hipMemcpyDeviceToHost, s.stream);
         if (e == hipSuccess)
             e = hipEventRecord(s.done, s.stream);
         if (e != hipSuccess) {
@@ -400,6 +556,13 @@ mont_status_t mont_serve_submit(mont_server_t *S, const mont_job_t *job)
     }
     S->cv_work.notify_one();
     return MONT_OK;
+}
+
+mont_status_t mont_serve_host_region(mont_server_t *S, void *ptr, size_t bytes)
+{
+    if (!S)
+        return fail(MONT_E_INVAL, "null server");
+    return S->be->add_region(ptr, bytes);
 }
 
 int64_t mont_serve_submit_timed(mont_server_t *S, const mont_job_t *jobs, const double *arrival_s, uint64_t n)

@@ -78,6 +78,17 @@ class JobStream:
             j = self.jobs[i]
             j.id, j.N, j.w, j.op, j.n, j.in0, j.in1, j.out = i, mods[i], w, op, n, in0, in1, out
 
+    def pinned_buffers(self):
+        """Every pinned host buffer the stream's jobs read or write."""
+        bufs = [t for pair in self.pool.values() for t in pair] + [self.exps]
+        bufs += list(getattr(self, "sink", {}).values()) + list(self.outs.values())
+        return bufs
+
+    def declare(self, server):
+        """Declares the stream's pinned buffers to the server (kernel staging)."""
+        for t in self.pinned_buffers():
+            server.host_region(t)
+
     def elements(self) -> int:
         return int(self.lens.sum())
 

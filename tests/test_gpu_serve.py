@@ -21,9 +21,12 @@ def oracle_of(stream, i):
     return orc.pow(w, N, x, y)
 
 
-def test_alone_vs_mix_and_oracle():
+@pytest.mark.parametrize("staging", ["kernel", "dma"])
+def test_alone_vs_mix_and_oracle(staging):
     stream = serve.JobStream(torch, njobs=400, seed_rep=3, distinct_outputs=True, hi=1 << 14)
     srv = mg.Server(hbm_budget_bytes=256 << 20, streams=3, max_batch_jobs=64)
+    if staging == "kernel":
+        stream.declare(srv)      # copies by the gather/scatter kernels
     try:
         done = serve.replay(srv, stream, stream.gaps_unit / 20000.0)   # Poisson, 20k jobs/s
         assert len(done) == stream.njobs and all(d[1] == 0 for d in done)
@@ -48,6 +51,7 @@ def test_budget_bounds_admission():
     stream = serve.JobStream(torch, njobs=300, seed_rep=4, distinct_outputs=True, hi=1 << 14)
     budget = 8 << 20
     srv = mg.Server(hbm_budget_bytes=budget, streams=2, max_batch_jobs=32)
+    stream.declare(srv)
     try:
         done = serve.replay(srv, stream, np.zeros(stream.njobs))       # everything at once
         assert all(d[1] == 0 for d in done)
@@ -63,5 +67,36 @@ def test_budget_bounds_admission():
         with pytest.raises(mg.MontError) as e:
             srv.submit(10**6 + 1, 8380418, 32, mg.OP_MUL, big[:8], big[:8], big[:8])
         assert e.value.code == -1
+    finally:
+        srv.close()
+
+
+def test_host_region_checks():
+    srv = mg.Server(hbm_budget_bytes=16 << 20, streams=1)
+    try:
+        pinned = torch.empty(1 << 12, dtype=torch.uint32, pin_memory=True)
+        srv.host_region(pinned)
+        srv.host_region(pinned[16:64])            # inside a declared region: accepted
+        pageable = torch.empty(1 << 12, dtype=torch.uint32)
+        with pytest.raises(mg.MontError) as e:
+            srv.host_region(pageable)             # not pinned: refused, DMA path stays
+        assert e.value.code == -1
+        dev = torch.empty(1 << 12, dtype=torch.uint32, device="cuda")
+        with pytest.raises(mg.MontError):
+            srv._keep = {}
+            import ctypes
+            from paper_2402_00675_amd import _lib
+            _lib.check(_lib._serve_lib().mont_serve_host_region(srv.h, ctypes.c_void_p(dev.data_ptr()), 4096))
+        # a job mixing a declared input and undeclared buffers still completes correctly
+        x = pinned[:256]
+        x.numpy()[:] = np.arange(256, dtype=np.uint32)
+        y = torch.empty(256, dtype=torch.uint32, pin_memory=True)
+        y.numpy()[:] = 7
+        o = torch.empty(256, dtype=torch.uint32)
+        srv.submit(1, 8380417, 32, mg.OP_MUL, x, y, o)
+        srv.drain(60_000)
+        assert srv.poll(4)[0][1] == 0
+        want = orc.mul("classic", 32, 8380417, x.numpy().copy(), y.numpy().copy())
+        assert np.array_equal(o.numpy(), want)
     finally:
         srv.close()
