@@ -391,6 +391,27 @@ def ragged(torch, mg, inp, nseg):
         if not (np.array_equal(o32h, o32.cpu().numpy()) and np.array_equal(o64h, o64.cpu().numpy())):
             raise SystemExit("bench: ragged persistent and per-vector results differ")
         res["speedup_vs_per_vector"] = round(ms_pv / ms, 2)
+        # the same per-vector launches replayed from one captured graph (no host launch cost)
+        o32.zero_()
+        o64.zero_()
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            bt.run_pervector(P)              # warm, outside the capture
+            torch.cuda.synchronize()
+            with torch.cuda.graph(g, stream=s):
+                bt.run_pervector(P, stream=s)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        o32.zero_()
+        o64.zero_()
+        _, ms_pg = timed(lambda: g.replay(), torch, 3, 1)
+        if not (np.array_equal(o32h, o32.cpu().numpy()) and np.array_equal(o64h, o64.cpu().numpy())):
+            raise SystemExit("bench: graph-replayed per-vector results differ")
+        res["per_vector_graph_replay"] = {"ms": round(ms_pg, 3), "nodes": len(segs)}
+        res["speedup_vs_per_vector_graph"] = round(ms_pg / ms, 2)
+        del g
         bt.close()
     log("ragged: %s" % res)
     return res

@@ -544,3 +544,26 @@ def test_crt_of_rns_product():
     X = words_to_ints(mg.crt(ctxs, prod).cpu().numpy())
     rows = [orc.mul("classic", 64, N, a[j], b[j]) for j, N in enumerate(wl.moduli)]
     assert X == orc.crt([[int(x) for x in r] for r in rows], wl.moduli)
+
+
+def test_tune_mul_and_cache(tmp_path, monkeypatch):
+    """The streaming tuner picks a candidate shape, keeps results exact and appends to the JSON cache."""
+    import json
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("MONT_TUNE_CACHE", str(cache))
+    N, w = 8380417, 32
+    c = mg.setup(N, w)
+    saved = mg.get_launch(mg.OP_MUL, w, "plantard")
+    try:
+        a, b = operands("plantard", w, N, 1 << 22, inp.rng(92, 1))
+        da, db = dev(a), dev(b)
+        out = torch.empty_like(da)
+        best = mg.tune_mul(c, da, db, out, variant="plantard")
+        assert best["unroll"] in (1, 2, 4) and best["nontemporal"] in (0, 1) and best["blocks_per_cu"] in (0, 4, 8, 16)
+        assert mg.get_launch(mg.OP_MUL, w, "plantard") == best
+        got = host(mg.mul(c, da, db, variant="plantard"))
+        assert np.array_equal(got, orc.mul("plantard", w, N, a, b))
+        rec = [json.loads(l) for l in cache.read_text().splitlines()]
+        assert rec[-1]["w"] == 32 and rec[-1]["variant"] == 2 and rec[-1]["unroll"] == best["unroll"]
+    finally:
+        mg.set_launch(mg.OP_MUL, w, "plantard", **saved)
