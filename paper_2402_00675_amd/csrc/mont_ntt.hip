@@ -8,9 +8,10 @@
 // and out, in place).
 //
 // One workgroup transforms one polynomial: coefficients are loaded into LDS
-// in bit-reversed order, log2(n) radix-2 Cooley-Tukey stages run with a
-// barrier between stages (each lane owns n/2/blockDim butterflies per stage),
-// and the result is written back (scaled by n^{-1} for the inverse).  The
+// in bit-reversed order together with the compact twiddles, the log2(n)
+// radix-2 Cooley-Tukey stages run two at a time as radix-4 steps in registers
+// (a barrier between steps), and the result is written back (scaled by n^{-1}
+// for the inverse).  The
 // twiddle product is a product by a fixed operand:
 //   classic  -- Montgomery product with w^k R mod N;
 //   Plantard -- Plantard product with b = -w^k 2^(2w) mod N through the
@@ -51,6 +52,48 @@ __device__ __forceinline__ El sub_mod(El u, El t, El N)
     return u >= t ? (El)(u - t) : (El)(u + (N - t));
 }
 
+// Twiddle as kept in LDS: what tw_mul needs of a KConst, nothing more.
+template <int W, int V>
+struct TwL {
+    uint64_t b;  // classic: w^k R mod N; Plantard (w <= 32): b N^{-1} mod 2^(2w)
+    __device__ __forceinline__ static TwL from(const KConst &k) { return {V == CLASSIC ? k.b : k.b1}; }
+    __device__ __forceinline__ KConst get() const
+    {
+        KConst k{};
+        if constexpr (V == CLASSIC)
+            k.b = b;
+        else
+            k.b1 = b;
+        return k;
+    }
+};
+template <>
+struct TwL<64, PLANTARD> {
+    uint64_t b1, b2;
+    __device__ __forceinline__ static TwL from(const KConst &k) { return {k.b1, k.b2}; }
+    __device__ __forceinline__ KConst get() const
+    {
+        KConst k{};
+        k.b1 = b1;
+        k.b2 = b2;
+        return k;
+    }
+};
+
+template <class R, int V, class T>
+__device__ __forceinline__ void butterfly(const R &red, typename R::E &u, typename R::E &v, const T &w,
+                                          typename R::E N)
+{
+    using El = typename R::E;
+    const El t = tw_mul<R, V>(red, v, w.get());
+    const El x = u;
+    u = add_mod<El>(x, t, N);
+    v = sub_mod<El>(x, t, N);
+}
+
+// LDS: n coefficients, then n/2 twiddles.  Pairs of radix-2 stages run as one
+// radix-4 step in registers (4 loads, 4 butterflies, 4 stores per group,
+// one barrier per two stages); an odd stage count ends with a radix-2 step.
 template <int W, int V>
 __global__ void __launch_bounds__(BLOCK)
     k_ntt(KCtx c, void *__restrict__ data, uint32_t log2n, const KConst *__restrict__ tw, KConst scale,
@@ -58,25 +101,48 @@ __global__ void __launch_bounds__(BLOCK)
 {
     using R = Red<W, V>;
     using El = typename R::E;
+    using T = TwL<W, V>;
     extern __shared__ __align__(16) unsigned char lds_raw[];
+    const uint32_t n = 1u << log2n;
     El *s = (El *)lds_raw;
+    T *ts = (T *)(lds_raw + ((n * sizeof(El) + 15) & ~(size_t)15));
     const R red(c);
     const El N = (El)c.N;
-    const uint32_t n = 1u << log2n;
     El *x = (El *)data + (uint64_t)blockIdx.x * n;
+    for (uint32_t i = threadIdx.x; i < n / 2; i += blockDim.x)
+        ts[i] = T::from(tw[i]);
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
         s[__brev(i) >> (32 - log2n)] = x[i];
     __syncthreads();
-    for (uint32_t lh = 0; lh < log2n; ++lh) {
+    uint32_t lh = 0;
+    for (; lh + 1 < log2n; lh += 2) {
+        const uint32_t len = 1u << lh;
+        const uint32_t sh0 = log2n - 1 - lh, sh1 = log2n - 2 - lh;  // twiddle strides of the two stages
+        for (uint32_t g = threadIdx.x; g < n / 4; g += blockDim.x) {
+            const uint32_t j = g & (len - 1);
+            const uint32_t i0 = ((g >> lh) << (lh + 2)) + j;
+            El a0 = s[i0], a1 = s[i0 + len], a2 = s[i0 + 2 * len], a3 = s[i0 + 3 * len];
+            const T w0 = ts[j << sh0];
+            butterfly<R, V>(red, a0, a1, w0, N);
+            butterfly<R, V>(red, a2, a3, w0, N);
+            butterfly<R, V>(red, a0, a2, ts[j << sh1], N);
+            butterfly<R, V>(red, a1, a3, ts[(j + len) << sh1], N);
+            s[i0] = a0;
+            s[i0 + len] = a1;
+            s[i0 + 2 * len] = a2;
+            s[i0 + 3 * len] = a3;
+        }
+        __syncthreads();
+    }
+    if (lh < log2n) {  // one radix-2 stage left
         const uint32_t len = 1u << lh;
         for (uint32_t b = threadIdx.x; b < n / 2; b += blockDim.x) {
             const uint32_t j = b & (len - 1);
             const uint32_t i0 = ((b >> lh) << (lh + 1)) + j;
-            const uint32_t i1 = i0 + len;
-            const El t = tw_mul<R, V>(red, s[i1], tw[j << (log2n - 1 - lh)]);
-            const El u = s[i0];
-            s[i0] = add_mod<El>(u, t, N);
-            s[i1] = sub_mod<El>(u, t, N);
+            El u = s[i0], v = s[i0 + len];
+            butterfly<R, V>(red, u, v, ts[j << (log2n - 1 - lh)], N);
+            s[i0] = u;
+            s[i0 + len] = v;
         }
         __syncthreads();
     }
@@ -184,8 +250,9 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
 {
     using El = typename Red<W, CLASSIC>::E;
     const uint32_t n = 1u << log2n;
-    const unsigned block = (unsigned)std::min<uint32_t>(BLOCK, std::max<uint32_t>(n / 2, 64));
-    const size_t lds = (size_t)n * sizeof(El);
+    const unsigned block = (unsigned)std::min<uint32_t>(BLOCK, std::max<uint32_t>(n / 4, 64));
+    const size_t tsz = variant == CLASSIC || W < 64 ? 8 : 16;
+    const size_t lds = (((size_t)n * sizeof(El) + 15) & ~(size_t)15) + (size_t)(n / 2) * tsz;
     if (variant == CLASSIC)
         hipLaunchKernelGGL((k_ntt<W, CLASSIC>), dim3((unsigned)batch), dim3(block), lds, s, k, data, log2n, t.dev,
                            t.scale, (uint32_t)inverse);

@@ -424,3 +424,60 @@ def test_dft_convolution_theorem():
     B = orc.dft(32, N, np.array(b, np.uint32), w)
     C = orc.dft(32, N, np.array(conv, np.uint32), w)
     assert [int(x) * int(y) % N for x, y in zip(A, B)] == [int(c) for c in C]
+
+
+# ------------------------------------------- algorithms step by step, wide words
+
+
+def _steps(variant, w, N, T, alpha=1):
+    """Each algorithm's steps with Python integers (Section 1 REDC, Algorithms 1-4)."""
+    if variant == "classic":
+        R = 1 << w
+        m = (T % R) * (R - pow(N, -1, R)) % R
+        t = (T + m * N) // R
+        return t - N if t >= N else t
+    if variant == "signed":
+        R = 1 << w
+        a1, a0 = T >> w, T & (R - 1)
+        m0 = orc.mods(a0 * pow(N, -1, R), R)
+        return a1 - ((m0 * N) >> w)
+    R = 1 << (2 * w)
+    if variant == "plantard":
+        m = T * pow(N, -1, R) % R
+        r = (((m >> w) + 1) * N) >> w
+        return 0 if r == N else r
+    m = orc.mods(T * orc.mods(pow(N, -1, R), R), R)
+    if variant == "signed_plantard":
+        q = (m + (1 << (w - 1))) >> w                  # round half up
+        return (q * N + (1 << (w - 1))) >> w
+    return (((m >> w) + (1 << alpha)) * N) >> w        # Algorithm 4
+
+
+@pytest.mark.parametrize("w", [16, 32, 64])
+def test_algorithm_steps_match_oracle_wide(w):
+    import random
+    rnd = random.Random(w)
+    for _ in range(40):
+        top = rnd.choice([w - 3, w - 1, w])
+        N = rnd.randrange(3, 1 << top) | 1
+        for variant in ["classic", "signed", "plantard", "signed_plantard", "signed_plantard_alpha"]:
+            c = orc.constants(N, w)
+            if variant == "signed_plantard_alpha":
+                if not N < 1 << (w - 2):
+                    continue
+            elif variant not in c["valid"]:
+                continue
+            R = 1 << w
+            lo, hi = {"classic": (0, R * N - 1), "signed": (-(N * R // 2) + 1, N * R // 2 - 1),
+                      "plantard": (0, N * N), "signed_plantard": (-(1 << (2 * w - 2)), 1 << (2 * w - 2)),
+                      "signed_plantard_alpha": (-4 * N * N, 4 * N * N)}[variant]
+            Ts = [lo, hi, 0] + [rnd.randint(lo, hi) for _ in range(60)]
+            if w < 64:
+                dt = {16: np.int32, 32: np.int64}[w] if variant.startswith("signed") else \
+                     {16: np.uint32, 32: np.uint64}[w]
+                arr = np.array(Ts, dtype=dt)
+            else:
+                arr = np.array([[t & (2**64 - 1), (t >> 64) & (2**64 - 1)] for t in Ts], dtype=np.uint64)
+            got = orc.redc(variant, w, N, arr, alpha=1)
+            want = [_steps(variant, w, N, T) for T in Ts]
+            assert [int(x) for x in got] == want, (variant, w, N)
