@@ -44,7 +44,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--sections", default=None,
                    help="comma list of secondary measurements to run (default: all unless --quick): "
-                        "copy,r32,const,crt,ntt,r16,pow,ragged,serving")
+                        "copy,r32,const,crt,ntt,r16,valu,pow,ragged,serving")
     p.add_argument("--ragged-segments", type=int, default=4096)
     p.add_argument("--serve-jobs", type=int, default=100_000)
     return p.parse_args()
@@ -207,7 +207,7 @@ def copy_ceiling(torch):
     return {"torch_copy_GBs": copy, "ref_2r1w_GBs": ref}
 
 
-SECTIONS = ("copy", "r32", "const", "crt", "ntt", "r16", "pow", "ragged", "serving")
+SECTIONS = ("copy", "r32", "const", "crt", "ntt", "r16", "valu", "pow", "ragged", "serving")
 
 
 def secondary(torch, mg, inp, args, sections):
@@ -304,6 +304,23 @@ def secondary(torch, mg, inp, args, sections):
         log("r16: mul %s, exhaustive %s" % (ex["r16_mul"], ex["r16_exhaustive_redc"]))
         del a, b, o, ro
 
+    if "valu" in sections:
+        # measured issue rates of the integer instructions the reductions are built from
+        from paper_2402_00675_amd._lib import VALU_KINDS
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        blocks, iters = cus * 8, 2048
+        o = torch.empty(blocks * 256, dtype=torch.int64, device=dev)
+        vr = {}
+        for kind, name in enumerate(VALU_KINDS):
+            _, ms = timed(lambda: mg.valu_ref(kind, iters, blocks, o), torch, 5, 2)
+            winst = blocks * 4 * iters * 32          # wave64 instructions
+            rate = winst / (ms * 1e-3)
+            vr[name] = {"G_wave_instr_s": round(rate / 1e9, 1), "T_lane_ops_s": round(rate * 64 / 1e12, 2),
+                        "cycles_per_instr_per_simd_at_2p4GHz": round(cus * 4 * 2.4e9 / rate, 2)}
+            log("valu %s: %s" % (name, vr[name]))
+        ex["valu_issue"] = vr
+        del o
+
     if "pow" in sections:
         # exponentiation: 2^22 elements, 31- and 62-bit odd moduli, uniform 64-bit exponents
         g = inp.rng(inp.W_SERVE, 7)
@@ -365,6 +382,17 @@ def serving(torch, mg, njobs):
     return res
 
 
+def _mismatch(o32, e32, o64, e64):
+    """Count of elements differing from the expected pools, with the first differing index of each."""
+    r = {"count": 0}
+    for name, o, e in (("w32", o32, e32), ("w64", o64, e64)):
+        d = np.flatnonzero(o.cpu().numpy() != e)
+        r["count"] += int(d.size)
+        if d.size:
+            r[name] = {"count": int(d.size), "first": int(d[0]), "last": int(d[-1])}
+    return r
+
+
 def ragged(torch, mg, inp, nseg):
     dev = torch.device("cuda:0")
     wl = inp.RaggedWorkload(nseg=nseg)
@@ -374,8 +402,9 @@ def ragged(torch, mg, inp, nseg):
     ctxs = [mg.setup(N, 64 if wd else 32) for N, wd in zip(mods, wide)]
     segs = [(i, mg.OP_MUL, "classic", int(n), int(o), int(o)) for i, (n, o) in enumerate(zip(lens, offs))]
     d = {k: torch.from_numpy(v).to(dev) for k, v in (("a32", a32), ("b32", b32), ("a64", a64), ("b64", b64))}
-    o32 = torch.empty_like(d["a32"])
-    o64 = torch.empty_like(d["a64"])
+    # zeroed: the padding between vectors is never written, and the pools are compared whole
+    o32 = torch.zeros_like(d["a32"])
+    o64 = torch.zeros_like(d["a64"])
     P = mg.pools([None, d["a32"], d["a64"]], [None, d["b32"], d["b64"]], [None, o32, o64])
     nbytes = 12 * int(sum(n for n, wd in zip(lens, wide) if not wd)) + 24 * int(sum(n for n, wd in zip(lens, wide) if wd))
     res = {"segments": nseg, "elements": int(lens.sum()), "bytes": nbytes}
@@ -404,13 +433,27 @@ def ragged(torch, mg, inp, nseg):
                 bt.run_pervector(P, stream=s)
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
-        o32.zero_()
-        o64.zero_()
+        # every replay is checked against the eager results, with eager work between replays
+        bad = []
+        for _ in range(3):
+            o32.zero_()
+            o64.zero_()
+            g.replay()
+            torch.cuda.synchronize()
+            bad.append(_mismatch(o32, o32h, o64, o64h))
         _, ms_pg = timed(lambda: g.replay(), torch, 3, 1)
-        if not (np.array_equal(o32h, o32.cpu().numpy()) and np.array_equal(o64h, o64.cpu().numpy())):
-            raise SystemExit("bench: graph-replayed per-vector results differ")
-        res["per_vector_graph_replay"] = {"ms": round(ms_pg, 3), "nodes": len(segs)}
-        res["speedup_vs_per_vector_graph"] = round(ms_pg / ms, 2)
+        bad.append(_mismatch(o32, o32h, o64, o64h))
+        bt.run_pervector(P)
+        torch.cuda.synchronize()
+        eager_after = _mismatch(o32, o32h, o64, o64h)
+        rep = {"ms": round(ms_pg, 3), "nodes": len(segs), "results_match": True}
+        if any(b["count"] for b in bad) or eager_after["count"]:
+            # recorded, not fatal: this is the comparison baseline, not the library's batched path
+            rep.update(results_match=False, mismatch_per_replay=bad, eager_after=eager_after)
+            log("ragged: graph-replayed per-vector results differ: %s, eager afterwards %s" % (bad, eager_after))
+        else:
+            res["speedup_vs_per_vector_graph"] = round(ms_pg / ms, 2)
+        res["per_vector_graph_replay"] = rep
         del g
         bt.close()
     log("ragged: %s" % res)

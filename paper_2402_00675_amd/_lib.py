@@ -96,6 +96,7 @@ def load():
         "mont_set_launch": (i32, [u32, u32, i32, P(LaunchStruct)]),
         "mont_get_launch": (i32, [u32, u32, i32, P(LaunchStruct)]),
         "mont_stream_ref": (i32, [vp, vp, vp, sz, vp]),
+        "mont_valu_ref": (i32, [u32, u32, u32, vp, vp]),
         "mont_last_error": (ctypes.c_char_p, []),
         "mont_version": (u32, []),
     }
@@ -285,6 +286,16 @@ def stream_ref(a, b, out, stream=None):
     check(load().mont_stream_ref(_dev(a, "a", 1, nbytes), _dev(b, "b", 1, nbytes), _dev(out, "out", 1, nbytes),
                                  nbytes, _stream(stream)))
     return out
+
+
+VALU_KINDS = ("v_mad_u64_u32", "v_mul_lo_u32", "v_mul_hi_u32", "v_mul_u32_u24", "v_add_u32",
+              "v_lshl_add_u64", "v_cndmask_b32", "v_cmp_le_u64", "v_lshrrev_b64", "v_sub_u32", "v_min_u32",
+              "v_mov_b32", "v_and_or_b32", "v_add3_u32")
+
+
+def valu_ref(kind: int, iters: int, blocks: int, out, stream=None):
+    """Issue-rate reference kernel: blocks x 256 lanes x iters x 32 instances of VALU_KINDS[kind]."""
+    check(load().mont_valu_ref(kind, iters, blocks, _dev(out, "out", 8, blocks * 256), _stream(stream)))
 
 
 def set_launch(op: int, w: int, variant, unroll=1, nontemporal=1, blocks_per_cu=0):

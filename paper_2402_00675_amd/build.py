@@ -28,6 +28,7 @@ SOURCES = [
     "mont_ref.hip",
     "mont_crt.hip",
     "mont_ntt.hip",
+    "mont_valu.hip",
     "mont_capi.cpp",
     "mont_setup.cpp",
     "mont_serve.cpp",

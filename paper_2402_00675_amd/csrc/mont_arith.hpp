@@ -101,6 +101,28 @@ __device__ __forceinline__ u128v sqr_64(uint64_t a)
 
 __device__ __forceinline__ uint64_t mulhi_64(uint64_t a, uint64_t b) { return mul_64x64(a, b).hi; }
 
+// 64 x 64 -> 128 for operands below 2^63 (a1, b1 < 2^31): the middle column
+// a0 b1 + a1 b0 + hi(a0 b0) stays below 2^64, so no carry word is needed.
+__device__ __forceinline__ u128v mul_63(uint64_t a, uint64_t b)
+{
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+    const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+    const uint64_t p00 = (uint64_t)a0 * b0;
+    const uint64_t mid = (uint64_t)a0 * b1 + ((uint64_t)a1 * b0 + (p00 >> 32));
+    const uint64_t hi = (uint64_t)a1 * b1 + (mid >> 32);
+    return {(mid << 32) | (uint32_t)p00, hi};
+}
+
+// a^2 for a below 2^63: 2 a1 fits in 32 bits and 2 a0 a1 + hi(a0^2) < 2^64.
+__device__ __forceinline__ u128v sqr_63(uint64_t a)
+{
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+    const uint64_t p00 = (uint64_t)a0 * a0;
+    const uint64_t mid = (uint64_t)a0 * (a1 << 1) + (p00 >> 32);
+    const uint64_t hi = (uint64_t)a1 * a1 + (mid >> 32);
+    return {(mid << 32) | (uint32_t)p00, hi};
+}
+
 // Signed product of two int64 as a 128-bit two's complement (lo, hi).
 __device__ __forceinline__ u128v mul_s64(int64_t a, int64_t b)
 {
@@ -255,6 +277,18 @@ struct Red<32, CLASSIC> {
     }
     __device__ __forceinline__ E mul(E a, E b) const { return redc((uint64_t)a * b); }
     __device__ __forceinline__ E sqr(E a) const { return mul(a, a); }
+    // Products for N < 2^31 and inputs below N: T + mN < 2^32 N + N^2 < 2^64,
+    // so one multiply-add forms the whole sum, its high word t = (T + mN)/R is
+    // below 2N < 2^32, and the unsigned min(t, t - N) is the reduced value
+    // (t - N wraps above t when t < N).
+    __device__ __forceinline__ E mul_fast(E a, E b) const
+    {
+        const uint64_t T = (uint64_t)a * b;
+        const uint32_t m = (uint32_t)T * np;
+        const uint32_t t = (uint32_t)(((uint64_t)m * N + T) >> 32);
+        return min(t, t - N);
+    }
+    __device__ __forceinline__ E sqr_fast(E a) const { return mul_fast(a, a); }
     __device__ __forceinline__ E mul_const(E a, const KConst &k) const
     {
         const uint64_t T = (uint64_t)a * (uint32_t)k.b;
@@ -396,19 +430,31 @@ struct Red<64, CLASSIC> {
     }
     // (T + mN)/R without the final subtraction: for N < 2^62 and inputs below
     // 2N the result is below 2N (the sum T + mN < 2RN never leaves 128 bits).
+    // With n1 = hi(N) < 2^30, floor(mN/R) = m1 n1 + hi(y) + hi(z) for
+    // x = m0 n0, y = m1 n0 + hi(x) < 2^64 and z = m0 n1 + lo(y) < 2^62 + 2^32,
+    // and th < 2^62, so every partial sum fits in 64 bits.
     __device__ __forceinline__ E reduce_lazy(uint64_t tl, uint64_t th) const
     {
         const uint64_t m = tl * np;
-        return th + mulhi_64(m, N) + (tl != 0u);
+        const uint32_t m0 = (uint32_t)m, m1 = (uint32_t)(m >> 32);
+        const uint32_t n0 = (uint32_t)N, n1 = (uint32_t)(N >> 32);
+        const uint64_t x = (uint64_t)m0 * n0;
+        const uint64_t y = (uint64_t)m1 * n0 + (x >> 32);
+        const uint64_t z = (uint64_t)m0 * n1 + (uint32_t)y;
+        const uint64_t w = (uint64_t)m1 * n1 + (th + (y >> 32));
+        // w + hi(z) + [tl != 0] as one 32-bit carry chain
+        unsigned int c;
+        const uint32_t lo = __builtin_addc((uint32_t)w, (uint32_t)(z >> 32), (unsigned int)(tl != 0u), &c);
+        return ((uint64_t)((uint32_t)(w >> 32) + c) << 32) | lo;
     }
-    __device__ __forceinline__ E mul_lazy(E a, E b) const
+    __device__ __forceinline__ E mul_fast(E a, E b) const
     {
-        const u128v p = mul_64x64(a, b);
+        const u128v p = mul_63(a, b);
         return reduce_lazy(p.lo, p.hi);
     }
-    __device__ __forceinline__ E sqr_lazy(E a) const
+    __device__ __forceinline__ E sqr_fast(E a) const
     {
-        const u128v p = sqr_64(a);
+        const u128v p = sqr_63(a);
         return reduce_lazy(p.lo, p.hi);
     }
     __device__ __forceinline__ E mul_const(E a, const KConst &k) const

@@ -104,13 +104,13 @@ hipError_t launch_pow(const KCtx &c, const void *x, const uint64_t *e, void *out
     L.blocks_per_cu = blocks_per_cu;
     const int U = unroll == 2 ? 2 : 1;
     dim3 grid((unsigned)grid_x(n, U, 1, L));
-    // lazy ladder (no per-product subtraction) when 4N <= R: 64-bit words with N < 2^62
-    const bool lazy = W == 64 && c.N < (1ull << 62);
-    if (lazy) {
+    // smaller-modulus ladder forms: lazy products for w = 64, N < 2^62; 32-bit registers for w = 32, N < 2^31
+    if (fast_ladder<W>(c.N)) {
+        constexpr bool F = W != 16;
         if (U == 2)
-            hipLaunchKernelGGL((k_pow<W, 2, W == 64>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
+            hipLaunchKernelGGL((k_pow<W, 2, F>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
         else
-            hipLaunchKernelGGL((k_pow<W, 1, W == 64>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
+            hipLaunchKernelGGL((k_pow<W, 1, F>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
     } else {
         if (U == 2)
             hipLaunchKernelGGL((k_pow<W, 2, false>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);

@@ -212,66 +212,91 @@ struct WideT<64> {
     __device__ static T128 of(uint64_t y) { return {y, 0}; }
 };
 
-// 2-bit fixed-window selection, branch-free.
-template <class El>
-__device__ __forceinline__ El sel4(uint32_t d, El t0, El t1, El t2, El t3)
+
+// Ladder products.  FAST selects the classic forms that need a smaller
+// modulus: for w = 64 and N < 2^62 the final subtraction is dropped ("lazy":
+// for 4N <= R and inputs below 2N, (T + mN)/R < 4N^2/R + N <= 2N, so every
+// result stays below 2N and is a valid input again); for w = 32 and N < 2^31
+// the whole reduction runs in 32-bit registers with fully reduced results.
+template <int W>
+__host__ __device__ __forceinline__ bool fast_ladder(uint64_t N)
 {
-    const El lo = (d & 1u) ? t1 : t0;
-    const El hi = (d & 1u) ? t3 : t2;
-    return (d & 2u) ? hi : lo;
+    return (W == 64 && N < (1ull << 62)) || (W == 32 && N < (1ull << 31));
 }
 
-// Montgomery products with the final subtraction dropped ("lazy"): for
-// 4N <= R and inputs below 2N, (T + mN)/R < 4N^2/R + N <= 2N, so every result
-// stays below 2N and is a valid input again.  Only the classic 64-bit form
-// provides them; they are used when N < 2^62.
-template <class R, bool LAZY>
+template <class R, bool FAST>
 struct Ladder {
     __device__ __forceinline__ static typename R::E mul(const R &r, typename R::E a, typename R::E b)
     {
-        if constexpr (LAZY)
-            return r.mul_lazy(a, b);
+        if constexpr (FAST)
+            return r.mul_fast(a, b);
         else
             return r.mul(a, b);
     }
     __device__ __forceinline__ static typename R::E sqr(const R &r, typename R::E a)
     {
-        if constexpr (LAZY)
-            return r.sqr_lazy(a);
+        if constexpr (FAST)
+            return r.sqr_fast(a);
         else
             return r.sqr(a);
     }
 };
 
-// x^e mod N: Montgomery form x R = REDC(x * (R^2 mod N)), a left-to-right
-// 2-bit fixed-window ladder of Montgomery products (every lane runs the same
-// 32 windows: no divergence), and REDC back to an ordinary residue; the
-// returned Montgomery-form value is below 2N (LAZY) or below N.
-template <class R, bool LAZY = false>
-__device__ __forceinline__ typename R::E pow_one(const R &red, typename R::E x, uint64_t k,
-                                                 typename R::E r2, typename R::E one)
+// x^e mod N for U elements of one lane, in lockstep (U independent product
+// chains per wave): Montgomery form x R = REDC(x * (R^2 mod N)), a
+// left-to-right 2-bit fixed-window ladder of Montgomery products (every lane
+// runs the same 32 windows: no divergence); the caller converts back with one
+// REDC.  The returned Montgomery-form values are below 2N (FAST with w = 64)
+// or below N.  Element u's four window entries (1, x, x^2, x^3 in Montgomery
+// form) live in LDS at tab[u * BLOCK + j * stride], j = 0..3: one LDS read per
+// window instead of a 4-way register select.  Lanes of a wave use adjacent
+// words of each entry row, so the reads are free of bank conflicts.
+template <class R, bool FAST, int U>
+__device__ __forceinline__ void pow_lanes(const R &red, const typename R::E (&x)[U], const uint64_t (&k)[U],
+                                          typename R::E r2, typename R::E one, typename R::E *tab, uint32_t stride,
+                                          typename R::E (&y)[U])
 {
     using El = typename R::E;
-    using L = Ladder<R, LAZY>;
-    const El x1 = L::mul(red, x, r2);
-    const El x2 = L::sqr(red, x1);
-    const El x3 = L::mul(red, x2, x1);
-    El y = sel4<El>((uint32_t)(k >> 62), one, x1, x2, x3);
+    using L = Ladder<R, FAST>;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        El *t = tab + u * BLOCK;
+        const El x1 = L::mul(red, x[u], r2);
+        const El x2 = L::sqr(red, x1);
+        const El x3 = L::mul(red, x2, x1);
+        t[0] = one;
+        t[stride] = x1;
+        t[2 * stride] = x2;
+        t[3 * stride] = x3;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        y[u] = tab[u * BLOCK + (uint32_t)(k[u] >> 62) * stride];
 #pragma unroll 4
     for (int s = 60; s >= 0; s -= 2) {
-        y = L::sqr(red, y);
-        y = L::sqr(red, y);
-        y = L::mul(red, y, sel4<El>((uint32_t)(k >> s) & 3u, one, x1, x2, x3));
+        El t[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            t[u] = tab[u * BLOCK + ((uint32_t)(k[u] >> s) & 3u) * stride];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            y[u] = L::sqr(red, y[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            y[u] = L::sqr(red, y[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            y[u] = L::mul(red, y[u], t[u]);
     }
-    return y;
 }
 
-template <int W, int U, bool LAZY>
+template <int W, int U, bool FAST>
 __global__ void __launch_bounds__(BLOCK)
     k_pow(KCtx c, const void *__restrict__ xin, const uint64_t *__restrict__ ein, void *__restrict__ out, uint64_t n)
 {
     using R = Red<W, CLASSIC>;
     using El = typename R::E;
+    __shared__ El tab[4 * BLOCK * U];
     const R red(c);
     const El r2 = (El)c.r2, one = (El)c.rmodn;
     const El *px = (const El *)xin;
@@ -287,9 +312,7 @@ __global__ void __launch_bounds__(BLOCK)
             k[u] = i < n ? ein[i] : 0;
         }
         El y[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            y[u] = pow_one<R, LAZY>(red, x[u], k[u], r2, one);
+        pow_lanes<R, FAST, U>(red, x, k, r2, one, tab + threadIdx.x, BLOCK * U, y);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint64_t i = base + (uint64_t)u * BLOCK;

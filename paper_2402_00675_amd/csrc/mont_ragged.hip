@@ -116,11 +116,19 @@ __device__ __forceinline__ void tile_pow(const KCtx &c, const DPools &P, uint64_
     const El *px = (const El *)P.in0[wc];
     const uint64_t *pe = (const uint64_t *)P.in1[wc] + (int64_t)(g1 - g0);
     El *po = (El *)P.out[wc];
-    const bool lazy = W == 64 && c.N < (1ull << 62);  // wave-uniform
+    __shared__ El tab[4 * BLOCK];
+    El *const mine = tab + threadIdx.x;
+    const bool fast = fast_ladder<W>(c.N);  // wave-uniform
     for (uint32_t i = threadIdx.x; i < cnt; i += BLOCK) {
         const uint64_t g = g0 + i;
-        const El y = lazy ? pow_one<R, W == 64>(red, px[g], pe[g], r2, one) : pow_one<R, false>(red, px[g], pe[g], r2, one);
-        po[g] = red.redc(WideT<W>::of(y));
+        const El x[1] = {px[g]};
+        const uint64_t k[1] = {pe[g]};
+        El y[1];
+        if (fast)
+            pow_lanes<R, W != 16, 1>(red, x, k, r2, one, mine, BLOCK, y);
+        else
+            pow_lanes<R, false, 1>(red, x, k, r2, one, mine, BLOCK, y);
+        po[g] = red.redc(WideT<W>::of(y[0]));
     }
 }
 
