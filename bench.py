@@ -154,10 +154,18 @@ def main():
         with cf.ThreadPoolExecutor(cores) as ex:
             list(ex.map(work, chunks))
         dt = time.perf_counter() - t0
+        # one thread over one chunk (2^22 products of row 0)
+        t1 = time.perf_counter()
+        work(chunks[0])
+        dt1 = time.perf_counter() - t1
+        n1 = chunks[0][2] - chunks[0][1]
         cpu = {"value": round(units / dt / 1e9, 4), "unit": "Gmodmul/s", "cores": cores, "kind": "oracle",
                "sample": "the whole headline workload (8 x 2^25 classic 64-bit products), "
-                         "128-bit '%%' oracle, %d threads, %.2f s" % (cores, dt)}
-        log("cpu oracle: %.3f Gmodmul/s on %d threads (%.2f s)" % (units / dt / 1e9, cores, dt))
+                         "128-bit '%%' oracle, %d threads, %.2f s" % (cores, dt),
+               "single_thread_value": round(n1 / dt1 / 1e9, 4),
+               "single_thread_sample": "2^22 products of row 0, %.3f s" % dt1}
+        log("cpu oracle: %.3f Gmodmul/s on %d threads (%.2f s), %.3f Gmodmul/s on one thread"
+            % (units / dt / 1e9, cores, dt, n1 / dt1 / 1e9))
     del a, b, out
     torch.cuda.empty_cache()
 
@@ -296,6 +304,23 @@ def secondary(torch, mg, inp, args, sections):
         o = torch.empty_like(a)
         _, ms = timed(lambda: mg.mul(c16, a, b, out=o), torch, 200, 20)
         ex["r16_mul"] = {"us": round(ms * 1e3, 2), "Gmodmul_s": round(w1.n / (ms * 1e-3) / 1e9, 1)}
+        # per-launch medians, warm and cold (a 512 MB write between launches evicts the
+        # 6 MiB working set from every cache level, the 256 MB last-level cache included)
+        flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+        for name, cold in (("warm", False), ("cold", True)):
+            t = []
+            for r in range(21):
+                if cold:
+                    flush.fill_(r + 1)
+                torch.cuda._sleep(100_000)   # GPU busy while the host enqueues: the events bracket the kernel only
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                mg.mul(c16, a, b, out=o)
+                e1.record()
+                torch.cuda.synchronize()
+                t.append(e0.elapsed_time(e1))
+            ex["r16_mul"][name + "_us_median"] = round(float(np.median(t[1:])) * 1e3, 2)
+        del flush
         total = w1.N << 16
         ro = torch.empty(total, dtype=torch.uint16, device=dev)
         _, ms = timed(lambda: mg.redc_range(c16, 0, total, out=ro), torch, 10, 2)

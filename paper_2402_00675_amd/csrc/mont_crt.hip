@@ -34,7 +34,26 @@ struct CrtTab {
     uint64_t cbar[CRT_MAX][CRT_MAX];  // [j][i] = (N_j^{-1} mod N_i) R mod N_i, j < i
 };
 
-template <int K, bool NARROW>
+// a N + c for N < 2^62 (n1 < 2^30) and any 64-bit a, c; the sum is below
+// 2^127.  Partial sums: a0 n0 + lo(c) < 2^64, t1 = a0 n1 + hi(p00) < 2^62 +
+// 2^32, mid = a1 n0 + lo(t1) + hi(c) < 2^64, hi = a1 n1 + hi(t1) + hi(mid)
+// < 2^63: no carry word anywhere.
+__device__ __forceinline__ u128v mul_add_62(uint64_t a, uint64_t N, uint64_t c)
+{
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+    const uint32_t n0 = (uint32_t)N, n1 = (uint32_t)(N >> 32);
+    const uint64_t p00 = (uint64_t)a0 * n0 + (uint32_t)c;
+    const uint64_t t1 = (uint64_t)a0 * n1 + (p00 >> 32);
+    const uint64_t mid = (uint64_t)a1 * n0 + ((uint64_t)(uint32_t)t1 + (c >> 32));
+    const uint64_t hi = (uint64_t)a1 * n1 + ((t1 >> 32) + (mid >> 32));
+    return {(mid << 32) | (uint32_t)p00, hi};
+}
+
+// FORM 0: any coprime odd moduli.  FORM 1 (NARROW): every modulus below twice
+// every other one.  FORM 2: NARROW and every modulus below 2^62, which admits
+// the lazy Montgomery product (result below 2N, one conditional subtraction
+// per digit) and carry-free Horner steps.
+template <int K, int FORM>
 __global__ void __launch_bounds__(BLOCK)
     k_crt(CrtTab tab, const uint64_t *__restrict__ res, uint64_t ld, uint64_t n, uint64_t *__restrict__ out)
 {
@@ -52,7 +71,12 @@ __global__ void __launch_bounds__(BLOCK)
 #pragma unroll
         for (int j = 0; j < i; ++j) {
             const uint64_t cb = tab.cbar[j][i];
-            if constexpr (NARROW) {
+            if constexpr (FORM == 2) {
+                const uint64_t vj = v[j] >= c.N ? v[j] - c.N : v[j];
+                const uint64_t d = t >= vj ? t - vj : t + (c.N - vj);
+                const uint64_t u = red.mul_fast(d, cb);   // d, cb < N < 2^62: u < 2N
+                t = u >= c.N ? u - c.N : u;
+            } else if constexpr (FORM == 1) {
                 const uint64_t vj = v[j] >= c.N ? v[j] - c.N : v[j];
                 const uint64_t d = t >= vj ? t - vj : t + (c.N - vj);
                 t = red.mul(d, cb);
@@ -76,10 +100,16 @@ __global__ void __launch_bounds__(BLOCK)
         // acc holds K - 1 - i words; acc * N_i + v_i fills K - i words
 #pragma unroll
         for (int w = 0; w < K - 1 - i; ++w) {
-            const u128v p = mul_64x64(acc[w], Ni);
-            const uint64_t lo = p.lo + carry;
-            carry = p.hi + (lo < carry);
-            acc[w] = lo;
+            if constexpr (FORM == 2) {
+                const u128v p = mul_add_62(acc[w], Ni, carry);
+                acc[w] = p.lo;
+                carry = p.hi;
+            } else {
+                const u128v p = mul_64x64(acc[w], Ni);
+                const uint64_t lo = p.lo + carry;
+                carry = p.hi + (lo < carry);
+                acc[w] = lo;
+            }
         }
         acc[K - 1 - i] = carry;
     }
@@ -102,14 +132,16 @@ __global__ void __launch_bounds__(BLOCK)
 }
 
 template <int K>
-static void go_crt(const CrtTab &t, bool narrow, const uint64_t *res, uint64_t ld, uint64_t n, uint64_t *out,
+static void go_crt(const CrtTab &t, int form, const uint64_t *res, uint64_t ld, uint64_t n, uint64_t *out,
                    hipStream_t s)
 {
     const unsigned grid = (unsigned)((n + BLOCK - 1) / BLOCK);
-    if (narrow)
-        hipLaunchKernelGGL((k_crt<K, true>), dim3(grid), dim3(BLOCK), 0, s, t, res, ld, n, out);
+    if (form == 2)
+        hipLaunchKernelGGL((k_crt<K, 2>), dim3(grid), dim3(BLOCK), 0, s, t, res, ld, n, out);
+    else if (form == 1)
+        hipLaunchKernelGGL((k_crt<K, 1>), dim3(grid), dim3(BLOCK), 0, s, t, res, ld, n, out);
     else
-        hipLaunchKernelGGL((k_crt<K, false>), dim3(grid), dim3(BLOCK), 0, s, t, res, ld, n, out);
+        hipLaunchKernelGGL((k_crt<K, 0>), dim3(grid), dim3(BLOCK), 0, s, t, res, ld, n, out);
 }
 
 typedef unsigned __int128 u128;
@@ -167,6 +199,7 @@ extern "C" mont_status_t mont_crt(const mont_ctx_t *ctxs, uint32_t k, const void
     if (!res || !out || ((uintptr_t)out & 15u))
         return fail(MONT_E_INVAL, "null residues or output not 16-byte aligned");
     const bool narrow = (u128)hi < 2 * (u128)lo;  // every v_j < 2 N_i: one conditional subtraction reduces it
+    const int form = narrow ? (hi < (1ull << 62) ? 2 : 1) : 0;
     if ((n + BLOCK - 1) / BLOCK > 0x7fffffffull)
         return fail(MONT_E_INVAL, "too many elements");
     hipStream_t s = (hipStream_t)stream;
@@ -175,7 +208,7 @@ extern "C" mont_status_t mont_crt(const mont_ctx_t *ctxs, uint32_t k, const void
     switch (k) {
 #define C(K)                                \
     case K:                                 \
-        go_crt<K>(t, narrow, r, ld, n, o, s); \
+        go_crt<K>(t, form, r, ld, n, o, s);   \
         break;
         C(1) C(2) C(3) C(4) C(5) C(6) C(7) C(8) C(9) C(10) C(11) C(12) C(13) C(14) C(15) C(16)
 #undef C

@@ -30,13 +30,23 @@
 
 namespace mont {
 
-template <class R, int V>
+// FAST (classic twiddles, N < 2^31 at w = 32 or N < 2^62 at w = 64): the
+// ladder's smaller-modulus products; the 64-bit one is lazy (below 2N), so one
+// conditional subtraction follows.
+template <class R, int V, bool FAST>
 __device__ __forceinline__ typename R::E tw_mul(const R &red, typename R::E a, const KConst &w)
 {
-    if constexpr (V == CLASSIC)
-        return red.mul(a, (typename R::E)w.b);
-    else
+    using El = typename R::E;
+    if constexpr (V == CLASSIC && FAST && sizeof(El) == 8) {
+        const El u = red.mul_fast(a, (El)w.b);
+        return u >= red.N ? u - red.N : u;
+    } else if constexpr (V == CLASSIC && FAST) {
+        return red.mul_fast(a, (El)w.b);
+    } else if constexpr (V == CLASSIC) {
+        return red.mul(a, (El)w.b);
+    } else {
         return red.mul_const(a, w);
+    }
 }
 
 template <class El>
@@ -80,12 +90,12 @@ struct TwL<64, PLANTARD> {
     }
 };
 
-template <class R, int V, class T>
+template <class R, int V, bool FAST, class T>
 __device__ __forceinline__ void butterfly(const R &red, typename R::E &u, typename R::E &v, const T &w,
                                           typename R::E N)
 {
     using El = typename R::E;
-    const El t = tw_mul<R, V>(red, v, w.get());
+    const El t = tw_mul<R, V, FAST>(red, v, w.get());
     const El x = u;
     u = add_mod<El>(x, t, N);
     v = sub_mod<El>(x, t, N);
@@ -94,7 +104,7 @@ __device__ __forceinline__ void butterfly(const R &red, typename R::E &u, typena
 // LDS: n coefficients, then n/2 twiddles.  Pairs of radix-2 stages run as one
 // radix-4 step in registers (4 loads, 4 butterflies, 4 stores per group,
 // one barrier per two stages); an odd stage count ends with a radix-2 step.
-template <int W, int V>
+template <int W, int V, bool FAST>
 __global__ void __launch_bounds__(BLOCK)
     k_ntt(KCtx c, void *__restrict__ data, uint32_t log2n, const KConst *__restrict__ tw, KConst scale,
           uint32_t do_scale)
@@ -123,10 +133,10 @@ __global__ void __launch_bounds__(BLOCK)
             const uint32_t i0 = ((g >> lh) << (lh + 2)) + j;
             El a0 = s[i0], a1 = s[i0 + len], a2 = s[i0 + 2 * len], a3 = s[i0 + 3 * len];
             const T w0 = ts[j << sh0];
-            butterfly<R, V>(red, a0, a1, w0, N);
-            butterfly<R, V>(red, a2, a3, w0, N);
-            butterfly<R, V>(red, a0, a2, ts[j << sh1], N);
-            butterfly<R, V>(red, a1, a3, ts[(j + len) << sh1], N);
+            butterfly<R, V, FAST>(red, a0, a1, w0, N);
+            butterfly<R, V, FAST>(red, a2, a3, w0, N);
+            butterfly<R, V, FAST>(red, a0, a2, ts[j << sh1], N);
+            butterfly<R, V, FAST>(red, a1, a3, ts[(j + len) << sh1], N);
             s[i0] = a0;
             s[i0 + len] = a1;
             s[i0 + 2 * len] = a2;
@@ -140,14 +150,14 @@ __global__ void __launch_bounds__(BLOCK)
             const uint32_t j = b & (len - 1);
             const uint32_t i0 = ((b >> lh) << (lh + 1)) + j;
             El u = s[i0], v = s[i0 + len];
-            butterfly<R, V>(red, u, v, ts[j << (log2n - 1 - lh)], N);
+            butterfly<R, V, FAST>(red, u, v, ts[j << (log2n - 1 - lh)], N);
             s[i0] = u;
             s[i0 + len] = v;
         }
         __syncthreads();
     }
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
-        x[i] = do_scale ? tw_mul<R, V>(red, s[i], scale) : s[i];
+        x[i] = do_scale ? tw_mul<R, V, FAST>(red, s[i], scale) : s[i];
 }
 
 typedef unsigned __int128 u128;
@@ -253,12 +263,15 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
     const unsigned block = (unsigned)std::min<uint32_t>(BLOCK, std::max<uint32_t>(n / 4, 64));
     const size_t tsz = variant == CLASSIC || W < 64 ? 8 : 16;
     const size_t lds = (((size_t)n * sizeof(El) + 15) & ~(size_t)15) + (size_t)(n / 2) * tsz;
-    if (variant == CLASSIC)
-        hipLaunchKernelGGL((k_ntt<W, CLASSIC>), dim3((unsigned)batch), dim3(block), lds, s, k, data, log2n, t.dev,
-                           t.scale, (uint32_t)inverse);
-    else
-        hipLaunchKernelGGL((k_ntt<W, PLANTARD>), dim3((unsigned)batch), dim3(block), lds, s, k, data, log2n,
+    if (variant == CLASSIC && fast_ladder<W>(k.N))
+        hipLaunchKernelGGL((k_ntt<W, CLASSIC, W != 16>), dim3((unsigned)batch), dim3(block), lds, s, k, data, log2n,
                            t.dev, t.scale, (uint32_t)inverse);
+    else if (variant == CLASSIC)
+        hipLaunchKernelGGL((k_ntt<W, CLASSIC, false>), dim3((unsigned)batch), dim3(block), lds, s, k, data, log2n,
+                           t.dev, t.scale, (uint32_t)inverse);
+    else
+        hipLaunchKernelGGL((k_ntt<W, PLANTARD, false>), dim3((unsigned)batch), dim3(block), lds, s, k, data,
+                           log2n, t.dev, t.scale, (uint32_t)inverse);
     return hipGetLastError();
 }
 

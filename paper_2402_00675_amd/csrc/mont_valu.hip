@@ -21,12 +21,15 @@ __global__ void __launch_bounds__(BLOCK) k_valu(uint32_t iters, uint32_t seed, u
     }
     const uint32_t m = seed | 1u;
     const uint64_t m64 = ((uint64_t)seed << 32) | m;
+    uint64_t cy[8] = {};  // kind 15: per-chain carry masks (scalar register pairs)
     // Exact instruction streams: a self-referential multiply-add for
     // v_mad_u64_u32, register-only ALU inline assembly for the others (the
     // compiler would otherwise fold repeated products algebraically).  Kinds 7
-    // (compares writing the condition mask VCC, which nothing reads) and 11
-    // (moves) put a round's eight instructions in one statement: the compiler
-    // adds a wait state after every separate statement of those forms.
+    // (compares writing the condition mask VCC, which nothing reads), 11
+    // (moves), 14 (carry-out adds, VCC written and never read), 15 (carry
+    // chains, one scalar register pair per chain) and 20 (compares) put a round's eight
+    // instructions in one statement: the compiler adds a wait state after
+    // every separate statement of those forms.
     for (uint32_t i = 0; i < iters; ++i) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -72,8 +75,47 @@ __global__ void __launch_bounds__(BLOCK) k_valu(uint32_t iters, uint32_t seed, u
                                      : "v"(m));
                 } else if constexpr (KIND == 12) {
                     asm volatile("v_and_or_b32 %0, %0, %1, %1" : "+v"(x[c]) : "v"(m));
-                } else {
+                } else if constexpr (KIND == 13) {
                     asm volatile("v_add3_u32 %0, %0, %1, %1" : "+v"(x[c]) : "v"(m));
+                } else if constexpr (KIND == 16) {
+                    asm volatile("v_or_b32 %0, %0, %1" : "+v"(x[c]) : "v"(m));
+                } else if constexpr (KIND == 17) {
+                    asm volatile("v_and_b32 %0, %0, %1" : "+v"(x[c]) : "v"(m));
+                } else if constexpr (KIND == 18) {
+                    asm volatile("v_lshlrev_b32 %0, 1, %0" : "+v"(x[c]));
+                } else if constexpr (KIND == 19) {
+                    asm volatile("v_alignbit_b32 %0, %0, %1, 31" : "+v"(x[c]) : "v"(m));
+                } else if constexpr (KIND == 20) {
+                    if (c == 0)
+                        asm volatile("v_cmp_ne_u32_e32 vcc, 0, %0\n\tv_cmp_ne_u32_e32 vcc, 0, %1\n\t"
+                                     "v_cmp_ne_u32_e32 vcc, 0, %2\n\tv_cmp_ne_u32_e32 vcc, 0, %3\n\t"
+                                     "v_cmp_ne_u32_e32 vcc, 0, %4\n\tv_cmp_ne_u32_e32 vcc, 0, %5\n\t"
+                                     "v_cmp_ne_u32_e32 vcc, 0, %6\n\tv_cmp_ne_u32_e32 vcc, 0, %7"
+                                     :
+                                     : "v"(x[0]), "v"(x[1]), "v"(x[2]), "v"(x[3]), "v"(x[4]), "v"(x[5]), "v"(x[6]),
+                                       "v"(x[7])
+                                     : "vcc");
+                } else if constexpr (KIND == 14) {
+                    if (c == 0)
+                        asm volatile("v_add_co_u32 %0, vcc, %0, %8\n\tv_add_co_u32 %1, vcc, %1, %8\n\t"
+                                     "v_add_co_u32 %2, vcc, %2, %8\n\tv_add_co_u32 %3, vcc, %3, %8\n\t"
+                                     "v_add_co_u32 %4, vcc, %4, %8\n\tv_add_co_u32 %5, vcc, %5, %8\n\t"
+                                     "v_add_co_u32 %6, vcc, %6, %8\n\tv_add_co_u32 %7, vcc, %7, %8"
+                                     : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]),
+                                       "+v"(x[6]), "+v"(x[7])
+                                     : "v"(m)
+                                     : "vcc");
+                } else {
+                    // carry in and out through one scalar register pair per chain
+                    if (c == 0)
+                        asm volatile("v_addc_co_u32_e64 %0, %8, %0, %16, %8\n\tv_addc_co_u32_e64 %1, %9, %1, %16, %9\n\t"
+                                     "v_addc_co_u32_e64 %2, %10, %2, %16, %10\n\tv_addc_co_u32_e64 %3, %11, %3, %16, %11\n\t"
+                                     "v_addc_co_u32_e64 %4, %12, %4, %16, %12\n\tv_addc_co_u32_e64 %5, %13, %5, %16, %13\n\t"
+                                     "v_addc_co_u32_e64 %6, %14, %6, %16, %14\n\tv_addc_co_u32_e64 %7, %15, %7, %16, %15"
+                                     : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]),
+                                       "+v"(x[6]), "+v"(x[7]), "+s"(cy[0]), "+s"(cy[1]), "+s"(cy[2]), "+s"(cy[3]),
+                                       "+s"(cy[4]), "+s"(cy[5]), "+s"(cy[6]), "+s"(cy[7])
+                                     : "v"(m));
                 }
             }
         }
@@ -81,7 +123,7 @@ __global__ void __launch_bounds__(BLOCK) k_valu(uint32_t iters, uint32_t seed, u
     uint64_t acc = 0;
 #pragma unroll
     for (int c = 0; c < 8; ++c)
-        acc ^= y[c] ^ x[c];
+        acc ^= y[c] ^ x[c] ^ cy[c];
     out[t] = acc;
 }
 
@@ -91,13 +133,14 @@ using namespace mont;
 
 extern "C" mont_status_t mont_valu_ref(uint32_t kind, uint32_t iters, uint32_t blocks, void *out, void *stream)
 {
-    if (kind > 13 || !out || !blocks || blocks > (1u << 20))
-        return fail(MONT_E_INVAL, "kind 0..13, 1 <= blocks <= 2^20, output of blocks * 256 uint64");
+    if (kind > 20 || !out || !blocks || blocks > (1u << 20))
+        return fail(MONT_E_INVAL, "kind 0..20, 1 <= blocks <= 2^20, output of blocks * 256 uint64");
     hipStream_t s = (hipStream_t)stream;
     uint64_t *o = (uint64_t *)out;
     typedef void (*kfn)(uint32_t, uint32_t, uint64_t *);
-    static const kfn kinds[14] = {k_valu<0>, k_valu<1>, k_valu<2>,  k_valu<3>,  k_valu<4>,  k_valu<5>,  k_valu<6>,
-                                  k_valu<7>, k_valu<8>, k_valu<9>, k_valu<10>, k_valu<11>, k_valu<12>, k_valu<13>};
+    static const kfn kinds[21] = {k_valu<0>,  k_valu<1>,  k_valu<2>,  k_valu<3>,  k_valu<4>,  k_valu<5>,  k_valu<6>,
+                                  k_valu<7>,  k_valu<8>,  k_valu<9>,  k_valu<10>, k_valu<11>, k_valu<12>, k_valu<13>,
+                                  k_valu<14>, k_valu<15>, k_valu<16>, k_valu<17>, k_valu<18>, k_valu<19>, k_valu<20>};
     hipLaunchKernelGGL(kinds[kind], dim3(blocks), dim3(BLOCK), 0, s, iters, 12345u, o);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? MONT_OK : hip_fail(e, "mont_valu_ref launch");

@@ -33,6 +33,8 @@ class JobStream:
     """Jobs of one stream with their host buffers (kept alive here)."""
 
     def __init__(self, torch, njobs, seed_rep=0, distinct_outputs=False, hi=None):
+        """distinct_outputs: True (every job), False (all jobs write one sink buffer per
+        word size) or a collection of job indices that get their own output buffers."""
         wl = inp.ServeWorkload()
         if hi is not None:
             wl.hi = hi
@@ -56,7 +58,8 @@ class JobStream:
         self.offs = offs
         self.jobs = (_lib.JobStruct * njobs)()
         self.outs = {}
-        if not distinct_outputs:
+        own = set(range(njobs)) if distinct_outputs is True else set(distinct_outputs or ())
+        if len(own) < njobs:
             self.sink = {32: _pinned(torch, P, torch.uint32), 64: _pinned(torch, P, torch.uint64)}
         esz = {32: 4, 64: 8}
         for i in range(njobs):
@@ -69,7 +72,7 @@ class JobStream:
                 op, in1 = _lib.OP_MUL, b.data_ptr() + o * esz[w]
             else:
                 op, in1 = _lib.OP_POW, self.exps.data_ptr() + o * 8
-            if distinct_outputs:
+            if i in own:
                 out_t = _pinned(torch, n, torch.uint32 if w == 32 else torch.uint64)
                 self.outs[i] = out_t
                 out = out_t.data_ptr()

@@ -34,6 +34,7 @@ CASES = [
     (16, 3329, [2, 8]),
     (32, 8380417, [1, 4, 8, 12]),
     (32, 2013265921, [6, 11]),
+    (32, 3221225473, [5, 10]),                # above 2^31: the general classic product
     (64, prime_1_mod(62, 12, 1), [2, 8, 12]),
     (64, GOLDILOCKS, [3, 9]),
 ]

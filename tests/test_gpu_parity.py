@@ -501,11 +501,13 @@ def words_to_ints(w):
 
 
 @pytest.mark.parametrize("k", [1, 2, 3, 8, 11, 16])
-@pytest.mark.parametrize("kind", ["primes60", "mixed"])
+@pytest.mark.parametrize("kind", ["primes60", "primes64", "mixed"])
 def test_crt_parity(k, kind):
     g = inp.rng(94, k)
     if kind == "primes60":
-        mods = inp.random_primes(g, 60, k)          # all within a factor 2: one-subtraction path
+        mods = inp.random_primes(g, 60, k)          # within a factor 2 and below 2^62: lazy products
+    elif kind == "primes64":
+        mods = inp.random_primes(g, 64, k)          # within a factor 2, above 2^63: one-subtraction path
     else:
         pool = [3, 5, 7, 65537, 1000000007, (1 << 61) - 1, (1 << 62) - 57, (1 << 64) - 59, 998244353,
                 4294967291, 2147483647, 18446744073709551557 - 2 * 0, 1099511627791, 127, 8191, 131071]
