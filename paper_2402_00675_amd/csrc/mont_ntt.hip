@@ -62,11 +62,12 @@ __device__ __forceinline__ El sub_mod(El u, El t, El N)
     return u >= t ? (El)(u - t) : (El)(u + (N - t));
 }
 
-// Twiddle as kept in LDS: what tw_mul needs of a KConst, nothing more.
+// Twiddle as kept in device memory and LDS: what tw_mul needs of a KConst,
+// nothing more (8 bytes, 16 for the 64-bit Plantard form).
 template <int W, int V>
 struct TwL {
     uint64_t b;  // classic: w^k R mod N; Plantard (w <= 32): b N^{-1} mod 2^(2w)
-    __device__ __forceinline__ static TwL from(const KConst &k) { return {V == CLASSIC ? k.b : k.b1}; }
+    static TwL from(const KConst &k) { return {V == CLASSIC ? k.b : k.b1}; }
     __device__ __forceinline__ KConst get() const
     {
         KConst k{};
@@ -80,7 +81,7 @@ struct TwL {
 template <>
 struct TwL<64, PLANTARD> {
     uint64_t b1, b2;
-    __device__ __forceinline__ static TwL from(const KConst &k) { return {k.b1, k.b2}; }
+    static TwL from(const KConst &k) { return {k.b1, k.b2}; }
     __device__ __forceinline__ KConst get() const
     {
         KConst k{};
@@ -104,14 +105,18 @@ __device__ __forceinline__ void butterfly(const R &red, typename R::E &u, typena
 // LDS: n coefficients, then n/2 twiddles.  Pairs of radix-2 stages run as one
 // radix-4 step in registers (4 loads, 4 butterflies, 4 stores per group,
 // one barrier per two stages); an odd stage count ends with a radix-2 step.
+// With VEC (16-byte aligned polynomials of at least 16 bytes) coefficients
+// move between HBM and LDS in 16-byte chunks; the bit-reversed LDS writes of
+// a chunk's lanes then fall on distinct words.
 template <int W, int V, bool FAST>
 __global__ void __launch_bounds__(BLOCK)
-    k_ntt(KCtx c, void *__restrict__ data, uint32_t log2n, const KConst *__restrict__ tw, KConst scale,
-          uint32_t do_scale)
+    k_ntt(KCtx c, void *__restrict__ data, uint32_t log2n, const TwL<W, V> *__restrict__ tw, KConst scale,
+          uint32_t do_scale, uint32_t vec)
 {
     using R = Red<W, V>;
     using El = typename R::E;
     using T = TwL<W, V>;
+    constexpr int E = 16 / (int)sizeof(El);
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const uint32_t n = 1u << log2n;
     El *s = (El *)lds_raw;
@@ -120,9 +125,19 @@ __global__ void __launch_bounds__(BLOCK)
     const El N = (El)c.N;
     El *x = (El *)data + (uint64_t)blockIdx.x * n;
     for (uint32_t i = threadIdx.x; i < n / 2; i += blockDim.x)
-        ts[i] = T::from(tw[i]);
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
-        s[__brev(i) >> (32 - log2n)] = x[i];
+        ts[i] = tw[i];
+    if (vec) {
+        for (uint32_t ci = threadIdx.x; ci < n / E; ci += blockDim.x) {
+            El v[E];
+            load_chunk<El, E, true>(x + ci * E, v);
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                s[__brev(ci * E + e) >> (32 - log2n)] = v[e];
+        }
+    } else {
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
+            s[__brev(i) >> (32 - log2n)] = x[i];
+    }
     __syncthreads();
     uint32_t lh = 0;
     for (; lh + 1 < log2n; lh += 2) {
@@ -156,8 +171,18 @@ __global__ void __launch_bounds__(BLOCK)
         }
         __syncthreads();
     }
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
-        x[i] = do_scale ? tw_mul<R, V, FAST>(red, s[i], scale) : s[i];
+    if (vec) {
+        for (uint32_t ci = threadIdx.x; ci < n / E; ci += blockDim.x) {
+            El v[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                v[e] = do_scale ? tw_mul<R, V, FAST>(red, s[ci * E + e], scale) : s[ci * E + e];
+            store_chunk<El, E, true>(x + ci * E, v);
+        }
+    } else {
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
+            x[i] = do_scale ? tw_mul<R, V, FAST>(red, s[i], scale) : s[i];
+    }
 }
 
 typedef unsigned __int128 u128;
@@ -211,7 +236,7 @@ struct TwKey {
 };
 
 struct TwEntry {
-    KConst *dev = nullptr;
+    void *dev = nullptr;  // n/2 compact twiddles (TwL of the width and variant)
     KConst scale{};
 };
 
@@ -242,9 +267,22 @@ static mont_status_t twiddles(const mont_ctx_t &c, int variant, uint64_t root, u
     // n^{-1} mod N: N odd, so (N + 1)/2 is 2^{-1}
     const uint64_t half = (uint64_t)(((u128)c.N + 1) / 2);
     e.scale = twiddle_const(c, variant, powmod(half, log2n, c.N));
-    if (hipMalloc(&e.dev, h.size() * sizeof(KConst)) != hipSuccess)
+    // compact device form: b (classic), b N^{-1} mod 2^(2w) (Plantard, w <= 32), its two words (w = 64)
+    const bool two = variant != CLASSIC && c.w == 64;
+    std::vector<uint64_t> hc;
+    hc.reserve(h.size() * (two ? 2 : 1));
+    for (const KConst &q : h) {
+        if (variant == CLASSIC) {
+            hc.push_back(q.b);
+        } else {
+            hc.push_back(q.b1);
+            if (two)
+                hc.push_back(q.b2);
+        }
+    }
+    if (hipMalloc(&e.dev, hc.size() * sizeof(uint64_t)) != hipSuccess)
         return fail(MONT_E_NOMEM, "twiddle table");
-    const hipError_t err = hipMemcpy(e.dev, h.data(), h.size() * sizeof(KConst), hipMemcpyHostToDevice);
+    const hipError_t err = hipMemcpy(e.dev, hc.data(), hc.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
     if (err != hipSuccess) {
         (void)hipFree(e.dev);
         return hip_fail(err, "twiddle upload");
@@ -263,15 +301,18 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
     const unsigned block = (unsigned)std::min<uint32_t>(BLOCK, std::max<uint32_t>(n / 4, 64));
     const size_t tsz = variant == CLASSIC || W < 64 ? 8 : 16;
     const size_t lds = (((size_t)n * sizeof(El) + 15) & ~(size_t)15) + (size_t)(n / 2) * tsz;
+    // 16-byte chunks when every polynomial starts on a 16-byte boundary
+    const uint32_t vec = ((uintptr_t)data % 16 == 0 && ((size_t)n * sizeof(El)) % 16 == 0) ? 1u : 0u;
+    const uint32_t inv = (uint32_t)inverse;
     if (variant == CLASSIC && fast_ladder<W>(k.N))
         hipLaunchKernelGGL((k_ntt<W, CLASSIC, W != 16>), dim3((unsigned)batch), dim3(block), lds, s, k, data, log2n,
-                           t.dev, t.scale, (uint32_t)inverse);
+                           (const TwL<W, CLASSIC> *)t.dev, t.scale, inv, vec);
     else if (variant == CLASSIC)
         hipLaunchKernelGGL((k_ntt<W, CLASSIC, false>), dim3((unsigned)batch), dim3(block), lds, s, k, data, log2n,
-                           t.dev, t.scale, (uint32_t)inverse);
+                           (const TwL<W, CLASSIC> *)t.dev, t.scale, inv, vec);
     else
         hipLaunchKernelGGL((k_ntt<W, PLANTARD, false>), dim3((unsigned)batch), dim3(block), lds, s, k, data,
-                           log2n, t.dev, t.scale, (uint32_t)inverse);
+                           log2n, (const TwL<W, PLANTARD> *)t.dev, t.scale, inv, vec);
     return hipGetLastError();
 }
 

@@ -76,3 +76,22 @@ def test_ntt_rejects_bad_root_and_variant():
     with pytest.raises(mg.MontError) as e:
         mg.ntt(c, d, root(12289, 16), variant="signed")
     assert e.value.code == -3
+
+
+@pytest.mark.parametrize("w,N", [(16, 12289), (32, 8380417), (64, prime_1_mod(62, 12, 1))])
+def test_ntt_unaligned_rows(w, N):
+    """Rows that do not start on a 16-byte boundary take the element-wise path."""
+    c = mg.setup(N, w)
+    g = inp.rng(93, 500 + w)
+    n, batch = 64, 5
+    wr = root(N, n)
+    x = g.integers(0, N, size=(batch, n), dtype=np.uint64).astype(DT[w])
+    want = np.stack([orc.dft(w, N, x[i], wr) for i in range(batch)])
+    flat = torch.zeros(batch * n + 1, dtype=torch.from_numpy(x).dtype, device="cuda")
+    view = flat[1:].view(batch, n)                 # one element in: misaligned for every width
+    view.copy_(torch.from_numpy(x).cuda())
+    for v in ["classic"] + (["plantard"] if c.valid("plantard") else []):
+        dv = flat.clone()[1:].view(batch, n)
+        assert dv.data_ptr() % 16 != 0
+        mg.ntt(c, dv, wr, variant=v)
+        assert np.array_equal(dv.cpu().numpy(), want), v
