@@ -30,9 +30,10 @@
 
 namespace mont {
 
-// FAST (classic twiddles, N < 2^31 at w = 32 or N < 2^62 at w = 64): the
-// ladder's smaller-modulus products; the 64-bit one is lazy (below 2N), so one
-// conditional subtraction follows.
+// FAST: N < 2^(w-1), so sums of two residues fit a word (branch-free modular
+// add and subtract below); with classic twiddles it also means N < 2^31 at
+// w = 32 or N < 2^62 at w = 64, the ladder's smaller-modulus products (the
+// 64-bit one is lazy, below 2N, so one conditional subtraction follows).
 template <class R, int V, bool FAST>
 __device__ __forceinline__ typename R::E tw_mul(const R &red, typename R::E a, const KConst &w)
 {
@@ -40,7 +41,7 @@ __device__ __forceinline__ typename R::E tw_mul(const R &red, typename R::E a, c
     if constexpr (V == CLASSIC && FAST && sizeof(El) == 8) {
         const El u = red.mul_fast(a, (El)w.b);
         return u >= red.N ? u - red.N : u;
-    } else if constexpr (V == CLASSIC && FAST) {
+    } else if constexpr (V == CLASSIC && FAST && sizeof(El) == 4) {
         return red.mul_fast(a, (El)w.b);
     } else if constexpr (V == CLASSIC) {
         return red.mul(a, (El)w.b);
@@ -49,17 +50,27 @@ __device__ __forceinline__ typename R::E tw_mul(const R &red, typename R::E a, c
     }
 }
 
-template <class El>
+template <class El, bool FAST>
 __device__ __forceinline__ El add_mod(El u, El t, El N)
 {
-    const El s = u + t;
-    return (s < u || s >= N) ? (El)(s - N) : s;  // s < u: the sum wrapped (N > 2^(w-1))
+    const El s = (El)(u + t);
+    if constexpr (FAST) {
+        const El d = (El)(s - N);  // s < 2N <= 2^w: s - N wraps above s exactly when s < N
+        return d < s ? d : s;
+    } else {
+        return (s < u || s >= N) ? (El)(s - N) : s;  // s < u: the sum wrapped (N > 2^(w-1))
+    }
 }
 
-template <class El>
+template <class El, bool FAST>
 __device__ __forceinline__ El sub_mod(El u, El t, El N)
 {
-    return u >= t ? (El)(u - t) : (El)(u + (N - t));
+    if constexpr (FAST) {
+        const El d = (El)(u - t), e = (El)(d + N);  // u < t: d wrapped and d + N < d
+        return e < d ? e : d;
+    } else {
+        return u >= t ? (El)(u - t) : (El)(u + (N - t));
+    }
 }
 
 // Twiddle as kept in device memory and LDS: what tw_mul needs of a KConst,
@@ -98,8 +109,8 @@ __device__ __forceinline__ void butterfly(const R &red, typename R::E &u, typena
     using El = typename R::E;
     const El t = tw_mul<R, V, FAST>(red, v, w.get());
     const El x = u;
-    u = add_mod<El>(x, t, N);
-    v = sub_mod<El>(x, t, N);
+    u = add_mod<El, FAST>(x, t, N);
+    v = sub_mod<El, FAST>(x, t, N);
 }
 
 // LDS: n coefficients, then n/2 twiddles.  Pairs of radix-2 stages run as one
@@ -139,8 +150,13 @@ __global__ void __launch_bounds__(BLOCK)
             s[__brev(i) >> (32 - log2n)] = x[i];
     }
     __syncthreads();
-    uint32_t lh = 0;
-    for (; lh + 1 < log2n; lh += 2) {
+    // at most six radix-4 steps (n <= 4096): unrolled, so lengths and shifts are constants
+    uint32_t done = 0;  // stages completed
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+        const uint32_t lh = 2u * (uint32_t)st;
+        if (lh + 1 >= log2n)
+            break;
         const uint32_t len = 1u << lh;
         const uint32_t sh0 = log2n - 1 - lh, sh1 = log2n - 2 - lh;  // twiddle strides of the two stages
         for (uint32_t g = threadIdx.x; g < n / 4; g += blockDim.x) {
@@ -158,8 +174,10 @@ __global__ void __launch_bounds__(BLOCK)
             s[i0 + 3 * len] = a3;
         }
         __syncthreads();
+        done = lh + 2;
     }
-    if (lh < log2n) {  // one radix-2 stage left
+    if (done < log2n) {  // one radix-2 stage left
+        const uint32_t lh = done;
         const uint32_t len = 1u << lh;
         for (uint32_t b = threadIdx.x; b < n / 2; b += blockDim.x) {
             const uint32_t j = b & (len - 1);
@@ -304,15 +322,20 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
     // 16-byte chunks when every polynomial starts on a 16-byte boundary
     const uint32_t vec = ((uintptr_t)data % 16 == 0 && ((size_t)n * sizeof(El)) % 16 == 0) ? 1u : 0u;
     const uint32_t inv = (uint32_t)inverse;
-    if (variant == CLASSIC && fast_ladder<W>(k.N))
-        hipLaunchKernelGGL((k_ntt<W, CLASSIC, W != 16>), dim3((unsigned)batch), dim3(block), lds, s, k, data, log2n,
-                           (const TwL<W, CLASSIC> *)t.dev, t.scale, inv, vec);
+    // FAST needs N < 2^(w-1); classic twiddles at w >= 32 also the ladder's smaller-modulus bound
+    const bool small = k.N < (1ull << (W - 1));
+    const bool fast = variant == CLASSIC && W != 16 ? fast_ladder<W>(k.N) : small;
+    const dim3 grid((unsigned)batch), blk(block);
+    const auto *twc = (const TwL<W, CLASSIC> *)t.dev;
+    const auto *twp = (const TwL<W, PLANTARD> *)t.dev;
+    if (variant == CLASSIC && fast)
+        hipLaunchKernelGGL((k_ntt<W, CLASSIC, true>), grid, blk, lds, s, k, data, log2n, twc, t.scale, inv, vec);
     else if (variant == CLASSIC)
-        hipLaunchKernelGGL((k_ntt<W, CLASSIC, false>), dim3((unsigned)batch), dim3(block), lds, s, k, data, log2n,
-                           (const TwL<W, CLASSIC> *)t.dev, t.scale, inv, vec);
+        hipLaunchKernelGGL((k_ntt<W, CLASSIC, false>), grid, blk, lds, s, k, data, log2n, twc, t.scale, inv, vec);
+    else if (fast)
+        hipLaunchKernelGGL((k_ntt<W, PLANTARD, true>), grid, blk, lds, s, k, data, log2n, twp, t.scale, inv, vec);
     else
-        hipLaunchKernelGGL((k_ntt<W, PLANTARD, false>), dim3((unsigned)batch), dim3(block), lds, s, k, data,
-                           log2n, (const TwL<W, PLANTARD> *)t.dev, t.scale, inv, vec);
+        hipLaunchKernelGGL((k_ntt<W, PLANTARD, false>), grid, blk, lds, s, k, data, log2n, twp, t.scale, inv, vec);
     return hipGetLastError();
 }
 

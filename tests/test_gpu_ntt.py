@@ -32,6 +32,8 @@ def prime_1_mod(bits, log2n, seed):
 CASES = [
     (16, 12289, [1, 3, 8, 12]),
     (16, 3329, [2, 8]),
+    (16, 36097, [3, 8]),                      # above 2^15: wrap-checked modular add/subtract (both twiddle forms)
+    (16, 40961, [4, 12]),                     # above 2^16/phi: classic only
     (32, 8380417, [1, 4, 8, 12]),
     (32, 2013265921, [6, 11]),
     (32, 3221225473, [5, 10]),                # above 2^31: the general classic product
