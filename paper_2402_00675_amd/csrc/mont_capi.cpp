@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
 
@@ -37,17 +38,17 @@ mont_status_t hip_fail(hipError_t e, const char *what)
 
 int device_cus()
 {
-    static int cus[64] = {0};
+    static std::atomic<int> cus[64];  // per device, 0 until first asked (static storage: zero-initialised)
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
         return 256;
-    if (!cus[dev]) {
-        int v = 0;
+    int v = cus[dev].load(std::memory_order_relaxed);
+    if (!v) {
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
             v = 256;
-        cus[dev] = v;
+        cus[dev].store(v, std::memory_order_relaxed);
     }
-    return cus[dev];
+    return v;
 }
 
 KCtx to_kctx(const mont_ctx_t &c)
@@ -376,39 +377,41 @@ extern "C" mont_status_t mont_tune_mul(const mont_ctx_t *ctx, const void *a, con
     if (n == 0 || !a || !b || !out)
         return fail(MONT_E_INVAL, "tuning needs non-empty device buffers");
     hipStream_t s = (hipStream_t)stream;
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0)
+            (void)hipEventDestroy(e0);
         return fail(MONT_E_DEVICE, "event create");
+    }
     const int wc = width_class(ctx->w);
     const Launch saved = get_launch(0, wc, variant);
     Launch bestL = saved;
     float best_ms = 1e30f;
     const int unrolls[] = {1, 2, 4};
     const int bpcs[] = {0, 4, 8, 16};
-    for (int u : unrolls)
-        for (int nt = 0; nt < 2; ++nt)
-            for (int bpc : bpcs) {
-                Launch L;
-                L.unroll = u;
-                L.nontemporal = nt;
-                L.blocks_per_cu = bpc;
-                set_launch(0, wc, variant, L);
-                rc = mont_mul(ctx, a, b, out, n, variant, stream);  // warm
-                (void)hipEventRecord(e0, s);
-                for (int r = 0; r < 5 && !rc; ++r)
-                    rc = mont_mul(ctx, a, b, out, n, variant, stream);
-                (void)hipEventRecord(e1, s);
-                if (!rc && hipEventSynchronize(e1) != hipSuccess)
-                    rc = fail(MONT_E_DEVICE, "tuning run failed");
-                if (rc)
-                    break;
-                float ms = 0;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    bestL = L;
-                }
-            }
+    // every candidate shape: unroll x non-temporal x workgroups per CU; the first failure ends the sweep
+    for (int c = 0; c < 3 * 2 * 4 && !rc; ++c) {
+        Launch L;
+        L.unroll = unrolls[c / 8];
+        L.nontemporal = (c / 4) % 2;
+        L.blocks_per_cu = bpcs[c % 4];
+        set_launch(0, wc, variant, L);
+        rc = mont_mul(ctx, a, b, out, n, variant, stream);  // warm
+        if (!rc && hipEventRecord(e0, s) != hipSuccess)
+            rc = fail(MONT_E_DEVICE, "event record");
+        for (int r = 0; r < 5 && !rc; ++r)
+            rc = mont_mul(ctx, a, b, out, n, variant, stream);
+        if (!rc && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+            rc = fail(MONT_E_DEVICE, "tuning run failed");
+        if (rc)
+            break;
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+            best_ms = ms;
+            bestL = L;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     set_launch(0, wc, variant, rc ? saved : bestL);

@@ -442,9 +442,12 @@ static mont_status_t tune(mont_batch &b, const DPools &P, hipStream_t s)
             return build_tiles(b, s);
         }
     }
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0)
+            (void)hipEventDestroy(e0);
         return fail(MONT_E_DEVICE, "event create");
+    }
     const uint32_t tiles[] = {1024, 2048, 4096, 8192, 16384};
     const uint32_t bpcs[] = {0, 4, 8, 16};
     float best = 1e30f;
@@ -488,12 +491,15 @@ static mont_status_t tune(mont_batch &b, const DPools &P, hipStream_t s)
 done:
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    // the best shape so far (the starting one if none was timed), also after a failure
     b.flags = (saved_flags & ~MONT_BATCH_DYNAMIC) | (bt.dynamic ? MONT_BATCH_DYNAMIC : 0u);
-    if (rc)
-        return rc;
     b.tile_base = bt.tile_base;
     b.blocks_per_cu = bt.blocks_per_cu;
     b.nt = bt.nt != 0;
+    if (rc) {
+        (void)build_tiles(b, s);
+        return rc;
+    }
     {
         std::lock_guard<std::mutex> g(g_rt_mu);
         g_rt_cache[key] = bt;
