@@ -427,6 +427,23 @@ const char *mont_last_error(void);
 /* Library version (ABI revision in the low 16 bits). */
 uint32_t mont_version(void);
 
+/*
+ * mont_debug_violations -- precondition counter of the MONT_DEBUG build
+ * (libmont_debug.so, same interface).  That build checks, ahead of each
+ * call's own kernels and on the same stream, every input element against the
+ * range its algorithm is defined on (the Require lines of Algorithms 1-4;
+ * 0 <= T < N R for classic REDC, Section 1): a product a b of mont_mul,
+ * mont_mul_const and the ragged products, a T of mont_redc and the ragged
+ * reductions; bases of mont_pow, coefficients of mont_ntt and residues of
+ * mont_crt must lie below their modulus; serving jobs are checked on the
+ * host at submission.  Results are unchanged (out-of-range elements still get
+ * an unspecified value).  Synchronises the current device, stores the number
+ * of violating elements counted since the last reset in *count (may be NULL),
+ * and resets the count if `reset` is non-zero.  The release library returns
+ * MONT_E_UNSUPPORTED and *count = 0.
+ */
+mont_status_t mont_debug_violations(uint64_t *count, int reset);
+
 #ifdef __cplusplus
 }
 #endif

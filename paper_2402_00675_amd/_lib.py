@@ -8,6 +8,7 @@ loudly: there is no fallback.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import re
@@ -16,6 +17,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmont.so")
+LIB_DEBUG_PATH = os.path.join(_HERE, "libmont_debug.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "mont.h")
 
 CLASSIC, SIGNED, PLANTARD, SIGNED_PLANTARD, SIGNED_PLANTARD_ALPHA = range(5)
@@ -63,14 +65,45 @@ class LaunchStruct(ctypes.Structure):
 _lib = None
 
 
+_opened = {}
+
+
 def load():
-    """Loads libmont.so (built by paper_2402_00675_amd.build); raises if absent."""
+    """The library every call of this module goes to: libmont.so (built by
+    paper_2402_00675_amd.build), or the file named by $MONT_LIBRARY; raises if absent."""
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise ImportError("libmont.so is not built (%s); run `python -m paper_2402_00675_amd.build`" % LIB_PATH)
-    lib = ctypes.CDLL(LIB_PATH)
+    _lib = _open(os.environ.get("MONT_LIBRARY") or LIB_PATH)
+    return _lib
+
+
+@contextlib.contextmanager
+def library(path: str = None):
+    """Routes this module's calls to another build of the library inside the
+    block, by default libmont_debug.so (MONT_DEBUG precondition counters)."""
+    global _lib
+    prev = _lib
+    _lib = _open(path or LIB_DEBUG_PATH)
+    try:
+        yield _lib
+    finally:
+        _lib = prev
+
+
+def debug_violations(reset: bool = False) -> int:
+    """Precondition violations counted by the MONT_DEBUG build since the last reset."""
+    c = ctypes.c_uint64(0)
+    check(load().mont_debug_violations(ctypes.byref(c), 1 if reset else 0))
+    return c.value
+
+
+def _open(path: str):
+    if path in _opened:
+        return _opened[path]
+    if not os.path.exists(path):
+        raise ImportError("%s is not built; run `python -m paper_2402_00675_amd.build`" % path)
+    lib = ctypes.CDLL(path)
     vp, u64, u32, i32, sz = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_size_t
     P = ctypes.POINTER
     sig = {
@@ -97,6 +130,7 @@ def load():
         "mont_get_launch": (i32, [u32, u32, i32, P(LaunchStruct)]),
         "mont_stream_ref": (i32, [vp, vp, vp, sz, vp]),
         "mont_valu_ref": (i32, [u32, u32, u32, vp, vp]),
+        "mont_debug_violations": (i32, [P(u64), i32]),
         "mont_last_error": (ctypes.c_char_p, []),
         "mont_version": (u32, []),
     }
@@ -104,7 +138,7 @@ def load():
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args
-    _lib = lib
+    _opened[path] = lib
     return lib
 
 

@@ -3,8 +3,9 @@
     python -m paper_2402_00675_amd.build
 
 Every source is compiled with hipcc for gfx950 only, objects go to
-``_build/`` at the repository root, and the shared library is written next
-to this file, where the Python binding loads it.
+``_build/`` at the repository root, and the shared libraries are written next
+to this file, where the Python binding loads them: ``libmont.so`` and
+``libmont_debug.so`` (the same library with MONT_DEBUG precondition counters).
 """
 from __future__ import annotations
 
@@ -34,6 +35,12 @@ SOURCES = [
     "mont_serve.cpp",
 ]
 
+# The MONT_DEBUG library: these sources again with -DMONT_DEBUG (precondition
+# counters ahead of every call), the rest shared with the release build.
+LIB_DEBUG = os.path.join(PKG, "libmont_debug.so")
+DEBUG_SOURCES = ["mont_capi.cpp", "mont_ragged.hip", "mont_crt.hip", "mont_ntt.hip", "mont_serve.cpp",
+                 "mont_debug.hip"]
+
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = [
     "--offload-arch=" + ARCH,
@@ -47,9 +54,10 @@ CFLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, "-x", "hip", *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, debug: bool = False) -> str:
+    obj = os.path.join(BUILD, "debug" if debug else "", os.path.splitext(src)[0] + ".o")
+    extra = ["-DMONT_DEBUG"] if debug else []
+    cmd = [HIPCC, "-x", "hip", *CFLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     out = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
@@ -59,18 +67,26 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None) -> str:
-    """Compile every HIP/C++ source and link libmont.so; returns its path."""
-    os.makedirs(BUILD, exist_ok=True)
-    jobs = jobs or min(8, len(SOURCES))
-    with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp%d" % os.getpid()
+def _link(objs: list, lib: str) -> None:
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s%s" % (r.stdout, r.stderr))
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(jobs: int | None = None) -> str:
+    """Compile every HIP/C++ source, link libmont.so and libmont_debug.so; returns the former's path."""
+    os.makedirs(os.path.join(BUILD, "debug"), exist_ok=True)
+    jobs = jobs or 8
+    units = [(src, False) for src in SOURCES] + [(src, True) for src in DEBUG_SOURCES]
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda u: _compile(*u), units))
+    rel = objs[:len(SOURCES)]
+    dbg = dict(zip(DEBUG_SOURCES, objs[len(SOURCES):]))
+    _link(rel, LIB)
+    _link([dbg.get(src, o) for src, o in zip(SOURCES, rel)] + [dbg["mont_debug.hip"]], LIB_DEBUG)
     return LIB
 
 

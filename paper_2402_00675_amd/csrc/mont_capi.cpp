@@ -12,6 +12,9 @@
 
 #include "../../include/mont.h"
 #include "mont_common.hpp"
+#ifdef MONT_DEBUG
+#include "mont_debug.hpp"
+#endif
 #include "mont_kernels.hpp"
 
 namespace mont {
@@ -192,6 +195,21 @@ static mont_status_t run_map(int op, const mont_ctx_t *ctxs, uint32_t rows, cons
     const int wc = width_class(ctxs[0].w);
     const Launch L = get_launch(op_launch, wc, variant);
     hipStream_t s = (hipStream_t)stream;
+#ifdef MONT_DEBUG
+    {
+        const uint32_t w = ctxs[0].w;
+        const size_t es = w / 8;
+        const uint64_t mask = w == 64 ? ~0ull : (1ull << w) - 1;
+        for (uint32_t r = 0; r < rows; ++r) {
+            const char *p0 = (const char *)in0 + (size_t)r * ld * es * (op == 1 ? 2 : 1);
+            const char *p1 = in1 ? (const char *)in1 + (size_t)r * ld * es : nullptr;
+            const int kind = op == 0 ? DBG_PRODUCT : op == 1 ? DBG_T : DBG_CONST;
+            const hipError_t de = debug_check(kind, ctxs[r], variant, p0, p1, kc ? kc->b & mask : 0, n, s);
+            if (de != hipSuccess)
+                return hip_fail(de, "precondition check");
+        }
+    }
+#endif
     hipError_t e = wc == 0 ? launch_map<16>(a, L, s) : wc == 1 ? launch_map<32>(a, L, s) : launch_map<64>(a, L, s);
     if (e != hipSuccess)
         return hip_fail(e, op == 1 ? "mont_redc launch" : "mont_mul launch");
@@ -275,6 +293,10 @@ mont_status_t mont_pow(const mont_ctx_t *ctx, const void *x, const uint64_t *e, 
     const int wc = width_class(ctx->w);
     const Launch L = get_launch(2, wc, CLASSIC);
     hipStream_t s = (hipStream_t)stream;
+#ifdef MONT_DEBUG
+    if (const hipError_t de = debug_check(DBG_BELOW_N, *ctx, CLASSIC, x, nullptr, 0, n, s))
+        return hip_fail(de, "precondition check");
+#endif
     hipError_t err = wc == 0   ? launch_pow<16>(k, x, e, out, n, L.unroll, L.blocks_per_cu, s)
                      : wc == 1 ? launch_pow<32>(k, x, e, out, n, L.unroll, L.blocks_per_cu, s)
                                : launch_pow<64>(k, x, e, out, n, L.unroll, L.blocks_per_cu, s);
@@ -425,3 +447,15 @@ extern "C" mont_status_t mont_tune_mul(const mont_ctx_t *ctx, const void *a, con
     }
     return MONT_OK;
 }
+
+#ifndef MONT_DEBUG
+// The release library keeps no precondition counters (mont_debug.hip, built
+// into the MONT_DEBUG library only, does).
+extern "C" mont_status_t mont_debug_violations(uint64_t *count, int reset)
+{
+    (void)reset;
+    if (count)
+        *count = 0;
+    return fail(MONT_E_UNSUPPORTED, "library built without MONT_DEBUG: load libmont_debug.so to count violations");
+}
+#endif

@@ -23,6 +23,9 @@
 #include <algorithm>
 
 #include "mont_common.hpp"
+#ifdef MONT_DEBUG
+#include "mont_debug.hpp"
+#endif
 
 namespace mont {
 
@@ -205,6 +208,11 @@ extern "C" mont_status_t mont_crt(const mont_ctx_t *ctxs, uint32_t k, const void
     hipStream_t s = (hipStream_t)stream;
     const uint64_t *r = (const uint64_t *)res;
     uint64_t *o = (uint64_t *)out;
+#ifdef MONT_DEBUG
+    for (uint32_t i = 0; i < k; ++i)
+        if (const hipError_t de = debug_check(DBG_BELOW_N, ctxs[i], CLASSIC, r + (size_t)i * ld, nullptr, 0, n, s))
+            return hip_fail(de, "precondition check");
+#endif
     switch (k) {
 #define C(K)                                \
     case K:                                 \

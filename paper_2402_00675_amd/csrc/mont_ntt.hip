@@ -27,6 +27,9 @@
 #include <vector>
 
 #include "mont_common.hpp"
+#ifdef MONT_DEBUG
+#include "mont_debug.hpp"
+#endif
 
 namespace mont {
 
@@ -371,6 +374,10 @@ extern "C" mont_status_t mont_ntt(const mont_ctx_t *ctx, void *data, size_t batc
         return rc;
     const KCtx k = to_kctx(*ctx);
     hipStream_t s = (hipStream_t)stream;
+#ifdef MONT_DEBUG
+    if (const hipError_t de = debug_check(DBG_BELOW_N, *ctx, CLASSIC, data, nullptr, 0, (uint64_t)batch << log2n, s))
+        return hip_fail(de, "precondition check");
+#endif
     const hipError_t e = ctx->w == 16   ? go_ntt<16>(k, variant, data, batch, log2n, t, inverse ? 1 : 0, s)
                          : ctx->w == 32 ? go_ntt<32>(k, variant, data, batch, log2n, t, inverse ? 1 : 0, s)
                                         : go_ntt<64>(k, variant, data, batch, log2n, t, inverse ? 1 : 0, s);

@@ -26,6 +26,9 @@
 #include <vector>
 
 #include "mont_common.hpp"
+#ifdef MONT_DEBUG
+#include "mont_debug.hpp"
+#endif
 #include "mont_ragged.hpp"
 
 namespace mont {
@@ -599,6 +602,24 @@ mont_status_t mont_batch_run(mont_batch_t *b, const mont_pools_t *pools, void *s
         return rc;
     const DPools P = to_dpools(*pools);
     hipStream_t s = (hipStream_t)stream;
+#ifdef MONT_DEBUG
+    for (size_t i = 0; i < b->segs.size(); ++i) {
+        const mont_seg_t &sg = b->segs[i];
+        const mont_ctx_t &c = b->ctxs[sg.ctx];
+        const size_t es = c.w / 8;
+        const uint32_t wc = b->hsegs[i].wc;
+        const char *i0 = (const char *)pools->in0[wc], *i1 = (const char *)pools->in1[wc];
+        hipError_t de;
+        if (sg.op == MONT_OP_MUL)
+            de = debug_check(DBG_PRODUCT, c, sg.variant, i0 + sg.off * es, i1 + sg.off1 * es, 0, sg.n, s);
+        else if (sg.op == MONT_OP_REDC)
+            de = debug_check(DBG_T, c, sg.variant, i0 + sg.off * 2 * es, nullptr, 0, sg.n, s);
+        else
+            de = debug_check(DBG_BELOW_N, c, CLASSIC, i0 + sg.off * es, nullptr, 0, sg.n, s);
+        if (de != hipSuccess)
+            return hip_fail(de, "precondition check");
+    }
+#endif
     if ((b->flags & MONT_BATCH_TUNE) && !b->tuned) {
         rc = tune(*b, P, s);
         if (rc)

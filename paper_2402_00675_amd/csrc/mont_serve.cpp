@@ -35,6 +35,9 @@
 #include <vector>
 
 #include "mont_common.hpp"
+#ifdef MONT_DEBUG
+#include "mont_debug.hpp"
+#endif
 #include "mont_ragged.hpp"
 #include "mont_sched.hpp"
 
@@ -549,6 +552,25 @@ mont_status_t mont_serve_submit(mont_server_t *S, const mont_job_t *job)
         ++S->rejected;
         return rc;
     }
+#ifdef MONT_DEBUG
+    {
+        // operands are in host memory: products must meet classic REDC's range, bases lie below N
+        uint64_t bad = 0;
+        for (uint64_t i = 0; i < job->n; ++i) {
+            const uint64_t x = job->w == 32 ? ((const uint32_t *)job->in0)[i] : ((const uint64_t *)job->in0)[i];
+            if (job->op == MONT_OP_POW) {
+                bad += x >= job->N;
+            } else {
+                const uint64_t y = job->w == 32 ? ((const uint32_t *)job->in1)[i] : ((const uint64_t *)job->in1)[i];
+                bool neg;
+                dbg_u128 mag;
+                dbg_product(CLASSIC, job->w, x, y, &neg, &mag);
+                bad += !dbg_t_in_range(CLASSIC, job->w, job->N, 0, neg, mag);
+            }
+        }
+        debug_count_host(bad);
+    }
+#endif
     {
         std::lock_guard<std::mutex> lk(S->mu);
         S->inbox.push_back(to_job(job, now_s()));

@@ -1,0 +1,176 @@
+"""The MONT_DEBUG build (libmont_debug.so): every call counts the input
+elements outside the range its algorithm is defined on (the Require lines of
+Algorithms 1-4, 0 <= T < N R for classic REDC, residues below N for
+exponentiation, NTT and CRT), and returns exactly what the release build
+returns for the same inputs, out-of-range elements included (their values are
+unspecified but deterministic).  Out-of-range inputs only reach arithmetic,
+never an index, so the kernels stay in bounds."""
+import numpy as np
+import pytest
+
+import paper_2402_00675_amd as mg
+from paper_2402_00675_amd import inputs as inp
+from paper_2402_00675_amd import serve
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def both(fn):
+    """fn() under the release and the debug build: (release result, debug result, debug count)."""
+    rel = fn().cpu().numpy()
+    with mg.library():
+        mg.debug_violations(reset=True)
+        got = fn().cpu().numpy()
+        count = mg.debug_violations(reset=True)
+    return rel, got, count
+
+
+def plant(g, n, k):
+    return np.sort(g.choice(n, size=k, replace=False))
+
+
+def test_products_and_reductions():
+    g = inp.rng(97, 1)
+    n = 20_011
+    N = 8380417
+    c = mg.setup(N, 32)
+    # classic: a b must stay below N R = N 2^32
+    a = g.integers(0, N, size=n, dtype=np.uint64).astype(np.uint32)
+    b = g.integers(0, N, size=n, dtype=np.uint64).astype(np.uint32)
+    bad = plant(g, n, 37)
+    a[bad] = 0xFFFFFFFF
+    b[bad] = 0xFFFFFFFF
+    rel, got, cnt = both(lambda: mg.mul(c, dev(a), dev(b), variant="classic"))
+    assert cnt == 37 and np.array_equal(rel, got)
+    # Algorithm 1: |a b| < N R/2
+    sa = g.integers(-(N // 2), N // 2 + 1, size=n).astype(np.int32)
+    sb = g.integers(-(N // 2), N // 2 + 1, size=n).astype(np.int32)
+    bad = plant(g, n, 11)
+    sa[bad] = -(1 << 31)
+    sb[bad] = -(1 << 31)
+    rel, got, cnt = both(lambda: mg.mul(c, dev(sa), dev(sb), variant="signed"))
+    assert cnt == 11 and np.array_equal(rel, got)
+    # Algorithm 2: 0 <= a b <= N^2 (the bound itself is inside)
+    a2 = a.copy()
+    b2 = b.copy()
+    a2[bad] = N
+    b2[bad] = N
+    a2[bad[:5]] = N + 1
+    rel, got, cnt = both(lambda: mg.mul(c, dev(a2), dev(b2), variant="plantard"))
+    over = int(np.sum((a2.astype(object) * b2.astype(object)) > N * N))   # those above and 5 of these
+    assert over >= 5 and cnt == over and np.array_equal(rel, got)
+    # Algorithm 3 reductions: |T| <= 2^62 for w = 32
+    T = g.integers(-(1 << 62), (1 << 62) + 1, size=n, dtype=np.int64)
+    bad = plant(g, n, 23)
+    T[bad] = np.int64((1 << 62) + 1)
+    T[bad[:7]] = np.int64(-(1 << 63))
+    rel, got, cnt = both(lambda: mg.redc(c, dev(T), variant="signed_plantard"))
+    assert cnt == 23 and np.array_equal(rel, got)
+    # classic REDC of 64-bit words: T < N 2^64
+    c64 = mg.setup((1 << 61) - 1, 64)
+    T2 = np.zeros((n, 2), np.uint64)
+    T2[:, 0] = g.integers(0, 1 << 63, size=n, dtype=np.uint64)
+    T2[:, 1] = g.integers(0, (1 << 61) - 1, size=n, dtype=np.uint64)
+    bad = plant(g, n, 9)
+    T2[bad, 1] = (1 << 61) - 1      # T >= N 2^64
+    rel, got, cnt = both(lambda: mg.redc(c64, dev(T2)))
+    assert cnt == 9 and np.array_equal(rel, got)
+
+
+def test_fixed_operand_rns_pow_ntt_crt():
+    g = inp.rng(97, 2)
+    n = 4099
+    N = 12289
+    c = mg.setup(N, 16)
+    a = g.integers(0, N, size=n, dtype=np.uint64).astype(np.uint16)
+    bad = plant(g, n, 5)
+    a[bad] = 0xFFFF                         # Plantard: 0xFFFF (N - 1) > N^2
+    rel, got, cnt = both(lambda: mg.mul_const(c, dev(a), N - 1, variant="plantard"))
+    assert cnt == 5 and np.array_equal(rel, got)
+    # RNS rows: each row against its own modulus
+    mods = inp.random_primes(g, 60, 3)
+    ctxs = [mg.setup(m, 64) for m in mods]
+    A = np.stack([g.integers(0, m, size=n, dtype=np.uint64) for m in mods])
+    B = A[::-1].copy() % np.array(mods, dtype=np.uint64)[:, None]
+    A[1, bad] = np.uint64(0xFFFFFFFFFFFFFFFF)
+    B[1, bad] = np.uint64(0xFFFFFFFFFFFFFFFF)
+    rel, got, cnt = both(lambda: mg.mul_rns(ctxs, dev(A), dev(B)))
+    assert cnt == 5 and np.array_equal(rel, got)
+    # exponentiation bases below N
+    N32 = (1 << 31) - 1
+    c32 = mg.setup(N32, 32)
+    x = g.integers(0, N32, size=n, dtype=np.uint64).astype(np.uint32)
+    e = inp.u64_uniform(g, n)
+    x[bad] = N32
+    rel, got, cnt = both(lambda: mg.pow(c32, dev(x), dev(e)))
+    assert cnt == 5 and np.array_equal(rel, got)
+    # NTT coefficients below N
+    P = 8380417
+    cp = mg.setup(P, 32)
+    poly = g.integers(0, P, size=(4, 64), dtype=np.uint64).astype(np.uint32)
+    poly[2, 7] = P + 3
+    poly[3, 0] = 0xFFFFFFFF
+    root = next(r for r in (pow(q, (P - 1) // 64, P) for q in range(2, 100)) if pow(r, 32, P) == P - 1)
+    rel, got, cnt = both(lambda: mg.ntt(cp, dev(poly), root))
+    assert cnt == 2 and np.array_equal(rel, got)
+    # CRT residues below their moduli
+    R3 = np.stack([g.integers(0, m, size=n, dtype=np.uint64) for m in mods])
+    R3[0, bad[:2]] = np.uint64(mods[0])
+    R3[2, bad[2:]] = np.uint64(mods[2] + 1)
+    rel, got, cnt = both(lambda: mg.crt(ctxs, dev(R3)))
+    assert cnt == 5 and np.array_equal(rel, got)
+
+
+def test_ragged_and_serving():
+    g = inp.rng(97, 3)
+    N32, N64 = 8380417, (1 << 61) - 1
+    ctxs = [mg.setup(N32, 32), mg.setup(N64, 64)]
+    n = 3000
+    a32 = g.integers(0, N32, size=2 * n, dtype=np.uint64).astype(np.uint32)
+    b32 = g.integers(0, N32, size=2 * n, dtype=np.uint64).astype(np.uint32)
+    a64 = g.integers(0, N64, size=2 * n, dtype=np.uint64)
+    e64 = inp.u64_uniform(g, 2 * n)
+    a32[[3, 4000]] = 0xFFFFFFFF
+    b32[[3, 4000]] = 0xFFFFFFFF
+    a64[[10, 11, 5999]] = np.uint64(N64 + 5)
+    segs = [(0, mg.OP_MUL, "classic", n, 0), (0, mg.OP_MUL, "classic", n, n),
+            (1, mg.OP_POW, "classic", n, 0), (1, mg.OP_POW, "classic", n, n)]
+    d = [dev(v) for v in (a32, b32, a64, e64)]
+
+    def run():
+        o32 = torch.zeros(2 * n, dtype=torch.uint32, device="cuda")
+        o64 = torch.zeros(2 * n, dtype=torch.uint64, device="cuda")
+        b = mg.Batch(ctxs, segs)
+        b.run(mg.pools([None, d[0], d[2]], [None, d[1], d[3]], [None, o32, o64]))
+        torch.cuda.synchronize()
+        b.close()
+        return torch.cat([o32.cpu().to(torch.int64), o64.cpu().view(torch.int64)])
+
+    rel, got, cnt = both(run)
+    assert cnt == 2 + 3 and np.array_equal(rel, got)
+    # serving: operands in host memory, checked at submission
+    with mg.library():
+        mg.debug_violations(reset=True)
+        stream = serve.JobStream(torch, njobs=40, seed_rep=9, distinct_outputs=True, hi=1 << 10)
+        for w in (32, 64):   # every job's window holds some of these
+            stream.pool[w][0].numpy()[::101] = np.iinfo(np.uint32 if w == 32 else np.uint64).max
+        srv = mg.Server(hbm_budget_bytes=64 << 20, streams=2)
+        try:
+            done = serve.replay(srv, stream, np.zeros(stream.njobs))
+        finally:
+            srv.close()
+        assert len(done) == stream.njobs
+        want = 0
+        for i in range(stream.njobs):
+            x, y = stream.inputs_of(i)
+            N, w = int(stream.mods[i]), 64 if stream.wide[i] else 32
+            if stream.ops[i] == 1:
+                want += int(np.sum(x.astype(object) >= N))
+            else:
+                want += int(np.sum(x.astype(object) * y.astype(object) >= N << w))
+        assert mg.debug_violations(reset=True) == want and want > 0

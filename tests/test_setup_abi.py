@@ -23,6 +23,21 @@ def test_every_declared_symbol_is_exported():
     assert not missing, missing
 
 
+def test_debug_build_exports_the_same_interface():
+    """libmont_debug.so (MONT_DEBUG) is a drop-in build of the same header."""
+    with mg.library() as dbg:
+        missing = [n for n in mg.header_functions() if not hasattr(dbg, n)]
+        assert not missing, missing
+        assert dbg.mont_version() == _lib._open(_lib.LIB_PATH).mont_version()
+    assert mg.load() is not dbg
+
+
+def test_release_build_has_no_violation_counter():
+    with pytest.raises(mg.MontError) as e:
+        mg.debug_violations()
+    assert e.value.code == -3
+
+
 def sample_moduli(w, k=60, seed=0):
     g = np.random.default_rng(seed + w)
     top = (1 << w) - 1
