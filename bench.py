@@ -28,7 +28,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-VALU_INT32_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 64 lanes/clk x 2.4 GHz
 
 
 def log(*a):
@@ -84,6 +83,24 @@ def timed(fn, torch, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return wall, e0.elapsed_time(e1) / steps
+
+
+def timed_sec(fn, torch, min_steps=10, warm_ms=30.0, span_ms=20.0):
+    """Secondary measurements: calls fn for warm_ms of wall time first (clocks
+    ramp up under load; a few calls of a 0.1 ms kernel are not enough), then
+    times enough calls to span at least span_ms; returns (None, HIP-event ms per call)."""
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        fn()
+        k += 1
+        if k % 4 == 0:
+            torch.cuda.synchronize()
+            if (time.perf_counter() - t0) * 1e3 >= warm_ms:
+                break
+    per_ms = (time.perf_counter() - t0) * 1e3 / k
+    steps = max(min_steps, int(span_ms / max(per_ms, 1e-3)) + 1)
+    return None, timed(fn, torch, steps, 0)[1]
 
 
 def main():
@@ -206,10 +223,10 @@ def copy_ceiling(torch):
 
     src = torch.empty(1 << 28, dtype=torch.int64, device="cuda:0")
     dst = torch.empty_like(src)
-    _, ms = timed(lambda: dst.copy_(src), torch, 10, 3)
+    _, ms = timed_sec(lambda: dst.copy_(src), torch)
     copy = round(2 * src.numel() * 8 / (ms * 1e-3) / 1e9, 1)
     src2 = torch.empty_like(src)
-    _, ms = timed(lambda: mg.stream_ref(src, src2, dst), torch, 10, 3)
+    _, ms = timed_sec(lambda: mg.stream_ref(src, src2, dst), torch)
     ref = round(3 * src.numel() * 8 / (ms * 1e-3) / 1e9, 1)
     log("copy: %.0f GB/s, 2-read/1-write reference: %.0f GB/s" % (copy, ref))
     return {"torch_copy_GBs": copy, "ref_2r1w_GBs": ref}
@@ -235,7 +252,7 @@ def secondary(torch, mg, inp, args, sections):
             b = torch.from_numpy(bh).to(dev)
             o = torch.empty_like(a)
             for v in (["signed", "signed_plantard", "signed_plantard_alpha"] if signed else ["classic", "plantard"]):
-                _, ms = timed(lambda: mg.mul(c32, a, b, out=o, variant=v), torch, 20, 5)
+                _, ms = timed_sec(lambda: mg.mul(c32, a, b, out=o, variant=v), torch)
                 gms = w2.n / (ms * 1e-3) / 1e9
                 r32[v] = {"Gmodmul_s": round(gms, 1), "GB_s": round(12 * gms, 1),
                           "frac_hbm": round(12 * gms / HBM_PEAK_GBS, 4)}
@@ -254,7 +271,7 @@ def secondary(torch, mg, inp, args, sections):
             o = torch.empty_like(a)
             b = int(ah[12345])
             for v in (["signed", "signed_plantard"] if signed else ["classic", "plantard"]):
-                _, ms = timed(lambda: mg.mul_const(c32, a, b, out=o, variant=v), torch, 20, 5)
+                _, ms = timed_sec(lambda: mg.mul_const(c32, a, b, out=o, variant=v), torch)
                 gms = w2.n / (ms * 1e-3) / 1e9
                 cst[v] = {"Gmodmul_s": round(gms, 1), "GB_s": round(8 * gms, 1),
                           "frac_hbm": round(8 * gms / HBM_PEAK_GBS, 4)}
@@ -269,7 +286,7 @@ def secondary(torch, mg, inp, args, sections):
         r = torch.from_numpy(ah).to(dev)
         ctxs = [mg.setup(N, 64) for N in wl.moduli]
         o = torch.empty((wl.n, wl.k), dtype=torch.uint64, device=dev)
-        _, ms = timed(lambda: mg.crt(ctxs, r, out=o), torch, 10, 2)
+        _, ms = timed_sec(lambda: mg.crt(ctxs, r, out=o), torch)
         ex["crt"] = {"k": wl.k, "elements": wl.n, "ms": round(ms, 3),
                      "Gelem_s": round(wl.n / (ms * 1e-3) / 1e9, 3),
                      "GB_s": round(2 * 8 * wl.k * wl.n / (ms * 1e-3) / 1e9, 1)}
@@ -286,7 +303,7 @@ def secondary(torch, mg, inp, args, sections):
         d = d.view(batch, n)
         res = {"N": N, "n": n, "batch": batch}
         for v in ("classic", "plantard"):
-            _, ms = timed(lambda: mg.ntt(c32, d, root, variant=v), torch, 10, 2)
+            _, ms = timed_sec(lambda: mg.ntt(c32, d, root, variant=v), torch)
             res[v] = {"ms": round(ms, 3), "Gcoef_s": round(batch * n / (ms * 1e-3) / 1e9, 1),
                       "Gbutterfly_s": round(batch * n // 2 * log2n / (ms * 1e-3) / 1e9, 1),
                       "GB_s": round(8 * batch * n / (ms * 1e-3) / 1e9, 1)}
@@ -302,7 +319,7 @@ def secondary(torch, mg, inp, args, sections):
         a = torch.from_numpy(ah).to(dev)
         b = torch.from_numpy(bh).to(dev)
         o = torch.empty_like(a)
-        _, ms = timed(lambda: mg.mul(c16, a, b, out=o), torch, 200, 20)
+        _, ms = timed_sec(lambda: mg.mul(c16, a, b, out=o), torch)
         ex["r16_mul"] = {"us": round(ms * 1e3, 2), "Gmodmul_s": round(w1.n / (ms * 1e-3) / 1e9, 1)}
         # per-launch medians, warm and cold (a 512 MB write between launches evicts the
         # 6 MiB working set from every cache level, the 256 MB last-level cache included)
@@ -323,7 +340,7 @@ def secondary(torch, mg, inp, args, sections):
         del flush
         total = w1.N << 16
         ro = torch.empty(total, dtype=torch.uint16, device=dev)
-        _, ms = timed(lambda: mg.redc_range(c16, 0, total, out=ro), torch, 10, 2)
+        _, ms = timed_sec(lambda: mg.redc_range(c16, 0, total, out=ro), torch)
         ex["r16_exhaustive_redc"] = {"T": total, "us": round(ms * 1e3, 1),
                                      "GB_s_written": round(2 * total / (ms * 1e-3) / 1e9, 1)}
         log("r16: mul %s, exhaustive %s" % (ex["r16_mul"], ex["r16_exhaustive_redc"]))
@@ -337,7 +354,7 @@ def secondary(torch, mg, inp, args, sections):
         o = torch.empty(blocks * 256, dtype=torch.int64, device=dev)
         vr = {}
         for kind, name in enumerate(VALU_KINDS):
-            _, ms = timed(lambda: mg.valu_ref(kind, iters, blocks, o), torch, 5, 2)
+            _, ms = timed_sec(lambda: mg.valu_ref(kind, iters, blocks, o), torch)
             winst = blocks * 4 * iters * 32          # wave64 instructions
             rate = winst / (ms * 1e-3)
             vr[name] = {"G_wave_instr_s": round(rate / 1e9, 1), "T_lane_ops_s": round(rate * 64 / 1e12, 2),
@@ -358,7 +375,7 @@ def secondary(torch, mg, inp, args, sections):
             e = torch.from_numpy(inp.u64_uniform(g, n)).to(dev)
             o = torch.empty_like(x)
             c = mg.setup(N, w)
-            _, ms = timed(lambda: mg.pow(c, x, e, out=o), torch, 5, 2)
+            _, ms = timed_sec(lambda: mg.pow(c, x, e, out=o), torch)
             rate = n / (ms * 1e-3) / 1e9
             pw["w%d" % w] = {"Gpow_s": round(rate, 3), "ms": round(ms, 3),
                              "Gmontmul_s": round(rate * 97, 1)}  # 3 + 31 windows x 3 + 1 products
@@ -437,10 +454,10 @@ def ragged(torch, mg, inp, nseg):
         bt = mg.Batch(ctxs, segs, flags=flags)
         bt.run(P)  # tunes
         torch.cuda.synchronize()
-        _, ms = timed(lambda: bt.run(P), torch, 10, 2)
+        _, ms = timed_sec(lambda: bt.run(P), torch)
         res[name] = {"ms": round(ms, 3), "GB_s": round(nbytes / (ms * 1e-3) / 1e9, 1), "info": bt.info()}
         o32h, o64h = o32.cpu().numpy(), o64.cpu().numpy()
-        _, ms_pv = timed(lambda: bt.run_pervector(P), torch, 3, 1)
+        _, ms_pv = timed_sec(lambda: bt.run_pervector(P), torch)
         res["per_vector_launches"] = {"ms": round(ms_pv, 3)}
         if not (np.array_equal(o32h, o32.cpu().numpy()) and np.array_equal(o64h, o64.cpu().numpy())):
             raise SystemExit("bench: ragged persistent and per-vector results differ")
@@ -466,7 +483,7 @@ def ragged(torch, mg, inp, nseg):
             g.replay()
             torch.cuda.synchronize()
             bad.append(_mismatch(o32, o32h, o64, o64h))
-        _, ms_pg = timed(lambda: g.replay(), torch, 3, 1)
+        _, ms_pg = timed_sec(lambda: g.replay(), torch)
         bad.append(_mismatch(o32, o32h, o64, o64h))
         bt.run_pervector(P)
         torch.cuda.synchronize()

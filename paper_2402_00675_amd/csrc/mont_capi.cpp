@@ -85,8 +85,10 @@ static void launch_defaults()
         for (auto &b : a)
             for (auto &l : b)
                 l = Launch{};
-    // exponentiation is ALU-bound: two independent elements per lane hide the
-    // latency of the dependent multiply chains
+    // exponentiation is ALU-bound: two independent elements per lane (run in
+    // lockstep) hide the latency of the dependent multiply chains; one, two
+    // and four measure within 1 % of each other on MI355X (2^22 elements,
+    // clocks at steady state), and two keeps the LDS window tables small
     for (auto &b : g_launch[2])
         for (auto &l : b)
             l.unroll = 2;

@@ -102,17 +102,21 @@ hipError_t launch_pow(const KCtx &c, const void *x, const uint64_t *e, void *out
 {
     Launch L;
     L.blocks_per_cu = blocks_per_cu;
-    const int U = unroll == 2 ? 2 : 1;
+    const int U = (unroll == 2 || unroll == 4) ? unroll : 1;
     dim3 grid((unsigned)grid_x(n, U, 1, L));
     // smaller-modulus ladder forms: lazy products for w = 64, N < 2^62; 32-bit registers for w = 32, N < 2^31
     if (fast_ladder<W>(c.N)) {
         constexpr bool F = W != 16;
-        if (U == 2)
+        if (U == 4)
+            hipLaunchKernelGGL((k_pow<W, 4, F>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
+        else if (U == 2)
             hipLaunchKernelGGL((k_pow<W, 2, F>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
         else
             hipLaunchKernelGGL((k_pow<W, 1, F>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
     } else {
-        if (U == 2)
+        if (U == 4)
+            hipLaunchKernelGGL((k_pow<W, 4, false>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
+        else if (U == 2)
             hipLaunchKernelGGL((k_pow<W, 2, false>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
         else
             hipLaunchKernelGGL((k_pow<W, 1, false>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);

@@ -330,6 +330,23 @@ def test_pow_parity(w):
         assert bad.size == 0, (N, bad[:5], x[bad[:5]], e[bad[:5]])
 
 
+@pytest.mark.parametrize("unroll", [1, 4])
+def test_pow_launch_shapes(unroll):
+    """Every lockstep width of the ladder (elements per lane) gives the same results."""
+    g = inp.rng(96, 100 + unroll)
+    for w, N in ((32, (1 << 31) - 1), (32, 4294967291), (64, (1 << 62) - 57), (64, (1 << 64) - 59)):
+        saved = mg.get_launch(mg.OP_POW, w, "classic")
+        try:
+            mg.set_launch(mg.OP_POW, w, "classic", unroll=unroll)
+            n = 5003
+            x = g.integers(0, N, size=n, dtype=np.uint64).astype(NP_E[w][0])
+            e = inp.u64_uniform(g, n)
+            got = host(mg.pow(mg.setup(N, w), dev(x), dev(e)))
+            assert np.array_equal(got, orc.pow(w, N, x, e)), (w, N, unroll)
+        finally:
+            mg.set_launch(mg.OP_POW, w, "classic", **saved)
+
+
 # -------------------------------------------------------------------- RNS
 
 
