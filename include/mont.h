@@ -247,6 +247,8 @@ typedef struct mont_batch mont_batch_t;
 #define MONT_BATCH_GRAPH 1u   /* replay the launch from a hipGraph */
 #define MONT_BATCH_DYNAMIC 2u /* tiles taken from an atomic counter (else static round-robin) */
 #define MONT_BATCH_TUNE 4u    /* autotune tile size and grid on the first run */
+#define MONT_BATCH_NONTEMPORAL 8u /* reported by mont_batch_info: the launch uses non-temporal
+                                     loads and stores (chosen by the tuner; set by default) */
 
 /*
  * mont_batch_create -- validates every segment (context valid for its
@@ -287,7 +289,7 @@ typedef struct mont_batch_info {
     uint32_t tile_elems; /* elements per tile for 32-bit mul/redc (others scale by bytes) */
     uint32_t grid;       /* workgroups of the persistent launch */
     uint32_t block;
-    uint32_t flags;
+    uint32_t flags;      /* the batch's flags, plus MONT_BATCH_NONTEMPORAL when it applies */
 } mont_batch_info_t;
 mont_status_t mont_batch_info(const mont_batch_t *batch, mont_batch_info_t *info);
 

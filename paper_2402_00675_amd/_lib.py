@@ -25,7 +25,7 @@ VARIANTS = {"classic": CLASSIC, "signed": SIGNED, "plantard": PLANTARD,
             "signed_plantard": SIGNED_PLANTARD, "signed_plantard_alpha": SIGNED_PLANTARD_ALPHA}
 SIGNED_VARIANTS = {SIGNED, SIGNED_PLANTARD, SIGNED_PLANTARD_ALPHA}
 OP_MUL, OP_REDC, OP_POW = 0, 1, 2
-BATCH_GRAPH, BATCH_DYNAMIC, BATCH_TUNE = 1, 2, 4
+BATCH_GRAPH, BATCH_DYNAMIC, BATCH_TUNE, BATCH_NONTEMPORAL = 1, 2, 4, 8
 
 STATUS = {0: "MONT_OK", -1: "MONT_E_INVAL", -2: "MONT_E_DOMAIN", -3: "MONT_E_UNSUPPORTED",
           -4: "MONT_E_NOMEM", -5: "MONT_E_DEVICE", -6: "MONT_E_BUSY"}

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <atomic>
+#include <chrono>
 #include <mutex>
 #include <string>
 
@@ -413,6 +414,16 @@ extern "C" mont_status_t mont_tune_mul(const mont_ctx_t *ctx, const void *a, con
     float best_ms = 1e30f;
     const int unrolls[] = {1, 2, 4};
     const int bpcs[] = {0, 4, 8, 16};
+    // clocks to their loaded state first (about 25 ms of the current shape)
+    {
+        const auto t0 = std::chrono::steady_clock::now();
+        do {
+            for (int r = 0; r < 4 && !rc; ++r)
+                rc = mont_mul(ctx, a, b, out, n, variant, stream);
+            if (!rc && hipStreamSynchronize(s) != hipSuccess)
+                rc = fail(MONT_E_DEVICE, "tuning warm-up failed");
+        } while (!rc && std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(25));
+    }
     // every candidate shape: unroll x non-temporal x workgroups per CU; the first failure ends the sweep
     for (int c = 0; c < 3 * 2 * 4 && !rc; ++c) {
         Launch L;
