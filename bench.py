@@ -337,6 +337,17 @@ def secondary(torch, mg, inp, args, sections):
                 torch.cuda.synchronize()
                 t.append(e0.elapsed_time(e1))
             ex["r16_mul"][name + "_us_median"] = round(float(np.median(t[1:])) * 1e3, 2)
+        # launch floor: the same call over 64 residues (one workgroup), timed the same way
+        t = []
+        for r in range(21):
+            torch.cuda._sleep(100_000)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            mg.mul(c16, a[:64], b[:64], out=o[:64])
+            e1.record()
+            torch.cuda.synchronize()
+            t.append(e0.elapsed_time(e1))
+        ex["r16_mul"]["floor_64_elements_us_median"] = round(float(np.median(t[1:])) * 1e3, 2)
         del flush
         total = w1.N << 16
         ro = torch.empty(total, dtype=torch.uint16, device=dev)
