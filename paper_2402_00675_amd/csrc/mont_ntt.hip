@@ -105,15 +105,47 @@ struct TwL<64, PLANTARD> {
     }
 };
 
-template <class R, int V, bool FAST, class T>
+// LAZY (classic twiddles, 4N <= 2^w: N < 2^30 at w = 32, N < 2^61 at w = 64,
+// the latter so that operands stay below 2^63): coefficients live in [0, 4N)
+// between stages.  The twiddle product without its final subtraction is
+// below 4N^2/R + N <= 2N; u is brought below 2N by one conditional
+// subtraction; then u + t and u - t + 2N both lie in [0, 4N) with no further
+// correction (the lazy butterfly of Harvey's NTT).  Results are reduced to
+// [0, N) once, when they are written out.
+template <class R>
+__device__ __forceinline__ typename R::E lazy_mul(const R &red, typename R::E a, typename R::E b)
+{
+    return red.mul_lazy(a, b);
+}
+template <>
+__device__ __forceinline__ uint64_t lazy_mul(const Red<64, CLASSIC> &red, uint64_t a, uint64_t b)
+{
+    return red.mul_fast(a, b);  // the 64-bit ladder product is already lazy
+}
+
+template <class El>
+__device__ __forceinline__ El below(El x, El m)  // x < 2m  ->  x mod m
+{
+    const El d = (El)(x - m);
+    return d < x ? d : x;
+}
+
+template <class R, int V, bool FAST, bool LAZY, class T>
 __device__ __forceinline__ void butterfly(const R &red, typename R::E &u, typename R::E &v, const T &w,
                                           typename R::E N)
 {
     using El = typename R::E;
-    const El t = tw_mul<R, V, FAST>(red, v, w.get());
-    const El x = u;
-    u = add_mod<El, FAST>(x, t, N);
-    v = sub_mod<El, FAST>(x, t, N);
+    if constexpr (LAZY) {
+        const El t = lazy_mul(red, v, (El)w.get().b);
+        const El x = below<El>(u, (El)(2 * N));
+        u = (El)(x + t);
+        v = (El)((El)(x + 2 * N) - t);
+    } else {
+        const El t = tw_mul<R, V, FAST>(red, v, w.get());
+        const El x = u;
+        u = add_mod<El, FAST>(x, t, N);
+        v = sub_mod<El, FAST>(x, t, N);
+    }
 }
 
 // LDS: n coefficients, then n/2 twiddles.  Pairs of radix-2 stages run as one
@@ -122,7 +154,7 @@ __device__ __forceinline__ void butterfly(const R &red, typename R::E &u, typena
 // With VEC (16-byte aligned polynomials of at least 16 bytes) coefficients
 // move between HBM and LDS in 16-byte chunks; the bit-reversed LDS writes of
 // a chunk's lanes then fall on distinct words.
-template <int W, int V, bool FAST>
+template <int W, int V, bool FAST, bool LAZY>
 __global__ void __launch_bounds__(BLOCK)
     k_ntt(KCtx c, void *__restrict__ data, uint32_t log2n, const TwL<W, V> *__restrict__ tw, KConst scale,
           uint32_t do_scale, uint32_t vec)
@@ -167,10 +199,10 @@ __global__ void __launch_bounds__(BLOCK)
             const uint32_t i0 = ((g >> lh) << (lh + 2)) + j;
             El a0 = s[i0], a1 = s[i0 + len], a2 = s[i0 + 2 * len], a3 = s[i0 + 3 * len];
             const T w0 = ts[j << sh0];
-            butterfly<R, V, FAST>(red, a0, a1, w0, N);
-            butterfly<R, V, FAST>(red, a2, a3, w0, N);
-            butterfly<R, V, FAST>(red, a0, a2, ts[j << sh1], N);
-            butterfly<R, V, FAST>(red, a1, a3, ts[(j + len) << sh1], N);
+            butterfly<R, V, FAST, LAZY>(red, a0, a1, w0, N);
+            butterfly<R, V, FAST, LAZY>(red, a2, a3, w0, N);
+            butterfly<R, V, FAST, LAZY>(red, a0, a2, ts[j << sh1], N);
+            butterfly<R, V, FAST, LAZY>(red, a1, a3, ts[(j + len) << sh1], N);
             s[i0] = a0;
             s[i0 + len] = a1;
             s[i0 + 2 * len] = a2;
@@ -186,23 +218,30 @@ __global__ void __launch_bounds__(BLOCK)
             const uint32_t j = b & (len - 1);
             const uint32_t i0 = ((b >> lh) << (lh + 1)) + j;
             El u = s[i0], v = s[i0 + len];
-            butterfly<R, V, FAST>(red, u, v, ts[j << (log2n - 1 - lh)], N);
+            butterfly<R, V, FAST, LAZY>(red, u, v, ts[j << (log2n - 1 - lh)], N);
             s[i0] = u;
             s[i0 + len] = v;
         }
         __syncthreads();
     }
+    // the output value of a coefficient (scaled by n^{-1} for the inverse; LAZY: from [0, 4N) to [0, N))
+    auto outv = [&](El y) -> El {
+        if constexpr (LAZY)
+            return do_scale ? below<El>(lazy_mul(red, y, (El)scale.b), N) : below<El>(below<El>(y, (El)(2 * N)), N);
+        else
+            return do_scale ? tw_mul<R, V, FAST>(red, y, scale) : y;
+    };
     if (vec) {
         for (uint32_t ci = threadIdx.x; ci < n / E; ci += blockDim.x) {
             El v[E];
 #pragma unroll
             for (int e = 0; e < E; ++e)
-                v[e] = do_scale ? tw_mul<R, V, FAST>(red, s[ci * E + e], scale) : s[ci * E + e];
+                v[e] = outv(s[ci * E + e]);
             store_chunk<El, E, true>(x + ci * E, v);
         }
     } else {
         for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
-            x[i] = do_scale ? tw_mul<R, V, FAST>(red, s[i], scale) : s[i];
+            x[i] = outv(s[i]);
     }
 }
 
@@ -325,20 +364,33 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
     // 16-byte chunks when every polynomial starts on a 16-byte boundary
     const uint32_t vec = ((uintptr_t)data % 16 == 0 && ((size_t)n * sizeof(El)) % 16 == 0) ? 1u : 0u;
     const uint32_t inv = (uint32_t)inverse;
-    // FAST needs N < 2^(w-1); classic twiddles at w >= 32 also the ladder's smaller-modulus bound
+    // FAST needs N < 2^(w-1); classic twiddles at w >= 32 also the ladder's smaller-modulus bound;
+    // LAZY (classic twiddles, w >= 32) needs 4N <= 2^w with operands below 2^63 at w = 64
     const bool small = k.N < (1ull << (W - 1));
     const bool fast = variant == CLASSIC && W != 16 ? fast_ladder<W>(k.N) : small;
+    const bool lazy = variant == CLASSIC && ((W == 32 && k.N < (1ull << 30)) || (W == 64 && k.N < (1ull << 61)));
     const dim3 grid((unsigned)batch), blk(block);
     const auto *twc = (const TwL<W, CLASSIC> *)t.dev;
     const auto *twp = (const TwL<W, PLANTARD> *)t.dev;
+    if constexpr (W != 16) {
+        if (lazy) {
+            hipLaunchKernelGGL((k_ntt<W, CLASSIC, true, true>), grid, blk, lds, s, k, data, log2n, twc, t.scale, inv,
+                               vec);
+            return hipGetLastError();
+        }
+    }
     if (variant == CLASSIC && fast)
-        hipLaunchKernelGGL((k_ntt<W, CLASSIC, true>), grid, blk, lds, s, k, data, log2n, twc, t.scale, inv, vec);
+        hipLaunchKernelGGL((k_ntt<W, CLASSIC, true, false>), grid, blk, lds, s, k, data, log2n, twc, t.scale, inv,
+                           vec);
     else if (variant == CLASSIC)
-        hipLaunchKernelGGL((k_ntt<W, CLASSIC, false>), grid, blk, lds, s, k, data, log2n, twc, t.scale, inv, vec);
+        hipLaunchKernelGGL((k_ntt<W, CLASSIC, false, false>), grid, blk, lds, s, k, data, log2n, twc, t.scale, inv,
+                           vec);
     else if (fast)
-        hipLaunchKernelGGL((k_ntt<W, PLANTARD, true>), grid, blk, lds, s, k, data, log2n, twp, t.scale, inv, vec);
+        hipLaunchKernelGGL((k_ntt<W, PLANTARD, true, false>), grid, blk, lds, s, k, data, log2n, twp, t.scale, inv,
+                           vec);
     else
-        hipLaunchKernelGGL((k_ntt<W, PLANTARD, false>), grid, blk, lds, s, k, data, log2n, twp, t.scale, inv, vec);
+        hipLaunchKernelGGL((k_ntt<W, PLANTARD, false, false>), grid, blk, lds, s, k, data, log2n, twp, t.scale, inv,
+                           vec);
     return hipGetLastError();
 }
 

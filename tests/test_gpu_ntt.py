@@ -38,6 +38,7 @@ CASES = [
     (32, 2013265921, [6, 11]),
     (32, 3221225473, [5, 10]),                # above 2^31: the general classic product
     (64, prime_1_mod(62, 12, 1), [2, 8, 12]),
+    (64, prime_1_mod(60, 12, 1), [3, 10]),    # below 2^61: lazy butterflies (8380417 takes them at w = 32)
     (64, GOLDILOCKS, [3, 9]),
 ]
 DT = {16: np.uint16, 32: np.uint32, 64: np.uint64}
