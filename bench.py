@@ -391,6 +391,16 @@ def secondary(torch, mg, inp, args, sections):
             pw["w%d" % w] = {"Gpow_s": round(rate, 3), "ms": round(ms, 3),
                              "Gmontmul_s": round(rate * 97, 1)}  # 3 + 31 windows x 3 + 1 products
             log("pow w%d: %.3f Gpow/s" % (w, rate))
+        # a modulus below 2^30 (the 32-bit workload's N = 8380417): lazy 32-bit ladder products
+        N = 8380417
+        x = torch.from_numpy(inp.uniform_residues(g, N, n, np.uint32)).to(dev)
+        e = torch.from_numpy(inp.u64_uniform(g, n)).to(dev)
+        o = torch.empty_like(x)
+        c = mg.setup(N, 32)
+        _, ms = timed_sec(lambda: mg.pow(c, x, e, out=o), torch)
+        rate = n / (ms * 1e-3) / 1e9
+        pw["w32_N8380417"] = {"Gpow_s": round(rate, 3), "ms": round(ms, 3), "Gmontmul_s": round(rate * 97, 1)}
+        log("pow w32, N = 8380417: %.3f Gpow/s" % rate)
         ex["pow"] = pw
 
     if "ragged" in sections:

@@ -289,14 +289,16 @@ struct Red<32, CLASSIC> {
         return min(t, t - N);
     }
     __device__ __forceinline__ E sqr_fast(E a) const { return mul_fast(a, a); }
-    // (T + mN)/R without the final subtraction, for N < 2^30, a < 4N and b < N:
-    // T + mN < 4N^2 + 2^32 N < 2^63 and the result is below 4N^2/R + N <= 2N.
+    // (T + mN)/R without the final subtraction, for N < 2^30 and a b < 4N^2
+    // (say a < 4N and b < N, or both below 2N): T + mN < 4N^2 + 2^32 N < 2^63
+    // and the result is below 4N^2/R + N <= 2N.
     __device__ __forceinline__ E mul_lazy(E a, E b) const
     {
         const uint64_t T = (uint64_t)a * b;
         const uint32_t m = (uint32_t)T * np;
         return (uint32_t)(((uint64_t)m * N + T) >> 32);
     }
+    __device__ __forceinline__ E sqr_lazy(E a) const { return mul_lazy(a, a); }
     __device__ __forceinline__ E mul_const(E a, const KConst &k) const
     {
         const uint64_t T = (uint64_t)a * (uint32_t)k.b;

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <algorithm>
+#include <type_traits>
 
 #include "mont_kernels.hpp"
 
@@ -104,22 +105,32 @@ hipError_t launch_pow(const KCtx &c, const void *x, const uint64_t *e, void *out
     L.blocks_per_cu = blocks_per_cu;
     const int U = (unroll == 2 || unroll == 4) ? unroll : 1;
     dim3 grid((unsigned)grid_x(n, U, 1, L));
-    // smaller-modulus ladder forms: lazy products for w = 64, N < 2^62; 32-bit registers for w = 32, N < 2^31
-    if (fast_ladder<W>(c.N)) {
-        constexpr bool F = W != 16;
+    // ladder mode by modulus (see ladder_mode): lazy products for w = 64, N < 2^62;
+    // 32-bit registers for w = 32, N < 2^31; lazy 32-bit products for N < 2^30
+    const int mode = ladder_mode<W>(c.N);
+    auto go = [&](auto mode_c) {
+        constexpr int M = decltype(mode_c)::value;
         if (U == 4)
-            hipLaunchKernelGGL((k_pow<W, 4, F>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
+            hipLaunchKernelGGL((k_pow<W, 4, M>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
         else if (U == 2)
-            hipLaunchKernelGGL((k_pow<W, 2, F>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
+            hipLaunchKernelGGL((k_pow<W, 2, M>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
         else
-            hipLaunchKernelGGL((k_pow<W, 1, F>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
+            hipLaunchKernelGGL((k_pow<W, 1, M>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
+    };
+    if constexpr (W == 32) {
+        if (mode == 2)
+            go(std::integral_constant<int, 2>{});
+        else if (mode == 1)
+            go(std::integral_constant<int, 1>{});
+        else
+            go(std::integral_constant<int, 0>{});
+    } else if constexpr (W == 64) {
+        if (mode == 1)
+            go(std::integral_constant<int, 1>{});
+        else
+            go(std::integral_constant<int, 0>{});
     } else {
-        if (U == 4)
-            hipLaunchKernelGGL((k_pow<W, 4, false>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
-        else if (U == 2)
-            hipLaunchKernelGGL((k_pow<W, 2, false>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
-        else
-            hipLaunchKernelGGL((k_pow<W, 1, false>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
+        go(std::integral_constant<int, 0>{});
     }
     return hipGetLastError();
 }

@@ -213,29 +213,41 @@ struct WideT<64> {
 };
 
 
-// Ladder products.  FAST selects the classic forms that need a smaller
-// modulus: for w = 64 and N < 2^62 the final subtraction is dropped ("lazy":
-// for 4N <= R and inputs below 2N, (T + mN)/R < 4N^2/R + N <= 2N, so every
-// result stays below 2N and is a valid input again); for w = 32 and N < 2^31
-// the whole reduction runs in 32-bit registers with fully reduced results.
+// Ladder products by mode.  0: the general classic product.  1 (FAST, the
+// classic forms that need a smaller modulus): for w = 64 and N < 2^62 the
+// final subtraction is dropped ("lazy": for 4N <= R and inputs below 2N,
+// (T + mN)/R < 4N^2/R + N <= 2N, so every result stays below 2N and is a valid
+// input again); for w = 32 and N < 2^31 the whole reduction runs in 32-bit
+// registers with fully reduced results.  2 (w = 32 and N < 2^30): lazy as
+// well, three instructions per product (no subtraction, no minimum).
 template <int W>
 __host__ __device__ __forceinline__ bool fast_ladder(uint64_t N)
 {
     return (W == 64 && N < (1ull << 62)) || (W == 32 && N < (1ull << 31));
 }
 
-template <class R, bool FAST>
+template <int W>
+__host__ __device__ __forceinline__ int ladder_mode(uint64_t N)
+{
+    return (W == 32 && N < (1ull << 30)) ? 2 : fast_ladder<W>(N) ? 1 : 0;
+}
+
+template <class R, int MODE>
 struct Ladder {
     __device__ __forceinline__ static typename R::E mul(const R &r, typename R::E a, typename R::E b)
     {
-        if constexpr (FAST)
+        if constexpr (MODE == 2)
+            return r.mul_lazy(a, b);
+        else if constexpr (MODE == 1)
             return r.mul_fast(a, b);
         else
             return r.mul(a, b);
     }
     __device__ __forceinline__ static typename R::E sqr(const R &r, typename R::E a)
     {
-        if constexpr (FAST)
+        if constexpr (MODE == 2)
+            return r.sqr_lazy(a);
+        else if constexpr (MODE == 1)
             return r.sqr_fast(a);
         else
             return r.sqr(a);
@@ -246,18 +258,18 @@ struct Ladder {
 // chains per wave): Montgomery form x R = REDC(x * (R^2 mod N)), a
 // left-to-right 2-bit fixed-window ladder of Montgomery products (every lane
 // runs the same 32 windows: no divergence); the caller converts back with one
-// REDC.  The returned Montgomery-form values are below 2N (FAST with w = 64)
-// or below N.  Element u's four window entries (1, x, x^2, x^3 in Montgomery
+// REDC.  The returned Montgomery-form values are below 2N (modes 1 at w = 64
+// and 2) or below N.  Element u's four window entries (1, x, x^2, x^3 in Montgomery
 // form) live in LDS at tab[u * BLOCK + j * stride], j = 0..3: one LDS read per
 // window instead of a 4-way register select.  Lanes of a wave use adjacent
 // words of each entry row, so the reads are free of bank conflicts.
-template <class R, bool FAST, int U>
+template <class R, int MODE, int U>
 __device__ __forceinline__ void pow_lanes(const R &red, const typename R::E (&x)[U], const uint64_t (&k)[U],
                                           typename R::E r2, typename R::E one, typename R::E *tab, uint32_t stride,
                                           typename R::E (&y)[U])
 {
     using El = typename R::E;
-    using L = Ladder<R, FAST>;
+    using L = Ladder<R, MODE>;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         El *t = tab + u * BLOCK;
@@ -290,7 +302,7 @@ __device__ __forceinline__ void pow_lanes(const R &red, const typename R::E (&x)
     }
 }
 
-template <int W, int U, bool FAST>
+template <int W, int U, int MODE>
 __global__ void __launch_bounds__(BLOCK)
     k_pow(KCtx c, const void *__restrict__ xin, const uint64_t *__restrict__ ein, void *__restrict__ out, uint64_t n)
 {
@@ -312,7 +324,7 @@ __global__ void __launch_bounds__(BLOCK)
             k[u] = i < n ? ein[i] : 0;
         }
         El y[U];
-        pow_lanes<R, FAST, U>(red, x, k, r2, one, tab + threadIdx.x, BLOCK * U, y);
+        pow_lanes<R, MODE, U>(red, x, k, r2, one, tab + threadIdx.x, BLOCK * U, y);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint64_t i = base + (uint64_t)u * BLOCK;

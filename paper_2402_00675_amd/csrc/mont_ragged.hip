@@ -121,16 +121,18 @@ __device__ __forceinline__ void tile_pow(const KCtx &c, const DPools &P, uint64_
     El *po = (El *)P.out[wc];
     __shared__ El tab[4 * BLOCK];
     El *const mine = tab + threadIdx.x;
-    const bool fast = fast_ladder<W>(c.N);  // wave-uniform
+    const int mode = ladder_mode<W>(c.N);  // wave-uniform
     for (uint32_t i = threadIdx.x; i < cnt; i += BLOCK) {
         const uint64_t g = g0 + i;
         const El x[1] = {px[g]};
         const uint64_t k[1] = {pe[g]};
         El y[1];
-        if (fast)
-            pow_lanes<R, W != 16, 1>(red, x, k, r2, one, mine, BLOCK, y);
+        if (W == 32 && mode == 2)
+            pow_lanes<R, W == 32 ? 2 : 0, 1>(red, x, k, r2, one, mine, BLOCK, y);
+        else if (mode)
+            pow_lanes<R, W != 16 ? 1 : 0, 1>(red, x, k, r2, one, mine, BLOCK, y);
         else
-            pow_lanes<R, false, 1>(red, x, k, r2, one, mine, BLOCK, y);
+            pow_lanes<R, 0, 1>(red, x, k, r2, one, mine, BLOCK, y);
         po[g] = red.redc(WideT<W>::of(y[0]));
     }
 }

@@ -312,9 +312,9 @@ def test_range_top_of_classic_w32():
 def test_pow_parity(w):
     dt = NP_E[w][0]
     g = inp.rng(96, w)
-    # both sides of the smaller-modulus ladder forms: N < 2^31 (w = 32), N < 2^62 (w = 64)
+    # both sides of the smaller-modulus ladder forms: N < 2^30 and N < 2^31 (w = 32), N < 2^62 (w = 64)
     Ns = {16: [3, 3329, 65521, 65535],
-          32: [3, 8380417, (1 << 31) - 1, (1 << 31) + 1, (1 << 30) + 3, 4294967291],
+          32: [3, 8380417, (1 << 30) - 35, (1 << 30) + 3, (1 << 31) - 1, (1 << 31) + 1, 4294967291],
           64: [3, (1 << 61) - 1, (1 << 62) - 57, (1 << 62) - 1, (1 << 62) + 1, (1 << 64) - 59]}[w]
     for N in Ns:
         n = 20_011
@@ -334,7 +334,7 @@ def test_pow_parity(w):
 def test_pow_launch_shapes(unroll):
     """Every lockstep width of the ladder (elements per lane) gives the same results."""
     g = inp.rng(96, 100 + unroll)
-    for w, N in ((32, (1 << 31) - 1), (32, 4294967291), (64, (1 << 62) - 57), (64, (1 << 64) - 59)):
+    for w, N in ((32, 8380417), (32, (1 << 31) - 1), (32, 4294967291), (64, (1 << 62) - 57), (64, (1 << 64) - 59)):
         saved = mg.get_launch(mg.OP_POW, w, "classic")
         try:
             mg.set_launch(mg.OP_POW, w, "classic", unroll=unroll)
