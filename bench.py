@@ -151,10 +151,21 @@ def main():
         if not np.array_equal(out_h[i, idx], want):
             raise SystemExit("bench: output mismatch against the oracle on row %d" % i)
 
+    # per-launch median over 21 launches, each bracketed by its own events (after the timed region)
+    per = []
+    for _ in range(21):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        step()
+        e1.record()
+        per.append((e0, e1))
+    torch.cuda.synchronize()
+    ms_median = float(np.median([x.elapsed_time(y) for x, y in per[1:]]))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(units),
                 "kernel": "k_map<64,classic,mul> (mont_mul_rns)", "bytes_per_unit": 24,
-                "units_per_launch": units, "ms_per_launch": round(ms_launch, 4)}
+                "units_per_launch": units, "ms_per_launch": round(ms_launch, 4),
+                "ms_per_launch_median": round(ms_median, 4)}
 
     # -------------------------------------------------------- CPU baseline
     cpu = None
