@@ -319,8 +319,19 @@ def secondary(torch, mg, inp, args, sections):
                       "Gbutterfly_s": round(batch * n // 2 * log2n / (ms * 1e-3) / 1e9, 1),
                       "GB_s": round(8 * batch * n / (ms * 1e-3) / 1e9, 1)}
             log("ntt %s: %s" % (v, res[v]))
+        # the same shape over the 16-bit modulus N = 3329 (2^18 transforms of length 256)
+        N16 = 3329
+        c16 = mg.setup(N16, 16)
+        root16 = next(w for w in (pow(g, (N16 - 1) // n, N16) for g in range(2, 100)) if pow(w, n // 2, N16) == N16 - 1)
+        d16 = torch.from_numpy(inp.uniform_residues(inp.rng(inp.W_R16, 9), N16, batch * n, np.uint16)).to(dev)
+        d16 = d16.view(batch, n)
+        for v in ("classic", "plantard"):
+            _, ms = timed_sec(lambda: mg.ntt(c16, d16, root16, variant=v), torch)
+            res["w16_N3329_" + v] = {"ms": round(ms, 3), "Gcoef_s": round(batch * n / (ms * 1e-3) / 1e9, 1),
+                                      "GB_s": round(4 * batch * n / (ms * 1e-3) / 1e9, 1)}
+            log("ntt w16 N=3329 %s: %s" % (v, res["w16_N3329_" + v]))
         ex["ntt"] = res
-        del d
+        del d, d16
 
     if "r16" in sections:
         # 16-bit workload: N = 3329, 2^20 residues + the exhaustive REDC sweep

@@ -161,6 +161,15 @@ struct Red<16, CLASSIC> {
     }
     __device__ __forceinline__ E mul(E a, E b) const { return redc((uint32_t)a * (uint32_t)b); }
     __device__ __forceinline__ E sqr(E a) const { return mul(a, a); }
+    // (T + mN)/R without the final subtraction, for N < 2^14 and a b < 4N^2:
+    // T + mN < 2^30 + 2^30 fits a 32-bit word and the result is below
+    // 4N^2/R + N <= 2N.
+    __device__ __forceinline__ E mul_lazy(E a, E b) const
+    {
+        const uint32_t T = (uint32_t)a * (uint32_t)b;
+        const uint32_t m = (T * np) & 0xffffu;
+        return (E)((m * N + T) >> 16);
+    }
     __device__ __forceinline__ E mul_const(E a, const KConst &k) const
     {
         const uint32_t T = (uint32_t)a * (uint32_t)k.b;

@@ -105,8 +105,9 @@ struct TwL<64, PLANTARD> {
     }
 };
 
-// LAZY (classic twiddles, 4N <= 2^w: N < 2^30 at w = 32, N < 2^61 at w = 64,
-// the latter so that operands stay below 2^63): coefficients live in [0, 4N)
+// LAZY (classic twiddles, 4N <= 2^w: N < 2^14 at w = 16, N < 2^30 at w = 32,
+// N < 2^61 at w = 64, the latter so that operands stay below 2^63):
+// coefficients live in [0, 4N)
 // between stages.  The twiddle product without its final subtraction is
 // below 4N^2/R + N <= 2N; u is brought below 2N by one conditional
 // subtraction; then u + t and u - t + 2N both lie in [0, 4N) with no further
@@ -365,19 +366,17 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
     const uint32_t vec = ((uintptr_t)data % 16 == 0 && ((size_t)n * sizeof(El)) % 16 == 0) ? 1u : 0u;
     const uint32_t inv = (uint32_t)inverse;
     // FAST needs N < 2^(w-1); classic twiddles at w >= 32 also the ladder's smaller-modulus bound;
-    // LAZY (classic twiddles, w >= 32) needs 4N <= 2^w with operands below 2^63 at w = 64
+    // LAZY (classic twiddles) needs 4N <= 2^w, with operands below 2^63 at w = 64
     const bool small = k.N < (1ull << (W - 1));
     const bool fast = variant == CLASSIC && W != 16 ? fast_ladder<W>(k.N) : small;
-    const bool lazy = variant == CLASSIC && ((W == 32 && k.N < (1ull << 30)) || (W == 64 && k.N < (1ull << 61)));
+    const bool lazy = variant == CLASSIC && ((W == 16 && k.N < (1ull << 14)) || (W == 32 && k.N < (1ull << 30)) ||
+                                             (W == 64 && k.N < (1ull << 61)));
     const dim3 grid((unsigned)batch), blk(block);
     const auto *twc = (const TwL<W, CLASSIC> *)t.dev;
     const auto *twp = (const TwL<W, PLANTARD> *)t.dev;
-    if constexpr (W != 16) {
-        if (lazy) {
-            hipLaunchKernelGGL((k_ntt<W, CLASSIC, true, true>), grid, blk, lds, s, k, data, log2n, twc, t.scale, inv,
-                               vec);
-            return hipGetLastError();
-        }
+    if (lazy) {
+        hipLaunchKernelGGL((k_ntt<W, CLASSIC, true, true>), grid, blk, lds, s, k, data, log2n, twc, t.scale, inv, vec);
+        return hipGetLastError();
     }
     if (variant == CLASSIC && fast)
         hipLaunchKernelGGL((k_ntt<W, CLASSIC, true, false>), grid, blk, lds, s, k, data, log2n, twc, t.scale, inv,

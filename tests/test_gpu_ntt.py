@@ -30,7 +30,7 @@ def prime_1_mod(bits, log2n, seed):
 
 
 CASES = [
-    (16, 12289, [1, 3, 8, 12]),
+    (16, 12289, [1, 3, 8, 12]),               # below 2^14: lazy butterflies (so is 3329)
     (16, 3329, [2, 8]),
     (16, 36097, [3, 8]),                      # above 2^15: wrap-checked modular add/subtract (both twiddle forms)
     (16, 40961, [4, 12]),                     # above 2^16/phi: classic only
