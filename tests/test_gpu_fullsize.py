@@ -137,3 +137,35 @@ def test_serving_stream_sampled():
     assert not bad, bad[:10]
     assert sum(1 for i in sample if stream.ops[i] == 0) > 400    # both kinds are well represented
     assert sum(1 for i in sample if stream.ops[i] == 1) > 300
+
+
+def test_crt_bench_shape_sampled():
+    """CRT reconstruction at the benchmark's shape (2^25 integers from the 8 rows
+    of the 64-bit RNS workload), every 8191st element and the last one checked."""
+    wl = inp.RNS64Workload()
+    a, _ = wl.operands()
+    ctxs = [mg.setup(N, 64) for N in wl.moduli]
+    got = mg.crt(ctxs, dev(a)).cpu().numpy().view(np.uint64)
+    idx = list(range(0, wl.n, 8191)) + [wl.n - 1]
+    want = orc.crt([[int(x) for x in a[j, idx]] for j in range(wl.k)], wl.moduli)
+    have = [sum(int(x) << (64 * w) for w, x in enumerate(got[i])) for i in idx]
+    assert have == want
+
+
+@pytest.mark.parametrize("variant", ["classic", "plantard"])
+def test_ntt_bench_shape_sampled(variant):
+    """NTTs at the benchmark's shape (2^18 transforms of length 256 over
+    N = 8380417), forward and back; 64 seeded transforms checked against the DFT
+    by its definition, and the round trip checked in full."""
+    N, n, batch = 8380417, 256, 1 << 18
+    c = mg.setup(N, 32)
+    root = next(w for w in (pow(q, (N - 1) // n, N) for q in range(2, 100)) if pow(w, n // 2, N) == N - 1)
+    x = inp.uniform_residues(inp.rng(inp.W_R32, 9), N, batch * n, np.uint32).reshape(batch, n)
+    d = dev(x)
+    mg.ntt(c, d, root, variant=variant)
+    got = d.cpu().numpy()
+    rows = np.random.default_rng(5).choice(batch, size=64, replace=False)
+    for r in rows:
+        assert np.array_equal(got[r], orc.dft(32, N, x[r], root)), r
+    mg.ntt(c, d, root, inverse=True, variant=variant)
+    assert np.array_equal(d.cpu().numpy(), x)
