@@ -151,7 +151,11 @@ struct Red<16, CLASSIC> {
     using E = uint16_t;
     using TT = uint32_t;
     uint32_t N, np;
-    __device__ __forceinline__ explicit Red(const KCtx &c) : N((uint32_t)c.N), np((uint32_t)c.nprime & 0xffffu) {}
+    uint16_t np16, N16;  // the same constants as 16-bit values (for 16-bit multiplies)
+    __device__ __forceinline__ explicit Red(const KCtx &c)
+        : N((uint32_t)c.N), np((uint32_t)c.nprime & 0xffffu), np16((uint16_t)c.nprime), N16((uint16_t)c.N)
+    {
+    }
     __device__ __forceinline__ E redc(TT T) const
     {
         const uint32_t tl = T & 0xffffu;
@@ -163,12 +167,13 @@ struct Red<16, CLASSIC> {
     __device__ __forceinline__ E sqr(E a) const { return mul(a, a); }
     // (T + mN)/R without the final subtraction, for N < 2^14 and a b < 4N^2:
     // T + mN < 2^30 + 2^30 fits a 32-bit word and the result is below
-    // 4N^2/R + N <= 2N.
+    // 4N^2/R + N <= 2N.  m is formed by a 16-bit multiply (only T mod R
+    // matters), so T, m and T + mN take three instructions.
     __device__ __forceinline__ E mul_lazy(E a, E b) const
     {
         const uint32_t T = (uint32_t)a * (uint32_t)b;
-        const uint32_t m = (T * np) & 0xffffu;
-        return (E)((m * N + T) >> 16);
+        const uint16_t m = (uint16_t)((uint16_t)T * np16);
+        return (E)(((uint32_t)m * (uint32_t)N16 + T) >> 16);
     }
     __device__ __forceinline__ E mul_const(E a, const KConst &k) const
     {

@@ -7,7 +7,10 @@
 // polynomials of n residues in [0, N) stored contiguously (natural order in
 // and out, in place).
 //
-// One workgroup transforms one polynomial: coefficients are loaded into LDS
+// Length 256 (k_ntt256): one wavefront per polynomial, coefficients loaded
+// from HBM straight into registers in bit-reversed order and exchanged between
+// radix-4 steps through a conflict-free LDS layout.  Other lengths (k_ntt):
+// one workgroup transforms one polynomial: coefficients are loaded into LDS
 // in bit-reversed order together with the compact twiddles, the log2(n)
 // radix-2 Cooley-Tukey stages run two at a time as radix-4 steps in registers
 // (a barrier between steps), and the result is written back (scaled by n^{-1}
@@ -246,6 +249,156 @@ __global__ void __launch_bounds__(BLOCK)
     }
 }
 
+// Butterfly by the unit twiddle (the first two stages of a bit-reversed
+// decimation-in-time transform multiply by 1 or by w^(n/4) only).  LAZY:
+// u, v < 2N give u + v < 4N and u - v + 2N in (0, 4N).
+// Workgroups per CU for the length-256 kernel (its waves loop over the batch).
+constexpr int NTT256_BPC = 8;
+
+template <class El, bool FAST, bool LAZY>
+__device__ __forceinline__ void butterfly1(El &u, El &v, El N)
+{
+    const El x = u;
+    if constexpr (LAZY) {
+        u = (El)(x + v);
+        v = (El)((El)(x + 2 * N) - v);
+    } else {
+        u = add_mod<El, FAST>(x, v, N);
+        v = sub_mod<El, FAST>(x, v, N);
+    }
+}
+
+// Four coefficients of one lane into its 4 consecutive LDS slots, one LDS
+// write (two for 64-bit words).
+template <class El>
+__device__ __forceinline__ void lds_put4(El *p, const El (&a)[4])
+{
+    if constexpr (sizeof(El) == 2) {
+        uint2 v;
+        v.x = (uint32_t)a[0] | ((uint32_t)a[1] << 16);
+        v.y = (uint32_t)a[2] | ((uint32_t)a[3] << 16);
+        *(uint2 *)p = v;
+    } else if constexpr (sizeof(El) == 4) {
+        *(uint4 *)p = make_uint4(a[0], a[1], a[2], a[3]);
+    } else {
+        *(ulonglong2 *)p = make_ulonglong2(a[0], a[1]);
+        *(ulonglong2 *)(p + 2) = make_ulonglong2(a[2], a[3]);
+    }
+}
+
+// Length-256 transforms, one wavefront per polynomial, no block barriers.
+//
+// Positions P (0..255) of the bit-reversed array split into four 2-bit fields
+// F0..F3 (F_s = bits 2s, 2s+1); radix-4 step s runs stages 2s and 2s+1 on the
+// groups of four positions that differ only in F_s.  A lane owns one group per
+// step, in registers:
+//   step 0  lane = brev6(F1 + 4 F2 + 16 F3); coefficient x[lane + 64 brev2(k)]
+//           is slot k (F0 = k) of the bit-reversed array, so each of the four
+//           HBM loads reads 64 consecutive words
+//   step 1  lane = F0 + 4 F3 + 16 F2       (slot F1)
+//   step 2  lane = F0 + 4 F1 + 16 F3       (slot F2)
+//   step 3  lane = F0 + 4 F1 + 16 F2       (slot F3): outputs x[lane + 64 k],
+//           again 64 consecutive words per store
+// Between steps each lane writes its four slots to 16 consecutive bytes of the
+// wave's LDS buffer at 16 lane (conflict-free: 16 lanes fill the 64 four-byte
+// banks) and reads the next group at base_s + 64 k (immediate offsets), where
+// the bases of the 64 lanes are 64 distinct banks:
+//   base_1 = F0 + 4 brev2(F3) + 16 brev2(F2)   (slot k at base_1 + 64 brev2(k))
+//   base_2 = F1 + 4 F0 + 16 F3
+//   base_3 = F2 + 4 F0 + 16 F1
+// The twiddles of a lane are the same for every polynomial and stay in
+// registers; waves loop over polynomials (the next one's loads in flight).
+template <int W, int V, bool FAST, bool LAZY>
+__global__ void __launch_bounds__(BLOCK)
+    k_ntt256(KCtx c, void *__restrict__ data, uint64_t batch, const TwL<W, V> *__restrict__ tw, KConst scale,
+             uint32_t do_scale)
+{
+    using R = Red<W, V>;
+    using El = typename R::E;
+    using T = TwL<W, V>;
+    constexpr int WAVES = BLOCK / 64;
+    __shared__ __align__(16) El lds[WAVES][256];
+    const R red(c);
+    const El N = (El)c.N;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    El *s = lds[wv];
+    auto br2 = [](uint32_t f) { return ((f & 1u) << 1) | (f >> 1); };
+    const uint32_t f0 = lane & 3u, f1 = (lane >> 2) & 3u, f2 = lane >> 4;
+    const uint32_t base1 = f0 + 4 * br2(f1) + 16 * br2(f2);  // step-1 lane: F0 = f0, F3 = f1, F2 = f2
+    const uint32_t base2 = f1 + 4 * f0 + 16 * f2;            // step-2 lane: F0 = f0, F1 = f1, F3 = f2
+    const uint32_t base3 = f2 + 4 * f0 + 16 * f1;            // step-3 lane: F0 = f0, F1 = f1, F2 = f2
+    const uint32_t j2 = f0 + 4 * f1;
+    // stage st pairs at distance 2^st use twiddle w^(j 2^(7 - st)) = tw[j << (7 - st)]
+    const T t01 = tw[64];
+    const T t10 = tw[f0 << 5], t11 = tw[f0 << 4], t12 = tw[(f0 + 4) << 4];
+    const T t20 = tw[j2 << 3], t21 = tw[j2 << 2], t22 = tw[(j2 + 16) << 2];
+    const T t30 = tw[lane << 1], t31 = tw[lane], t32 = tw[lane + 64];
+    auto outv = [&](El y) -> El {
+        if constexpr (LAZY)
+            return do_scale ? below<El>(lazy_mul(red, y, (El)scale.b), N) : below<El>(below<El>(y, (El)(2 * N)), N);
+        else
+            return do_scale ? tw_mul<R, V, FAST>(red, y, scale) : y;
+    };
+    const uint64_t stride = (uint64_t)gridDim.x * WAVES;
+    uint64_t t = (uint64_t)blockIdx.x * WAVES + wv;
+    El nx[4];
+    auto fetch = [&](uint64_t p) {
+        const El *x = (const El *)data + (p << 8) + lane;
+        nx[0] = x[0];
+        nx[1] = x[128];
+        nx[2] = x[64];
+        nx[3] = x[192];
+    };
+    if (t < batch)
+        fetch(t);
+    for (; t < batch; t += stride) {
+        El a[4] = {nx[0], nx[1], nx[2], nx[3]};
+        if (t + stride < batch)
+            fetch(t + stride);
+        // step 0: stage 0 (unit twiddles), stage 1 (1 and w^64)
+        butterfly1<El, FAST, LAZY>(a[0], a[1], N);
+        butterfly1<El, FAST, LAZY>(a[2], a[3], N);
+        butterfly1<El, FAST, LAZY>(a[0], a[2], N);
+        butterfly<R, V, FAST, LAZY>(red, a[1], a[3], t01, N);
+        lds_put4<El>(s + 4 * lane, a);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        a[0] = s[base1];
+        a[1] = s[base1 + 128];
+        a[2] = s[base1 + 64];
+        a[3] = s[base1 + 192];
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        butterfly<R, V, FAST, LAZY>(red, a[0], a[1], t10, N);
+        butterfly<R, V, FAST, LAZY>(red, a[2], a[3], t10, N);
+        butterfly<R, V, FAST, LAZY>(red, a[0], a[2], t11, N);
+        butterfly<R, V, FAST, LAZY>(red, a[1], a[3], t12, N);
+        lds_put4<El>(s + 4 * lane, a);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            a[k] = s[base2 + 64 * k];
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        butterfly<R, V, FAST, LAZY>(red, a[0], a[1], t20, N);
+        butterfly<R, V, FAST, LAZY>(red, a[2], a[3], t20, N);
+        butterfly<R, V, FAST, LAZY>(red, a[0], a[2], t21, N);
+        butterfly<R, V, FAST, LAZY>(red, a[1], a[3], t22, N);
+        lds_put4<El>(s + 4 * lane, a);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            a[k] = s[base3 + 64 * k];
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        butterfly<R, V, FAST, LAZY>(red, a[0], a[1], t30, N);
+        butterfly<R, V, FAST, LAZY>(red, a[2], a[3], t30, N);
+        butterfly<R, V, FAST, LAZY>(red, a[0], a[2], t31, N);
+        butterfly<R, V, FAST, LAZY>(red, a[1], a[3], t32, N);
+        El *y = (El *)data + (t << 8) + lane;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            y[64 * k] = outv(a[k]);
+    }
+}
+
 typedef unsigned __int128 u128;
 
 static uint64_t mulmod(uint64_t a, uint64_t b, uint64_t N) { return (uint64_t)(((u128)a * b) % N); }
@@ -374,6 +527,24 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
     const dim3 grid((unsigned)batch), blk(block);
     const auto *twc = (const TwL<W, CLASSIC> *)t.dev;
     const auto *twp = (const TwL<W, PLANTARD> *)t.dev;
+    if (log2n == 8) {
+        // one wavefront per polynomial, waves looping over the batch
+        constexpr uint64_t WAVES = BLOCK / 64;
+        const uint64_t blocks = std::min<uint64_t>((batch + WAVES - 1) / WAVES, (uint64_t)device_cus() * NTT256_BPC);
+        const dim3 g((unsigned)blocks), b(BLOCK);
+        const uint64_t nb = batch;
+        if (lazy)
+            hipLaunchKernelGGL((k_ntt256<W, CLASSIC, true, true>), g, b, 0, s, k, data, nb, twc, t.scale, inv);
+        else if (variant == CLASSIC && fast)
+            hipLaunchKernelGGL((k_ntt256<W, CLASSIC, true, false>), g, b, 0, s, k, data, nb, twc, t.scale, inv);
+        else if (variant == CLASSIC)
+            hipLaunchKernelGGL((k_ntt256<W, CLASSIC, false, false>), g, b, 0, s, k, data, nb, twc, t.scale, inv);
+        else if (fast)
+            hipLaunchKernelGGL((k_ntt256<W, PLANTARD, true, false>), g, b, 0, s, k, data, nb, twp, t.scale, inv);
+        else
+            hipLaunchKernelGGL((k_ntt256<W, PLANTARD, false, false>), g, b, 0, s, k, data, nb, twp, t.scale, inv);
+        return hipGetLastError();
+    }
     if (lazy) {
         hipLaunchKernelGGL((k_ntt<W, CLASSIC, true, true>), grid, blk, lds, s, k, data, log2n, twc, t.scale, inv, vec);
         return hipGetLastError();
