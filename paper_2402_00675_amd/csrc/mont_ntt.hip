@@ -7,9 +7,9 @@
 // polynomials of n residues in [0, N) stored contiguously (natural order in
 // and out, in place).
 //
-// Length 256 (k_ntt256): one wavefront per polynomial, coefficients loaded
-// from HBM straight into registers in bit-reversed order and exchanged between
-// radix-4 steps through a conflict-free LDS layout.  Other lengths (k_ntt):
+// Lengths 256, 512, 1024 (k_nttw): one wavefront per polynomial, coefficients
+// loaded from HBM straight into registers in bit-reversed order and exchanged
+// between radix-4 steps through a conflict-free LDS layout.  Other lengths (k_ntt):
 // one workgroup transforms one polynomial: coefficients are loaded into LDS
 // in bit-reversed order together with the compact twiddles, the log2(n)
 // radix-2 Cooley-Tukey stages run two at a time as radix-4 steps in registers
@@ -27,6 +27,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "mont_common.hpp"
@@ -252,8 +253,8 @@ __global__ void __launch_bounds__(BLOCK)
 // Butterfly by the unit twiddle (the first two stages of a bit-reversed
 // decimation-in-time transform multiply by 1 or by w^(n/4) only).  LAZY:
 // u, v < 2N give u + v < 4N and u - v + 2N in (0, 4N).
-// Workgroups per CU for the length-256 kernel (its waves loop over the batch).
-constexpr int NTT256_BPC = 8;
+// Workgroups per CU for the one-wave-per-polynomial kernel (its waves loop over the batch).
+constexpr int NTTW_BPC = 8;
 
 template <class El, bool FAST, bool LAZY>
 __device__ __forceinline__ void butterfly1(El &u, El &v, El N)
@@ -286,54 +287,79 @@ __device__ __forceinline__ void lds_put4(El *p, const El (&a)[4])
     }
 }
 
-// Length-256 transforms, one wavefront per polynomial, no block barriers.
+// Lengths n = 256 G (G = 1, 2, 4): one wavefront per polynomial, no
+// workgroup barriers.
 //
-// Positions P (0..255) of the bit-reversed array split into four 2-bit fields
-// F0..F3 (F_s = bits 2s, 2s+1); radix-4 step s runs stages 2s and 2s+1 on the
-// groups of four positions that differ only in F_s.  A lane owns one group per
-// step, in registers:
-//   step 0  lane = brev6(F1 + 4 F2 + 16 F3); coefficient x[lane + 64 brev2(k)]
-//           is slot k (F0 = k) of the bit-reversed array, so each of the four
-//           HBM loads reads 64 consecutive words
+// In a decimation-in-time transform of the bit-reversed array, the first
+// eight stages act on the G blocks of 256 consecutive positions separately:
+// they are G transforms of length 256 with the root w^G (twiddle w^(G i) =
+// tw[G i]).  Block b holds the coefficients x[brev(b) + G m], m = 0..255
+// (brev over log2 G bits), so the G values a lane needs for one slot of all
+// blocks are G consecutive words of the polynomial.  After those stages the
+// remaining log2 G stages pair positions that differ only in the block index,
+// and a lane already holds every member of its groups: they run in registers.
+//
+// Within a block, positions P (0..255) split into four 2-bit fields F0..F3
+// (F_s = bits 2s, 2s+1); radix-4 step s runs stages 2s and 2s+1 on the groups
+// of four positions that differ only in F_s.  A lane owns one group per step:
+//   step 0  lane = brev6(F1 + 4 F2 + 16 F3); slot k (F0 = k) is coefficient
+//           m = lane + 64 brev2(k), so each load reads 64 consecutive
+//           G-word chunks
 //   step 1  lane = F0 + 4 F3 + 16 F2       (slot F1)
 //   step 2  lane = F0 + 4 F1 + 16 F3       (slot F2)
-//   step 3  lane = F0 + 4 F1 + 16 F2       (slot F3): outputs x[lane + 64 k],
-//           again 64 consecutive words per store
+//   step 3  lane = F0 + 4 F1 + 16 F2       (slot F3): position lane + 64 k,
+//           written to x[256 b + lane + 64 k] after the block stages (64
+//           consecutive words per store)
 // Between steps each lane writes its four slots to 16 consecutive bytes of the
-// wave's LDS buffer at 16 lane (conflict-free: 16 lanes fill the 64 four-byte
+// block's LDS buffer at 16 lane (conflict-free: 16 lanes fill the 64 four-byte
 // banks) and reads the next group at base_s + 64 k (immediate offsets), where
 // the bases of the 64 lanes are 64 distinct banks:
 //   base_1 = F0 + 4 brev2(F3) + 16 brev2(F2)   (slot k at base_1 + 64 brev2(k))
 //   base_2 = F1 + 4 F0 + 16 F3
 //   base_3 = F2 + 4 F0 + 16 F1
-// The twiddles of a lane are the same for every polynomial and stay in
-// registers; waves loop over polynomials (the next one's loads in flight).
-template <int W, int V, bool FAST, bool LAZY>
+// Stage 0 and half of stage 1 multiply by 1 and skip the product.  A lane's
+// twiddles are the same for every polynomial and stay in registers; waves
+// loop over polynomials (the next one's loads in flight).
+template <int W, int V, bool FAST, bool LAZY, int G>
 __global__ void __launch_bounds__(BLOCK)
-    k_ntt256(KCtx c, void *__restrict__ data, uint64_t batch, const TwL<W, V> *__restrict__ tw, KConst scale,
-             uint32_t do_scale)
+    k_nttw(KCtx c, void *__restrict__ data, uint64_t batch, const TwL<W, V> *__restrict__ tw, KConst scale,
+           uint32_t do_scale, uint32_t vec)
 {
     using R = Red<W, V>;
     using El = typename R::E;
     using T = TwL<W, V>;
     constexpr int WAVES = BLOCK / 64;
-    __shared__ __align__(16) El lds[WAVES][256];
+    constexpr uint32_t n = 256u * G;
+    __shared__ __align__(16) El lds[WAVES][G][256];
     const R red(c);
     const El N = (El)c.N;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    El *s = lds[wv];
     auto br2 = [](uint32_t f) { return ((f & 1u) << 1) | (f >> 1); };
     const uint32_t f0 = lane & 3u, f1 = (lane >> 2) & 3u, f2 = lane >> 4;
     const uint32_t base1 = f0 + 4 * br2(f1) + 16 * br2(f2);  // step-1 lane: F0 = f0, F3 = f1, F2 = f2
     const uint32_t base2 = f1 + 4 * f0 + 16 * f2;            // step-2 lane: F0 = f0, F1 = f1, F3 = f2
     const uint32_t base3 = f2 + 4 * f0 + 16 * f1;            // step-3 lane: F0 = f0, F1 = f1, F2 = f2
     const uint32_t j2 = f0 + 4 * f1;
-    // stage st pairs at distance 2^st use twiddle w^(j 2^(7 - st)) = tw[j << (7 - st)]
-    const T t01 = tw[64];
-    const T t10 = tw[f0 << 5], t11 = tw[f0 << 4], t12 = tw[(f0 + 4) << 4];
-    const T t20 = tw[j2 << 3], t21 = tw[j2 << 2], t22 = tw[(j2 + 16) << 2];
-    const T t30 = tw[lane << 1], t31 = tw[lane], t32 = tw[lane + 64];
+    // block stage st pairs at distance 2^st use w^(G j 2^(7 - st)) = tw[G (j << (7 - st))]
+    const T t01 = tw[G * 64];
+    const T t10 = tw[G * (f0 << 5)], t11 = tw[G * (f0 << 4)], t12 = tw[G * ((f0 + 4) << 4)];
+    const T t20 = tw[G * (j2 << 3)], t21 = tw[G * (j2 << 2)], t22 = tw[G * ((j2 + 16) << 2)];
+    const T t30 = tw[G * (lane << 1)], t31 = tw[G * lane], t32 = tw[G * (lane + 64)];
+    // stages across blocks, at position j = lane + 64 k of the block: stage 8 uses
+    // w^(j n / 512) = tw[j (G / 2)], stage 9 (G = 4) tw[j] and tw[j + 256]
+    T u0[4], u1[4], u2[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t j = lane + 64u * (uint32_t)k;
+        if constexpr (G == 2) {
+            u0[k] = tw[j];
+        } else if constexpr (G == 4) {
+            u0[k] = tw[2 * j];
+            u1[k] = tw[j];
+            u2[k] = tw[j + 256];
+        }
+    }
     auto outv = [&](El y) -> El {
         if constexpr (LAZY)
             return do_scale ? below<El>(lazy_mul(red, y, (El)scale.b), N) : below<El>(below<El>(y, (El)(2 * N)), N);
@@ -342,60 +368,113 @@ __global__ void __launch_bounds__(BLOCK)
     };
     const uint64_t stride = (uint64_t)gridDim.x * WAVES;
     uint64_t t = (uint64_t)blockIdx.x * WAVES + wv;
-    El nx[4];
+    El nx[G][4];
+    // block b, slot k: x[brev(b) + G (lane + 64 brev2(k))]; chunk element e is block brev(e)
     auto fetch = [&](uint64_t p) {
-        const El *x = (const El *)data + (p << 8) + lane;
-        nx[0] = x[0];
-        nx[1] = x[128];
-        nx[2] = x[64];
-        nx[3] = x[192];
+        const El *x = (const El *)data + p * n + (uint64_t)G * lane;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const El *q = x + 64 * G * br2((uint32_t)k);
+            El v[G];
+            if constexpr (G == 1) {
+                v[0] = q[0];
+            } else if (vec) {
+                load_chunk<El, G, false>(q, v);
+            } else {
+#pragma unroll
+                for (int e = 0; e < G; ++e)
+                    v[e] = q[e];
+            }
+#pragma unroll
+            for (int e = 0; e < G; ++e)
+                nx[G == 4 ? (int)br2((uint32_t)e) : e][k] = v[e];
+        }
     };
     if (t < batch)
         fetch(t);
     for (; t < batch; t += stride) {
-        El a[4] = {nx[0], nx[1], nx[2], nx[3]};
+        El a[G][4];
+#pragma unroll
+        for (int b = 0; b < G; ++b)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                a[b][k] = nx[b][k];
         if (t + stride < batch)
             fetch(t + stride);
-        // step 0: stage 0 (unit twiddles), stage 1 (1 and w^64)
-        butterfly1<El, FAST, LAZY>(a[0], a[1], N);
-        butterfly1<El, FAST, LAZY>(a[2], a[3], N);
-        butterfly1<El, FAST, LAZY>(a[0], a[2], N);
-        butterfly<R, V, FAST, LAZY>(red, a[1], a[3], t01, N);
-        lds_put4<El>(s + 4 * lane, a);
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        a[0] = s[base1];
-        a[1] = s[base1 + 128];
-        a[2] = s[base1 + 64];
-        a[3] = s[base1 + 192];
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        butterfly<R, V, FAST, LAZY>(red, a[0], a[1], t10, N);
-        butterfly<R, V, FAST, LAZY>(red, a[2], a[3], t10, N);
-        butterfly<R, V, FAST, LAZY>(red, a[0], a[2], t11, N);
-        butterfly<R, V, FAST, LAZY>(red, a[1], a[3], t12, N);
-        lds_put4<El>(s + 4 * lane, a);
+        // step 0: stage 0 (unit twiddles), stage 1 (1 and w^64 of the block root)
+#pragma unroll
+        for (int b = 0; b < G; ++b) {
+            butterfly1<El, FAST, LAZY>(a[b][0], a[b][1], N);
+            butterfly1<El, FAST, LAZY>(a[b][2], a[b][3], N);
+            butterfly1<El, FAST, LAZY>(a[b][0], a[b][2], N);
+            butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t01, N);
+            lds_put4<El>(&lds[wv][b][4 * lane], a[b]);
+        }
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            a[k] = s[base2 + 64 * k];
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        butterfly<R, V, FAST, LAZY>(red, a[0], a[1], t20, N);
-        butterfly<R, V, FAST, LAZY>(red, a[2], a[3], t20, N);
-        butterfly<R, V, FAST, LAZY>(red, a[0], a[2], t21, N);
-        butterfly<R, V, FAST, LAZY>(red, a[1], a[3], t22, N);
-        lds_put4<El>(s + 4 * lane, a);
+        for (int b = 0; b < G; ++b) {
+            const El *s = lds[wv][b];
+            a[b][0] = s[base1];
+            a[b][1] = s[base1 + 128];
+            a[b][2] = s[base1 + 64];
+            a[b][3] = s[base1 + 192];
+        }
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            a[k] = s[base3 + 64 * k];
+        for (int b = 0; b < G; ++b) {
+            butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][1], t10, N);
+            butterfly<R, V, FAST, LAZY>(red, a[b][2], a[b][3], t10, N);
+            butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][2], t11, N);
+            butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t12, N);
+            lds_put4<El>(&lds[wv][b][4 * lane], a[b]);
+        }
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        butterfly<R, V, FAST, LAZY>(red, a[0], a[1], t30, N);
-        butterfly<R, V, FAST, LAZY>(red, a[2], a[3], t30, N);
-        butterfly<R, V, FAST, LAZY>(red, a[0], a[2], t31, N);
-        butterfly<R, V, FAST, LAZY>(red, a[1], a[3], t32, N);
-        El *y = (El *)data + (t << 8) + lane;
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            y[64 * k] = outv(a[k]);
+        for (int b = 0; b < G; ++b)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                a[b][k] = lds[wv][b][base2 + 64 * k];
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+        for (int b = 0; b < G; ++b) {
+            butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][1], t20, N);
+            butterfly<R, V, FAST, LAZY>(red, a[b][2], a[b][3], t20, N);
+            butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][2], t21, N);
+            butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t22, N);
+            lds_put4<El>(&lds[wv][b][4 * lane], a[b]);
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+        for (int b = 0; b < G; ++b)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                a[b][k] = lds[wv][b][base3 + 64 * k];
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+        for (int b = 0; b < G; ++b) {
+            butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][1], t30, N);
+            butterfly<R, V, FAST, LAZY>(red, a[b][2], a[b][3], t30, N);
+            butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][2], t31, N);
+            butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t32, N);
+        }
+        // the stages across blocks: position lane + 64 k of every block, in registers
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if constexpr (G == 2) {
+                butterfly<R, V, FAST, LAZY>(red, a[0][k], a[1][k], u0[k], N);
+            } else if constexpr (G == 4) {
+                butterfly<R, V, FAST, LAZY>(red, a[0][k], a[1][k], u0[k], N);
+                butterfly<R, V, FAST, LAZY>(red, a[2][k], a[3][k], u0[k], N);
+                butterfly<R, V, FAST, LAZY>(red, a[0][k], a[2][k], u1[k], N);
+                butterfly<R, V, FAST, LAZY>(red, a[1][k], a[3][k], u2[k], N);
+            }
+        }
+        El *y = (El *)data + t * n + lane;
+#pragma unroll
+        for (int b = 0; b < G; ++b)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                y[256 * b + 64 * k] = outv(a[b][k]);
     }
 }
 
@@ -527,22 +606,38 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
     const dim3 grid((unsigned)batch), blk(block);
     const auto *twc = (const TwL<W, CLASSIC> *)t.dev;
     const auto *twp = (const TwL<W, PLANTARD> *)t.dev;
-    if (log2n == 8) {
+    if (log2n >= 8 && log2n <= 10) {
         // one wavefront per polynomial, waves looping over the batch
         constexpr uint64_t WAVES = BLOCK / 64;
-        const uint64_t blocks = std::min<uint64_t>((batch + WAVES - 1) / WAVES, (uint64_t)device_cus() * NTT256_BPC);
+        const uint64_t blocks = std::min<uint64_t>((batch + WAVES - 1) / WAVES, (uint64_t)device_cus() * NTTW_BPC);
         const dim3 g((unsigned)blocks), b(BLOCK);
         const uint64_t nb = batch;
-        if (lazy)
-            hipLaunchKernelGGL((k_ntt256<W, CLASSIC, true, true>), g, b, 0, s, k, data, nb, twc, t.scale, inv);
-        else if (variant == CLASSIC && fast)
-            hipLaunchKernelGGL((k_ntt256<W, CLASSIC, true, false>), g, b, 0, s, k, data, nb, twc, t.scale, inv);
-        else if (variant == CLASSIC)
-            hipLaunchKernelGGL((k_ntt256<W, CLASSIC, false, false>), g, b, 0, s, k, data, nb, twc, t.scale, inv);
-        else if (fast)
-            hipLaunchKernelGGL((k_ntt256<W, PLANTARD, true, false>), g, b, 0, s, k, data, nb, twp, t.scale, inv);
+        // chunk loads (n / 256 words per lane and slot) when the polynomials are aligned to them
+        const size_t chunk = std::min<size_t>(16, ((size_t)n / 256) * sizeof(El));
+        const uint32_t cv = (uintptr_t)data % chunk == 0 ? 1u : 0u;
+        auto go = [&](auto gc) {
+            constexpr int GG = decltype(gc)::value;
+            if (lazy)
+                hipLaunchKernelGGL((k_nttw<W, CLASSIC, true, true, GG>), g, b, 0, s, k, data, nb, twc, t.scale, inv, cv);
+            else if (variant == CLASSIC && fast)
+                hipLaunchKernelGGL((k_nttw<W, CLASSIC, true, false, GG>), g, b, 0, s, k, data, nb, twc, t.scale, inv,
+                                   cv);
+            else if (variant == CLASSIC)
+                hipLaunchKernelGGL((k_nttw<W, CLASSIC, false, false, GG>), g, b, 0, s, k, data, nb, twc, t.scale, inv,
+                                   cv);
+            else if (fast)
+                hipLaunchKernelGGL((k_nttw<W, PLANTARD, true, false, GG>), g, b, 0, s, k, data, nb, twp, t.scale, inv,
+                                   cv);
+            else
+                hipLaunchKernelGGL((k_nttw<W, PLANTARD, false, false, GG>), g, b, 0, s, k, data, nb, twp, t.scale,
+                                   inv, cv);
+        };
+        if (log2n == 8)
+            go(std::integral_constant<int, 1>{});
+        else if (log2n == 9)
+            go(std::integral_constant<int, 2>{});
         else
-            hipLaunchKernelGGL((k_ntt256<W, PLANTARD, false, false>), g, b, 0, s, k, data, nb, twp, t.scale, inv);
+            go(std::integral_constant<int, 4>{});
         return hipGetLastError();
     }
     if (lazy) {
