@@ -290,6 +290,22 @@ struct Red<32, CLASSIC> {
         return t >= N ? (uint32_t)(t - N) : (uint32_t)t;
     }
     __device__ __forceinline__ E mul(E a, E b) const { return redc((uint64_t)a * b); }
+    // Products of values in (-N, N) held as two's-complement words, N < 2^31:
+    // with m = T N' mod 2^32 read as a signed word, T + m N is divisible by
+    // 2^32 and |T + m N| < N^2 + 2^31 N < 2^32 N, so the quotient lies in
+    // (-N, N) again and needs no correction (Algorithm 1's signed reduction,
+    // with -N^{-1} in place of N^{-1}): three instructions per product.
+    __device__ __forceinline__ E mul_signed(E a, E b) const
+    {
+        // Empty statements that hide the origins of T and m from the compiler:
+        // without them it widens m's 32-bit multiply to a 64-bit one or forms
+        // T's low word with an extra multiply (one to three more instructions).
+        int64_t T = (int64_t)(int32_t)a * (int64_t)(int32_t)b;
+        asm("" : "+v"(T));
+        uint32_t m = (uint32_t)T * np;
+        asm("" : "+v"(m));
+        return (E)(uint32_t)(((int64_t)(int32_t)m * (int64_t)(int32_t)N + T) >> 32);
+    }
     __device__ __forceinline__ E sqr(E a) const { return mul(a, a); }
     // Products for N < 2^31 and inputs below N: T + mN < 2^32 N + N^2 < 2^64,
     // so one multiply-add forms the whole sum, its high word t = (T + mN)/R is
@@ -302,7 +318,6 @@ struct Red<32, CLASSIC> {
         const uint32_t t = (uint32_t)(((uint64_t)m * N + T) >> 32);
         return min(t, t - N);
     }
-    __device__ __forceinline__ E sqr_fast(E a) const { return mul_fast(a, a); }
     // (T + mN)/R without the final subtraction, for N < 2^30 and a b < 4N^2
     // (say a < 4N and b < N, or both below 2N): T + mN < 4N^2 + 2^32 N < 2^63
     // and the result is below 4N^2/R + N <= 2N.
@@ -312,7 +327,6 @@ struct Red<32, CLASSIC> {
         const uint32_t m = (uint32_t)T * np;
         return (uint32_t)(((uint64_t)m * N + T) >> 32);
     }
-    __device__ __forceinline__ E sqr_lazy(E a) const { return mul_lazy(a, a); }
     __device__ __forceinline__ E mul_const(E a, const KConst &k) const
     {
         const uint64_t T = (uint64_t)a * (uint32_t)k.b;

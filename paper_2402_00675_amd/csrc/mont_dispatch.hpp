@@ -106,7 +106,7 @@ hipError_t launch_pow(const KCtx &c, const void *x, const uint64_t *e, void *out
     const int U = (unroll == 2 || unroll == 4) ? unroll : 1;
     dim3 grid((unsigned)grid_x(n, U, 1, L));
     // ladder mode by modulus (see ladder_mode): lazy products for w = 64, N < 2^62;
-    // 32-bit registers for w = 32, N < 2^31; lazy 32-bit products for N < 2^30
+    // signed three-instruction products for w = 32, N < 2^31
     const int mode = ladder_mode<W>(c.N);
     auto go = [&](auto mode_c) {
         constexpr int M = decltype(mode_c)::value;
@@ -118,10 +118,8 @@ hipError_t launch_pow(const KCtx &c, const void *x, const uint64_t *e, void *out
             hipLaunchKernelGGL((k_pow<W, 1, M>), grid, dim3(BLOCK), 0, s, c, x, e, out, n);
     };
     if constexpr (W == 32) {
-        if (mode == 2)
-            go(std::integral_constant<int, 2>{});
-        else if (mode == 1)
-            go(std::integral_constant<int, 1>{});
+        if (mode == 3)
+            go(std::integral_constant<int, 3>{});
         else
             go(std::integral_constant<int, 0>{});
     } else if constexpr (W == 64) {

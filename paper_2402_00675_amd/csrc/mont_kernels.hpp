@@ -213,13 +213,12 @@ struct WideT<64> {
 };
 
 
-// Ladder products by mode.  0: the general classic product.  1 (FAST, the
-// classic forms that need a smaller modulus): for w = 64 and N < 2^62 the
-// final subtraction is dropped ("lazy": for 4N <= R and inputs below 2N,
-// (T + mN)/R < 4N^2/R + N <= 2N, so every result stays below 2N and is a valid
-// input again); for w = 32 and N < 2^31 the whole reduction runs in 32-bit
-// registers with fully reduced results.  2 (w = 32 and N < 2^30): lazy as
-// well, three instructions per product (no subtraction, no minimum).
+// Ladder products by mode.  0: the general classic product.  1 (w = 64,
+// N < 2^62): the final subtraction is dropped ("lazy": for 4N <= R and inputs
+// below 2N, (T + mN)/R < 4N^2/R + N <= 2N, so every result stays below 2N and
+// is a valid input again).  3 (w = 32, N < 2^31): signed products, values in
+// (-N, N) as two's-complement words, three instructions per product and no
+// correction (Red<32, CLASSIC>::mul_signed).
 template <int W>
 __host__ __device__ __forceinline__ bool fast_ladder(uint64_t N)
 {
@@ -229,15 +228,15 @@ __host__ __device__ __forceinline__ bool fast_ladder(uint64_t N)
 template <int W>
 __host__ __device__ __forceinline__ int ladder_mode(uint64_t N)
 {
-    return (W == 32 && N < (1ull << 30)) ? 2 : fast_ladder<W>(N) ? 1 : 0;
+    return !fast_ladder<W>(N) ? 0 : W == 32 ? 3 : 1;
 }
 
 template <class R, int MODE>
 struct Ladder {
     __device__ __forceinline__ static typename R::E mul(const R &r, typename R::E a, typename R::E b)
     {
-        if constexpr (MODE == 2)
-            return r.mul_lazy(a, b);
+        if constexpr (MODE == 3)
+            return r.mul_signed(a, b);
         else if constexpr (MODE == 1)
             return r.mul_fast(a, b);
         else
@@ -245,12 +244,20 @@ struct Ladder {
     }
     __device__ __forceinline__ static typename R::E sqr(const R &r, typename R::E a)
     {
-        if constexpr (MODE == 2)
-            return r.sqr_lazy(a);
+        if constexpr (MODE == 3)
+            return r.mul_signed(a, a);
         else if constexpr (MODE == 1)
             return r.sqr_fast(a);
         else
             return r.sqr(a);
+    }
+    // Montgomery form (in the mode's range) to the residue in [0, N)
+    __device__ __forceinline__ static typename R::E out(const R &r, typename R::E y)
+    {
+        using El = typename R::E;
+        if constexpr (MODE == 3)
+            y = (int32_t)y < 0 ? (El)(y + r.N) : y;
+        return r.redc(WideT<8 * (int)sizeof(El)>::of(y));
     }
 };
 
@@ -258,8 +265,8 @@ struct Ladder {
 // chains per wave): Montgomery form x R = REDC(x * (R^2 mod N)), a
 // left-to-right 2-bit fixed-window ladder of Montgomery products (every lane
 // runs the same 32 windows: no divergence); the caller converts back with one
-// REDC.  The returned Montgomery-form values are below 2N (modes 1 at w = 64
-// and 2) or below N.  Element u's four window entries (1, x, x^2, x^3 in Montgomery
+// REDC (Ladder::out).  The returned Montgomery-form values are below 2N
+// (mode 1), in (-N, N) (mode 3) or below N.  Element u's four window entries (1, x, x^2, x^3 in Montgomery
 // form) live in LDS at tab[u * BLOCK + j * stride], j = 0..3: one LDS read per
 // window instead of a 4-way register select.  Lanes of a wave use adjacent
 // words of each entry row, so the reads are free of bank conflicts.
@@ -329,7 +336,7 @@ __global__ void __launch_bounds__(BLOCK)
         for (int u = 0; u < U; ++u) {
             const uint64_t i = base + (uint64_t)u * BLOCK;
             if (i < n)
-                po[i] = red.redc(WideT<W>::of(y[u]));
+                po[i] = Ladder<R, MODE>::out(red, y[u]);
         }
     }
 }

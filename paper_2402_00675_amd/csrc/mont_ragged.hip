@@ -127,13 +127,16 @@ __device__ __forceinline__ void tile_pow(const KCtx &c, const DPools &P, uint64_
         const El x[1] = {px[g]};
         const uint64_t k[1] = {pe[g]};
         El y[1];
-        if (W == 32 && mode == 2)
-            pow_lanes<R, W == 32 ? 2 : 0, 1>(red, x, k, r2, one, mine, BLOCK, y);
-        else if (mode)
-            pow_lanes<R, W != 16 ? 1 : 0, 1>(red, x, k, r2, one, mine, BLOCK, y);
-        else
+        if (W == 32 && mode == 3) {
+            pow_lanes<R, W == 32 ? 3 : 0, 1>(red, x, k, r2, one, mine, BLOCK, y);
+            po[g] = Ladder<R, W == 32 ? 3 : 0>::out(red, y[0]);
+        } else if (W == 64 && mode == 1) {
+            pow_lanes<R, W == 64 ? 1 : 0, 1>(red, x, k, r2, one, mine, BLOCK, y);
+            po[g] = Ladder<R, W == 64 ? 1 : 0>::out(red, y[0]);
+        } else {
             pow_lanes<R, 0, 1>(red, x, k, r2, one, mine, BLOCK, y);
-        po[g] = red.redc(WideT<W>::of(y[0]));
+            po[g] = Ladder<R, 0>::out(red, y[0]);
+        }
     }
 }
 

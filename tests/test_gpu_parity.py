@@ -312,7 +312,8 @@ def test_range_top_of_classic_w32():
 def test_pow_parity(w):
     dt = NP_E[w][0]
     g = inp.rng(96, w)
-    # both sides of the smaller-modulus ladder forms: N < 2^30 and N < 2^31 (w = 32), N < 2^62 (w = 64)
+    # both sides of the smaller-modulus ladder forms: signed products for N < 2^31 (w = 32), lazy ones
+    # for N < 2^62 (w = 64)
     Ns = {16: [3, 3329, 65521, 65535],
           32: [3, 8380417, (1 << 30) - 35, (1 << 30) + 3, (1 << 31) - 1, (1 << 31) + 1, 4294967291],
           64: [3, (1 << 61) - 1, (1 << 62) - 57, (1 << 62) - 1, (1 << 62) + 1, (1 << 64) - 59]}[w]
