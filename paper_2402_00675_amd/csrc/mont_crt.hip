@@ -8,16 +8,18 @@
 //     v_0 = x_0,  v_i = ((x_i - v_0) c_{0,i} - v_1) c_{1,i} ... - v_{i-1}) c_{i-1,i}  mod N_i,
 //     c_{j,i} = N_j^{-1} mod N_i,
 //     X = v_0 + N_0 (v_1 + N_1 (v_2 + ... + N_{k-2} v_{k-1})),
-// where every modular product is a Montgomery product against the constant
-// c_{j,i} R mod N_i: REDC(t (c R)) = t c (mod N_i).  A v_j that is not yet
-// reduced modulo N_i is multiplied the same way (v_j (cR) < R N_i is inside
-// REDC's range), so (t - v_j) c = REDC(t cR) - REDC(v_j cR) needs no separate
-// reduction; when every modulus is below twice every other one, a single
-// conditional subtraction reduces v_j instead (one product per step).
-// The mixed-radix digits are then folded into k little-endian 64-bit words by
-// Horner's rule with 64x64->128 multiply-adds.  Constants are kernel
-// arguments (read with scalar loads); residues are limb-major [k][ld], the
-// result element-major [n][k] words.
+// where each modular product is a product by a constant.  In general it is a
+// Montgomery product against c_{j,i} R mod N_i: REDC(t (c R)) = t c (mod N_i).
+// A v_j that is not yet reduced modulo N_i is multiplied the same way
+// (v_j (cR) < R N_i is inside REDC's range), so (t - v_j) c =
+// REDC(t cR) - REDC(v_j cR) needs no separate reduction; when every modulus is
+// below twice every other one, a single conditional subtraction reduces v_j
+// instead (one product per step).  When moreover every modulus is below 2^62
+// the steps take Shoup's fixed-operand product on unreduced values (see
+// FORM 2 below).  The mixed-radix digits are then folded into k little-endian
+// 64-bit words by Horner's rule with 64x64->128 multiply-adds.  Constants are
+// kernel arguments (read with scalar loads); residues are limb-major [k][ld],
+// the result element-major [n][k] words, written through LDS.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,11 +33,27 @@ namespace mont {
 
 constexpr int CRT_MAX = 16;
 
+constexpr int CRT_PAIRS = CRT_MAX * (CRT_MAX - 1) / 2;
+
+// The constant of step (j, i), j < i, sits at pair index i (i - 1)/2 + j.
 struct CrtTab {
     uint64_t N[CRT_MAX];
     uint64_t np[CRT_MAX];
-    uint64_t cbar[CRT_MAX][CRT_MAX];  // [j][i] = (N_j^{-1} mod N_i) R mod N_i, j < i
+    uint64_t c[CRT_PAIRS];   // forms 0, 1: (N_j^{-1} mod N_i) R mod N_i;  form 2: N_j^{-1} mod N_i
+    uint64_t cq[CRT_PAIRS];  // form 2: floor(c 2^64 / N_i)
 };
+
+__host__ __device__ constexpr int crt_pair(int j, int i) { return i * (i - 1) / 2 + j; }
+
+// Shoup's product by a fixed c < N with the precomputed quotient factor
+// cq = floor(c 2^64 / N): for any 64-bit d, q = floor(d cq / 2^64) is at
+// least floor(d c / N) - 1 and at most d c / N, so d c - q N (computed modulo
+// 2^64) is d c mod N or that plus N: a value below 2N, whatever d is.
+__device__ __forceinline__ uint64_t shoup_mul(uint64_t d, uint64_t c, uint64_t cq, uint64_t N)
+{
+    const uint64_t q = mulhi_64(d, cq);
+    return d * c - q * N;
+}
 
 // a N + c for N < 2^62 (n1 < 2^30) and any 64-bit a, c; the sum is below
 // 2^127.  Partial sums: a0 n0 + lo(c) < 2^64, t1 = a0 n1 + hi(p00) < 2^62 +
@@ -52,17 +70,25 @@ __device__ __forceinline__ u128v mul_add_62(uint64_t a, uint64_t N, uint64_t c)
     return {(mid << 32) | (uint32_t)p00, hi};
 }
 
-// FORM 0: any coprime odd moduli.  FORM 1 (NARROW): every modulus below twice
-// every other one.  FORM 2: NARROW and every modulus below 2^62, which admits
-// the lazy Montgomery product (result below 2N, one conditional subtraction
-// per digit) and carry-free Horner steps.
+// FORM 0: any coprime odd moduli (Montgomery products, two per step).
+// FORM 1 (NARROW): every modulus below twice every other one, so v_j needs one
+// conditional subtraction and each step is one Montgomery product.  FORM 2:
+// NARROW and every modulus below 2^62: Shoup steps on unreduced values,
+// t <- shoup(t + 2N_i - v_j) with t < 2N_i and v_j < N_j < 2N_i, so the
+// operand stays below 4N_i < 2^64 and each step is one fixed-operand product
+// with no reduction before or after it (the digit is reduced once at the
+// end), and carry-free Horner steps.
 template <int K, int FORM>
 __global__ void __launch_bounds__(BLOCK)
     k_crt(CrtTab tab, const uint64_t *__restrict__ res, uint64_t ld, uint64_t n, uint64_t *__restrict__ out)
 {
-    const uint64_t e = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
-    if (e >= n)
-        return;
+    const uint64_t base = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * BLOCK;  // the block's first element
+    const uint64_t e = base + threadIdx.x;
+    const bool live = e < n;  // the lanes past n still take part in the block's output pass
+    uint64_t x[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        x[i] = live ? __builtin_nontemporal_load(res + (uint64_t)i * ld + e) : 0;
     uint64_t v[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
@@ -70,15 +96,12 @@ __global__ void __launch_bounds__(BLOCK)
         c.N = tab.N[i];
         c.nprime = tab.np[i];
         const Red<64, CLASSIC> red(c);
-        uint64_t t = __builtin_nontemporal_load(res + (uint64_t)i * ld + e);
+        uint64_t t = x[i];
 #pragma unroll
         for (int j = 0; j < i; ++j) {
-            const uint64_t cb = tab.cbar[j][i];
+            const uint64_t cb = tab.c[crt_pair(j, i)];
             if constexpr (FORM == 2) {
-                const uint64_t vj = v[j] >= c.N ? v[j] - c.N : v[j];
-                const uint64_t d = t >= vj ? t - vj : t + (c.N - vj);
-                const uint64_t u = red.mul_fast(d, cb);   // d, cb < N < 2^62: u < 2N
-                t = u >= c.N ? u - c.N : u;
+                t = shoup_mul(t + 2 * c.N - v[j], cb, tab.cq[crt_pair(j, i)], c.N);
             } else if constexpr (FORM == 1) {
                 const uint64_t vj = v[j] >= c.N ? v[j] - c.N : v[j];
                 const uint64_t d = t >= vj ? t - vj : t + (c.N - vj);
@@ -89,6 +112,8 @@ __global__ void __launch_bounds__(BLOCK)
                 t = a >= b ? a - b : a + (c.N - b);
             }
         }
+        if constexpr (FORM == 2)
+            t = t >= c.N ? t - c.N : t;
         v[i] = t;
     }
     uint64_t acc[K];
@@ -116,21 +141,35 @@ __global__ void __launch_bounds__(BLOCK)
         }
         acc[K - 1 - i] = carry;
     }
-    uint64_t *o = out + e * K;
-    if constexpr (K % 2 == 0) {
+    // The block's results leave through LDS: element-major output written
+    // straight from the lanes would put 16-byte stores 8k bytes apart, every
+    // wave writing parts of many cache lines at once (the access pattern
+    // alone, without arithmetic, runs at a quarter of the rate of the same
+    // bytes written as below).  Here consecutive lanes write consecutive
+    // 16-byte chunks of the block's contiguous output.  Rows of K + 1 words
+    // spread each lane's LDS writes over the banks.
+    constexpr uint32_t SR = K + 1;
+    __shared__ uint64_t st[BLOCK * SR];
 #pragma unroll
-        for (int w = 0; w < K; w += 2) {
-            u32x4 q;
-            q.x = (uint32_t)acc[w];
-            q.y = (uint32_t)(acc[w] >> 32);
-            q.z = (uint32_t)acc[w + 1];
-            q.w = (uint32_t)(acc[w + 1] >> 32);
-            __builtin_nontemporal_store(q, (u32x4 *)(o + w));
+    for (int w = 0; w < K; ++w)
+        st[threadIdx.x * SR + w] = acc[w];
+    __syncthreads();
+    const uint32_t words = (uint32_t)(min((uint64_t)BLOCK, n - base) * K);
+    uint64_t *ob = out + base * K;  // 16-byte aligned: out is, and base is a multiple of BLOCK
+    for (uint32_t q = threadIdx.x; 2 * q < words; q += BLOCK) {
+        const uint32_t w0 = 2 * q, w1 = w0 + 1;
+        const uint64_t a0 = st[(w0 / K) * SR + w0 % K];
+        if (w1 < words) {
+            const uint64_t a1 = st[(w1 / K) * SR + w1 % K];
+            u32x4 v;
+            v.x = (uint32_t)a0;
+            v.y = (uint32_t)(a0 >> 32);
+            v.z = (uint32_t)a1;
+            v.w = (uint32_t)(a1 >> 32);
+            __builtin_nontemporal_store(v, (u32x4 *)(ob + w0));
+        } else {
+            ob[w0] = a0;
         }
-    } else {
-#pragma unroll
-        for (int w = 0; w < K; ++w)
-            o[w] = acc[w];
     }
 }
 
@@ -190,19 +229,28 @@ extern "C" mont_status_t mont_crt(const mont_ctx_t *ctxs, uint32_t k, const void
         t.np[i] = ctxs[i].nprime;
         lo = std::min(lo, ctxs[i].N);
         hi = std::max(hi, ctxs[i].N);
+    }
+    const bool narrow = (u128)hi < 2 * (u128)lo;  // every v_j < 2 N_i: one conditional subtraction reduces it
+    const int form = narrow ? (hi < (1ull << 62) ? 2 : 1) : 0;
+    for (uint32_t i = 1; i < k; ++i) {
+        const uint64_t Ni = ctxs[i].N;
         for (uint32_t j = 0; j < i; ++j) {
-            const uint64_t c = inv_mod(ctxs[j].N % ctxs[i].N, ctxs[i].N);
+            const uint64_t c = inv_mod(ctxs[j].N % Ni, Ni);
             if (!c)
                 return fail(MONT_E_DOMAIN, "moduli %u and %u are not coprime", j, i);
-            t.cbar[j][i] = (uint64_t)(((u128)c * ctxs[i].r_mod_n) % ctxs[i].N);  // c R mod N_i
+            const int p = crt_pair((int)j, (int)i);
+            if (form == 2) {
+                t.c[p] = c;
+                t.cq[p] = (uint64_t)(((u128)c << 64) / Ni);  // below 2^64: c < N_i
+            } else {
+                t.c[p] = (uint64_t)(((u128)c * ctxs[i].r_mod_n) % Ni);  // c R mod N_i
+            }
         }
     }
     if (n == 0)
         return MONT_OK;
     if (!res || !out || ((uintptr_t)out & 15u))
         return fail(MONT_E_INVAL, "null residues or output not 16-byte aligned");
-    const bool narrow = (u128)hi < 2 * (u128)lo;  // every v_j < 2 N_i: one conditional subtraction reduces it
-    const int form = narrow ? (hi < (1ull << 62) ? 2 : 1) : 0;
     if ((n + BLOCK - 1) / BLOCK > 0x7fffffffull)
         return fail(MONT_E_INVAL, "too many elements");
     hipStream_t s = (hipStream_t)stream;
