@@ -325,7 +325,7 @@ def stream_ref(a, b, out, stream=None):
 VALU_KINDS = ("v_mad_u64_u32", "v_mul_lo_u32", "v_mul_hi_u32", "v_mul_u32_u24", "v_add_u32",
               "v_lshl_add_u64", "v_cndmask_b32", "v_cmp_le_u64", "v_lshrrev_b64", "v_sub_u32", "v_min_u32",
               "v_mov_b32", "v_and_or_b32", "v_add3_u32", "v_add_co_u32", "v_addc_co_u32", "v_or_b32", "v_and_b32",
-              "v_lshlrev_b32", "v_alignbit_b32", "v_cmp_ne_u32")
+              "v_lshlrev_b32", "v_alignbit_b32", "v_cmp_ne_u32", "v_mad_i64_i32")
 
 
 def valu_ref(kind: int, iters: int, blocks: int, out, stream=None):

@@ -27,7 +27,8 @@ __global__ void __launch_bounds__(BLOCK) k_valu(uint32_t iters, uint32_t seed, u
     // compiler would otherwise fold repeated products algebraically).  Kinds 7
     // (compares writing the condition mask VCC, which nothing reads), 11
     // (moves), 14 (carry-out adds, VCC written and never read), 15 (carry
-    // chains, one scalar register pair per chain) and 20 (compares) put a round's eight
+    // chains, one scalar register pair per chain), 20 (compares) and 21 (signed
+    // multiply-adds, VCC written) put a round's eight
     // instructions in one statement: the compiler adds a wait state after
     // every separate statement of those forms.
     for (uint32_t i = 0; i < iters; ++i) {
@@ -95,6 +96,18 @@ __global__ void __launch_bounds__(BLOCK) k_valu(uint32_t iters, uint32_t seed, u
                                      : "v"(x[0]), "v"(x[1]), "v"(x[2]), "v"(x[3]), "v"(x[4]), "v"(x[5]), "v"(x[6]),
                                        "v"(x[7])
                                      : "vcc");
+                } else if constexpr (KIND == 21) {
+                    // signed y = x * m + y (the exponentiation ladder's product form), VCC written, never read
+                    if (c == 0)
+                        asm volatile("v_mad_i64_i32 %0, vcc, %8, %16, %0\n\tv_mad_i64_i32 %1, vcc, %9, %16, %1\n\t"
+                                     "v_mad_i64_i32 %2, vcc, %10, %16, %2\n\tv_mad_i64_i32 %3, vcc, %11, %16, %3\n\t"
+                                     "v_mad_i64_i32 %4, vcc, %12, %16, %4\n\tv_mad_i64_i32 %5, vcc, %13, %16, %5\n\t"
+                                     "v_mad_i64_i32 %6, vcc, %14, %16, %6\n\tv_mad_i64_i32 %7, vcc, %15, %16, %7"
+                                     : "+v"(y[0]), "+v"(y[1]), "+v"(y[2]), "+v"(y[3]), "+v"(y[4]), "+v"(y[5]),
+                                       "+v"(y[6]), "+v"(y[7])
+                                     : "v"(x[0]), "v"(x[1]), "v"(x[2]), "v"(x[3]), "v"(x[4]), "v"(x[5]), "v"(x[6]),
+                                       "v"(x[7]), "v"(m)
+                                     : "vcc");
                 } else if constexpr (KIND == 14) {
                     if (c == 0)
                         asm volatile("v_add_co_u32 %0, vcc, %0, %8\n\tv_add_co_u32 %1, vcc, %1, %8\n\t"
@@ -133,14 +146,15 @@ using namespace mont;
 
 extern "C" mont_status_t mont_valu_ref(uint32_t kind, uint32_t iters, uint32_t blocks, void *out, void *stream)
 {
-    if (kind > 20 || !out || !blocks || blocks > (1u << 20))
-        return fail(MONT_E_INVAL, "kind 0..20, 1 <= blocks <= 2^20, output of blocks * 256 uint64");
+    if (kind > 21 || !out || !blocks || blocks > (1u << 20))
+        return fail(MONT_E_INVAL, "kind 0..21, 1 <= blocks <= 2^20, output of blocks * 256 uint64");
     hipStream_t s = (hipStream_t)stream;
     uint64_t *o = (uint64_t *)out;
     typedef void (*kfn)(uint32_t, uint32_t, uint64_t *);
-    static const kfn kinds[21] = {k_valu<0>,  k_valu<1>,  k_valu<2>,  k_valu<3>,  k_valu<4>,  k_valu<5>,  k_valu<6>,
-                                  k_valu<7>,  k_valu<8>,  k_valu<9>,  k_valu<10>, k_valu<11>, k_valu<12>, k_valu<13>,
-                                  k_valu<14>, k_valu<15>, k_valu<16>, k_valu<17>, k_valu<18>, k_valu<19>, k_valu<20>};
+    static const kfn kinds[22] = {k_valu<0>,  k_valu<1>,  k_valu<2>,  k_valu<3>,  k_valu<4>,  k_valu<5>,
+                                  k_valu<6>,  k_valu<7>,  k_valu<8>,  k_valu<9>,  k_valu<10>, k_valu<11>,
+                                  k_valu<12>, k_valu<13>, k_valu<14>, k_valu<15>, k_valu<16>, k_valu<17>,
+                                  k_valu<18>, k_valu<19>, k_valu<20>, k_valu<21>};
     hipLaunchKernelGGL(kinds[kind], dim3(blocks), dim3(BLOCK), 0, s, iters, 12345u, o);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? MONT_OK : hip_fail(e, "mont_valu_ref launch");
