@@ -7,7 +7,7 @@
 // polynomials of n residues in [0, N) stored contiguously (natural order in
 // and out, in place).
 //
-// Lengths 256, 512, 1024 (k_nttw): one wavefront per polynomial, coefficients
+// Lengths 16 to 1024 (k_nttw): one wavefront per max(n, 256) coefficients,
 // loaded from HBM straight into registers in bit-reversed order and exchanged
 // between radix-4 steps through a conflict-free LDS layout.  Other lengths (k_ntt):
 // one workgroup transforms one polynomial: coefficients are loaded into LDS
@@ -287,29 +287,35 @@ __device__ __forceinline__ void lds_put4(El *p, const El (&a)[4])
     }
 }
 
-// Lengths n = 256 G (G = 1, 2, 4): one wavefront per polynomial, no
-// workgroup barriers.
+// Lengths n = 2^L, 4 <= L <= 10: one wavefront per unit of max(n, 256)
+// consecutive coefficients, no workgroup barriers.
 //
-// In a decimation-in-time transform of the bit-reversed array, the first
-// eight stages act on the G blocks of 256 consecutive positions separately:
-// they are G transforms of length 256 with the root w^G (twiddle w^(G i) =
-// tw[G i]).  Block b holds the coefficients x[brev(b) + G m], m = 0..255
-// (brev over log2 G bits), so the G values a lane needs for one slot of all
-// blocks are G consecutive words of the polynomial.  After those stages the
-// remaining log2 G stages pair positions that differ only in the block index,
-// and a lane already holds every member of its groups: they run in registers.
+// A unit is one polynomial when n >= 256 and 256/n polynomials side by side
+// when n < 256; below, "positions" are those of the unit's bit-reversed array
+// (each polynomial reversed within itself).  In a decimation-in-time transform
+// stage st pairs positions that differ in bit st, with the twiddle
+// w^(j n / 2^(st+1)) = tw[j << (L - 1 - st)] at position j mod 2^st.  Stages
+// L..7 do not exist when n < 256 and are skipped (the polynomials of a unit
+// never mix).  When n = 256 G, G = 2 or 4, the first eight stages act on G
+// separate blocks of 256 positions; block b holds the coefficients
+// x[brev(b) + G m], m = 0..255 (brev over log2 G bits), so the G values a
+// lane needs for one slot of all blocks are G consecutive words; after those
+// stages the remaining log2 G stages pair positions that differ only in the
+// block index, and a lane already holds every member of its groups: they run
+// in registers.
 //
-// Within a block, positions P (0..255) split into four 2-bit fields F0..F3
+// Within a block of 256, positions P split into four 2-bit fields F0..F3
 // (F_s = bits 2s, 2s+1); radix-4 step s runs stages 2s and 2s+1 on the groups
 // of four positions that differ only in F_s.  A lane owns one group per step:
-//   step 0  lane = brev6(F1 + 4 F2 + 16 F3); slot k (F0 = k) is coefficient
-//           m = lane + 64 brev2(k), so each load reads 64 consecutive
-//           G-word chunks
+//   step 0  lane = brev6(F1 + 4 F2 + 16 F3); slot k (F0 = k) is position
+//           4 brev6(lane) + k: coefficient lane + 64 brev2(k) when n >= 256
+//           (each load reads 64 consecutive words or G-word chunks), runs of
+//           16 or more consecutive words when n < 256
 //   step 1  lane = F0 + 4 F3 + 16 F2       (slot F1)
 //   step 2  lane = F0 + 4 F1 + 16 F3       (slot F2)
 //   step 3  lane = F0 + 4 F1 + 16 F2       (slot F3): position lane + 64 k,
-//           written to x[256 b + lane + 64 k] after the block stages (64
-//           consecutive words per store)
+//           written to x[256 b + lane + 64 k] of the unit after the last stage
+//           (64 consecutive words per store)
 // Between steps each lane writes its four slots to 16 consecutive bytes of the
 // block's LDS buffer at 16 lane (conflict-free: 16 lanes fill the 64 four-byte
 // banks) and reads the next group at base_s + 64 k (immediate offsets), where
@@ -318,18 +324,22 @@ __device__ __forceinline__ void lds_put4(El *p, const El (&a)[4])
 //   base_2 = F1 + 4 F0 + 16 F3
 //   base_3 = F2 + 4 F0 + 16 F1
 // Stage 0 and half of stage 1 multiply by 1 and skip the product.  A lane's
-// twiddles are the same for every polynomial and stay in registers; waves
-// loop over polynomials (the next one's loads in flight).
-template <int W, int V, bool FAST, bool LAZY, int G>
+// twiddles are the same for every unit and stay in registers; waves loop over
+// units (the next one's loads in flight).  `nelem` (the batch's coefficient
+// count) bounds the last unit when n < 256.
+template <int W, int V, bool FAST, bool LAZY, int L>
 __global__ void __launch_bounds__(BLOCK)
-    k_nttw(KCtx c, void *__restrict__ data, uint64_t batch, const TwL<W, V> *__restrict__ tw, KConst scale,
-           uint32_t do_scale, uint32_t vec)
+    k_nttw(KCtx c, void *__restrict__ data, uint64_t units, uint64_t nelem, const TwL<W, V> *__restrict__ tw,
+           KConst scale, uint32_t do_scale, uint32_t vec)
 {
     using R = Red<W, V>;
     using El = typename R::E;
     using T = TwL<W, V>;
+    static_assert(L >= 4 && L <= 10, "lengths 16 to 1024");
+    constexpr int G = L > 8 ? 1 << (L - 8) : 1;
+    constexpr uint32_t UNIT = 256u * G;
+    constexpr bool H2 = L > 2, H3 = L > 3, H4 = L > 4, H5 = L > 5, H6 = L > 6, H7 = L > 7;  // stage st exists
     constexpr int WAVES = BLOCK / 64;
-    constexpr uint32_t n = 256u * G;
     __shared__ __align__(16) El lds[WAVES][G][256];
     const R red(c);
     const El N = (El)c.N;
@@ -341,13 +351,29 @@ __global__ void __launch_bounds__(BLOCK)
     const uint32_t base2 = f1 + 4 * f0 + 16 * f2;            // step-2 lane: F0 = f0, F1 = f1, F3 = f2
     const uint32_t base3 = f2 + 4 * f0 + 16 * f1;            // step-3 lane: F0 = f0, F1 = f1, F2 = f2
     const uint32_t j2 = f0 + 4 * f1;
-    // block stage st pairs at distance 2^st use w^(G j 2^(7 - st)) = tw[G (j << (7 - st))]
-    const T t01 = tw[G * 64];
-    const T t10 = tw[G * (f0 << 5)], t11 = tw[G * (f0 << 4)], t12 = tw[G * ((f0 + 4) << 4)];
-    const T t20 = tw[G * (j2 << 3)], t21 = tw[G * (j2 << 2)], t22 = tw[G * ((j2 + 16) << 2)];
-    const T t30 = tw[G * (lane << 1)], t31 = tw[G * lane], t32 = tw[G * (lane + 64)];
-    // stages across blocks, at position j = lane + 64 k of the block: stage 8 uses
-    // w^(j n / 512) = tw[j (G / 2)], stage 9 (G = 4) tw[j] and tw[j + 256]
+    auto twi = [&](int st, uint32_t j) -> T { return tw[j << (L - 1 - st)]; };
+    const T t01 = twi(1, 1);
+    T t10{}, t11{}, t12{}, t20{}, t21{}, t22{}, t30{}, t31{}, t32{};
+    if constexpr (H2)
+        t10 = twi(2, f0);
+    if constexpr (H3) {
+        t11 = twi(3, f0);
+        t12 = twi(3, f0 + 4);
+    }
+    if constexpr (H4)
+        t20 = twi(4, j2);
+    if constexpr (H5) {
+        t21 = twi(5, j2);
+        t22 = twi(5, j2 + 16);
+    }
+    if constexpr (H6)
+        t30 = twi(6, lane);
+    if constexpr (H7) {
+        t31 = twi(7, lane);
+        t32 = twi(7, lane + 64);
+    }
+    // stages across blocks (G > 1), at position j = lane + 64 k of the block: stage 8 uses
+    // tw[j << (L - 9)], stage 9 (G = 4) tw[j] and tw[j + 256]
     T u0[4], u1[4], u2[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -360,6 +386,14 @@ __global__ void __launch_bounds__(BLOCK)
             u2[k] = tw[j + 256];
         }
     }
+    // G = 1: the unit offset of slot k's coefficient (position 4 brev6(lane) + k)
+    uint32_t off[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t P = 4 * (__brev(lane) >> 26) + (uint32_t)k;
+        const uint32_t p = P & ((1u << L) - 1);
+        off[k] = (P - p) + (__brev(p) >> (32 - L));
+    }
     auto outv = [&](El y) -> El {
         if constexpr (LAZY)
             return do_scale ? below<El>(lazy_mul(red, y, (El)scale.b), N) : below<El>(below<El>(y, (El)(2 * N)), N);
@@ -369,39 +403,50 @@ __global__ void __launch_bounds__(BLOCK)
     const uint64_t stride = (uint64_t)gridDim.x * WAVES;
     uint64_t t = (uint64_t)blockIdx.x * WAVES + wv;
     El nx[G][4];
-    // block b, slot k: x[brev(b) + G (lane + 64 brev2(k))]; chunk element e is block brev(e)
     auto fetch = [&](uint64_t p) {
-        const El *x = (const El *)data + p * n + (uint64_t)G * lane;
+        if constexpr (G == 1) {
+            const El *x = (const El *)data + p * UNIT;
+            if (L >= 8 || (p + 1) * UNIT <= nelem) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const El *q = x + 64 * G * br2((uint32_t)k);
-            El v[G];
-            if constexpr (G == 1) {
-                v[0] = q[0];
-            } else if (vec) {
-                load_chunk<El, G, false>(q, v);
-            } else {
+                for (int k = 0; k < 4; ++k)
+                    nx[0][k] = x[off[k]];
+            } else {  // the batch's last, partial unit: whole polynomials in or out
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    nx[0][k] = p * UNIT + off[k] < nelem ? x[off[k]] : (El)0;
+            }
+        } else {
+            // block b, slot k: x[brev(b) + G (lane + 64 brev2(k))]; chunk element e is block brev(e)
+            const El *x = (const El *)data + p * UNIT + (uint64_t)G * lane;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const El *q = x + 64 * G * br2((uint32_t)k);
+                El v[G];
+                if (vec) {
+                    load_chunk<El, G, false>(q, v);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < G; ++e)
+                        v[e] = q[e];
+                }
 #pragma unroll
                 for (int e = 0; e < G; ++e)
-                    v[e] = q[e];
+                    nx[G == 4 ? (int)br2((uint32_t)e) : e][k] = v[e];
             }
-#pragma unroll
-            for (int e = 0; e < G; ++e)
-                nx[G == 4 ? (int)br2((uint32_t)e) : e][k] = v[e];
         }
     };
-    if (t < batch)
+    if (t < units)
         fetch(t);
-    for (; t < batch; t += stride) {
+    for (; t < units; t += stride) {
         El a[G][4];
 #pragma unroll
         for (int b = 0; b < G; ++b)
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 a[b][k] = nx[b][k];
-        if (t + stride < batch)
+        if (t + stride < units)
             fetch(t + stride);
-        // step 0: stage 0 (unit twiddles), stage 1 (1 and w^64 of the block root)
+        // step 0: stage 0 (unit twiddles), stage 1 (1 and w^(n/4))
 #pragma unroll
         for (int b = 0; b < G; ++b) {
             butterfly1<El, FAST, LAZY>(a[b][0], a[b][1], N);
@@ -422,10 +467,14 @@ __global__ void __launch_bounds__(BLOCK)
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
         for (int b = 0; b < G; ++b) {
-            butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][1], t10, N);
-            butterfly<R, V, FAST, LAZY>(red, a[b][2], a[b][3], t10, N);
-            butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][2], t11, N);
-            butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t12, N);
+            if constexpr (H2) {
+                butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][1], t10, N);
+                butterfly<R, V, FAST, LAZY>(red, a[b][2], a[b][3], t10, N);
+            }
+            if constexpr (H3) {
+                butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][2], t11, N);
+                butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t12, N);
+            }
             lds_put4<El>(&lds[wv][b][4 * lane], a[b]);
         }
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -437,10 +486,14 @@ __global__ void __launch_bounds__(BLOCK)
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
         for (int b = 0; b < G; ++b) {
-            butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][1], t20, N);
-            butterfly<R, V, FAST, LAZY>(red, a[b][2], a[b][3], t20, N);
-            butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][2], t21, N);
-            butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t22, N);
+            if constexpr (H4) {
+                butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][1], t20, N);
+                butterfly<R, V, FAST, LAZY>(red, a[b][2], a[b][3], t20, N);
+            }
+            if constexpr (H5) {
+                butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][2], t21, N);
+                butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t22, N);
+            }
             lds_put4<El>(&lds[wv][b][4 * lane], a[b]);
         }
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -452,10 +505,14 @@ __global__ void __launch_bounds__(BLOCK)
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
         for (int b = 0; b < G; ++b) {
-            butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][1], t30, N);
-            butterfly<R, V, FAST, LAZY>(red, a[b][2], a[b][3], t30, N);
-            butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][2], t31, N);
-            butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t32, N);
+            if constexpr (H6) {
+                butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][1], t30, N);
+                butterfly<R, V, FAST, LAZY>(red, a[b][2], a[b][3], t30, N);
+            }
+            if constexpr (H7) {
+                butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][2], t31, N);
+                butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t32, N);
+            }
         }
         // the stages across blocks: position lane + 64 k of every block, in registers
 #pragma unroll
@@ -469,12 +526,19 @@ __global__ void __launch_bounds__(BLOCK)
                 butterfly<R, V, FAST, LAZY>(red, a[1][k], a[3][k], u2[k], N);
             }
         }
-        El *y = (El *)data + t * n + lane;
+        El *y = (El *)data + t * UNIT + lane;
+        if (L >= 8 || (t + 1) * UNIT <= nelem) {
 #pragma unroll
-        for (int b = 0; b < G; ++b)
+            for (int b = 0; b < G; ++b)
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    y[256 * b + 64 * k] = outv(a[b][k]);
+        } else {
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                y[256 * b + 64 * k] = outv(a[b][k]);
+                if (t * UNIT + lane + 64 * k < nelem)
+                    y[64 * k] = outv(a[0][k]);
+        }
     }
 }
 
@@ -606,38 +670,43 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
     const dim3 grid((unsigned)batch), blk(block);
     const auto *twc = (const TwL<W, CLASSIC> *)t.dev;
     const auto *twp = (const TwL<W, PLANTARD> *)t.dev;
-    if (log2n >= 8 && log2n <= 10) {
-        // one wavefront per polynomial, waves looping over the batch
+    if (log2n >= 4 && log2n <= 10) {
+        // one wavefront per unit of max(n, 256) coefficients, waves looping over the units
         constexpr uint64_t WAVES = BLOCK / 64;
-        const uint64_t blocks = std::min<uint64_t>((batch + WAVES - 1) / WAVES, (uint64_t)device_cus() * NTTW_BPC);
+        const uint64_t nelem = (uint64_t)batch << log2n;
+        const uint64_t units = log2n >= 8 ? (uint64_t)batch : (nelem + 255) / 256;
+        const uint64_t blocks = std::min<uint64_t>((units + WAVES - 1) / WAVES, (uint64_t)device_cus() * NTTW_BPC);
         const dim3 g((unsigned)blocks), b(BLOCK);
-        const uint64_t nb = batch;
         // chunk loads (n / 256 words per lane and slot) when the polynomials are aligned to them
-        const size_t chunk = std::min<size_t>(16, ((size_t)n / 256) * sizeof(El));
+        const size_t chunk = std::min<size_t>(16, std::max<size_t>(1, (size_t)n / 256) * sizeof(El));
         const uint32_t cv = (uintptr_t)data % chunk == 0 ? 1u : 0u;
-        auto go = [&](auto gc) {
-            constexpr int GG = decltype(gc)::value;
+        auto go = [&](auto lc) {
+            constexpr int LL = decltype(lc)::value;
             if (lazy)
-                hipLaunchKernelGGL((k_nttw<W, CLASSIC, true, true, GG>), g, b, 0, s, k, data, nb, twc, t.scale, inv, cv);
+                hipLaunchKernelGGL((k_nttw<W, CLASSIC, true, true, LL>), g, b, 0, s, k, data, units, nelem, twc,
+                                   t.scale, inv, cv);
             else if (variant == CLASSIC && fast)
-                hipLaunchKernelGGL((k_nttw<W, CLASSIC, true, false, GG>), g, b, 0, s, k, data, nb, twc, t.scale, inv,
-                                   cv);
+                hipLaunchKernelGGL((k_nttw<W, CLASSIC, true, false, LL>), g, b, 0, s, k, data, units, nelem, twc,
+                                   t.scale, inv, cv);
             else if (variant == CLASSIC)
-                hipLaunchKernelGGL((k_nttw<W, CLASSIC, false, false, GG>), g, b, 0, s, k, data, nb, twc, t.scale, inv,
-                                   cv);
+                hipLaunchKernelGGL((k_nttw<W, CLASSIC, false, false, LL>), g, b, 0, s, k, data, units, nelem, twc,
+                                   t.scale, inv, cv);
             else if (fast)
-                hipLaunchKernelGGL((k_nttw<W, PLANTARD, true, false, GG>), g, b, 0, s, k, data, nb, twp, t.scale, inv,
-                                   cv);
+                hipLaunchKernelGGL((k_nttw<W, PLANTARD, true, false, LL>), g, b, 0, s, k, data, units, nelem, twp,
+                                   t.scale, inv, cv);
             else
-                hipLaunchKernelGGL((k_nttw<W, PLANTARD, false, false, GG>), g, b, 0, s, k, data, nb, twp, t.scale,
-                                   inv, cv);
+                hipLaunchKernelGGL((k_nttw<W, PLANTARD, false, false, LL>), g, b, 0, s, k, data, units, nelem, twp,
+                                   t.scale, inv, cv);
         };
-        if (log2n == 8)
-            go(std::integral_constant<int, 1>{});
-        else if (log2n == 9)
-            go(std::integral_constant<int, 2>{});
-        else
-            go(std::integral_constant<int, 4>{});
+        switch (log2n) {
+        case 4: go(std::integral_constant<int, 4>{}); break;
+        case 5: go(std::integral_constant<int, 5>{}); break;
+        case 6: go(std::integral_constant<int, 6>{}); break;
+        case 7: go(std::integral_constant<int, 7>{}); break;
+        case 8: go(std::integral_constant<int, 8>{}); break;
+        case 9: go(std::integral_constant<int, 9>{}); break;
+        default: go(std::integral_constant<int, 10>{}); break;
+        }
         return hipGetLastError();
     }
     if (lazy) {
