@@ -7,7 +7,7 @@
 // polynomials of n residues in [0, N) stored contiguously (natural order in
 // and out, in place).
 //
-// Lengths 16 to 1024 (k_nttw): one wavefront per max(n, 256) coefficients,
+// Lengths 16 to 4096, to 1024 for 64-bit words (k_nttw): one wavefront per max(n, 256) coefficients,
 // loaded from HBM straight into registers in bit-reversed order and exchanged
 // between radix-4 steps through a conflict-free LDS layout.  Other lengths (k_ntt):
 // one workgroup transforms one polynomial: coefficients are loaded into LDS
@@ -287,7 +287,7 @@ __device__ __forceinline__ void lds_put4(El *p, const El (&a)[4])
     }
 }
 
-// Lengths n = 2^L, 4 <= L <= 10: one wavefront per unit of max(n, 256)
+// Lengths n = 2^L, 4 <= L <= 12: one wavefront per unit of max(n, 256)
 // consecutive coefficients, no workgroup barriers.
 //
 // A unit is one polynomial when n >= 256 and 256/n polynomials side by side
@@ -296,13 +296,14 @@ __device__ __forceinline__ void lds_put4(El *p, const El (&a)[4])
 // stage st pairs positions that differ in bit st, with the twiddle
 // w^(j n / 2^(st+1)) = tw[j << (L - 1 - st)] at position j mod 2^st.  Stages
 // L..7 do not exist when n < 256 and are skipped (the polynomials of a unit
-// never mix).  When n = 256 G, G = 2 or 4, the first eight stages act on G
+// never mix).  When n = 256 G, G = 2 to 16, the first eight stages act on G
 // separate blocks of 256 positions; block b holds the coefficients
 // x[brev(b) + G m], m = 0..255 (brev over log2 G bits), so the G values a
 // lane needs for one slot of all blocks are G consecutive words; after those
 // stages the remaining log2 G stages pair positions that differ only in the
 // block index, and a lane already holds every member of its groups: they run
-// in registers.
+// in registers (G = 2^(L-8) up to 16; from G = 8 on the blocks take their
+// steps in turn through one LDS buffer and no unit is loaded ahead).
 //
 // Within a block of 256, positions P split into four 2-bit fields F0..F3
 // (F_s = bits 2s, 2s+1); radix-4 step s runs stages 2s and 2s+1 on the groups
@@ -335,12 +336,16 @@ __global__ void __launch_bounds__(BLOCK)
     using R = Red<W, V>;
     using El = typename R::E;
     using T = TwL<W, V>;
-    static_assert(L >= 4 && L <= 10, "lengths 16 to 1024");
+    static_assert(L >= 4 && L <= 12, "lengths 16 to 4096");
     constexpr int G = L > 8 ? 1 << (L - 8) : 1;
     constexpr uint32_t UNIT = 256u * G;
+    constexpr bool PREFETCH = G <= 4;  // registers: the next unit's G x 4 coefficients
+    // LDS: one buffer per block when G <= 4 (their steps interleave); one per wave
+    // when G >= 8, the blocks taking their steps in turn (G buffers would not fit)
+    constexpr int NB = G <= 4 ? G : 1;
     constexpr bool H2 = L > 2, H3 = L > 3, H4 = L > 4, H5 = L > 5, H6 = L > 6, H7 = L > 7;  // stage st exists
     constexpr int WAVES = BLOCK / 64;
-    __shared__ __align__(16) El lds[WAVES][G][256];
+    __shared__ __align__(16) El lds[WAVES][NB][256];
     const R red(c);
     const El N = (El)c.N;
     const uint32_t lane = threadIdx.x & 63u;
@@ -400,6 +405,46 @@ __global__ void __launch_bounds__(BLOCK)
         else
             return do_scale ? tw_mul<R, V, FAST>(red, y, scale) : y;
     };
+    // the four radix-4 steps of one block through one LDS buffer (G >= 8)
+    auto block_steps = [&](El(&ab)[4], El *sb) {
+        butterfly1<El, FAST, LAZY>(ab[0], ab[1], N);
+        butterfly1<El, FAST, LAZY>(ab[2], ab[3], N);
+        butterfly1<El, FAST, LAZY>(ab[0], ab[2], N);
+        butterfly<R, V, FAST, LAZY>(red, ab[1], ab[3], t01, N);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        lds_put4<El>(sb + 4 * lane, ab);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        ab[0] = sb[base1];
+        ab[1] = sb[base1 + 128];
+        ab[2] = sb[base1 + 64];
+        ab[3] = sb[base1 + 192];
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        butterfly<R, V, FAST, LAZY>(red, ab[0], ab[1], t10, N);
+        butterfly<R, V, FAST, LAZY>(red, ab[2], ab[3], t10, N);
+        butterfly<R, V, FAST, LAZY>(red, ab[0], ab[2], t11, N);
+        butterfly<R, V, FAST, LAZY>(red, ab[1], ab[3], t12, N);
+        lds_put4<El>(sb + 4 * lane, ab);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            ab[k] = sb[base2 + 64 * k];
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        butterfly<R, V, FAST, LAZY>(red, ab[0], ab[1], t20, N);
+        butterfly<R, V, FAST, LAZY>(red, ab[2], ab[3], t20, N);
+        butterfly<R, V, FAST, LAZY>(red, ab[0], ab[2], t21, N);
+        butterfly<R, V, FAST, LAZY>(red, ab[1], ab[3], t22, N);
+        lds_put4<El>(sb + 4 * lane, ab);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            ab[k] = sb[base3 + 64 * k];
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        butterfly<R, V, FAST, LAZY>(red, ab[0], ab[1], t30, N);
+        butterfly<R, V, FAST, LAZY>(red, ab[2], ab[3], t30, N);
+        butterfly<R, V, FAST, LAZY>(red, ab[0], ab[2], t31, N);
+        butterfly<R, V, FAST, LAZY>(red, ab[1], ab[3], t32, N);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    };
     const uint64_t stride = (uint64_t)gridDim.x * WAVES;
     uint64_t t = (uint64_t)blockIdx.x * WAVES + wv;
     El nx[G][4];
@@ -431,87 +476,95 @@ __global__ void __launch_bounds__(BLOCK)
                 }
 #pragma unroll
                 for (int e = 0; e < G; ++e)
-                    nx[G == 4 ? (int)br2((uint32_t)e) : e][k] = v[e];
+                    nx[G == 1 ? 0 : (int)(__brev((uint32_t)e) >> (32 - __builtin_ctz(G)))][k] = v[e];
             }
         }
     };
-    if (t < units)
+    if (PREFETCH && t < units)
         fetch(t);
     for (; t < units; t += stride) {
+        if (!PREFETCH)
+            fetch(t);
         El a[G][4];
 #pragma unroll
         for (int b = 0; b < G; ++b)
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 a[b][k] = nx[b][k];
-        if (t + stride < units)
+        if (PREFETCH && t + stride < units)
             fetch(t + stride);
-        // step 0: stage 0 (unit twiddles), stage 1 (1 and w^(n/4))
+        if constexpr (G >= 8) {
 #pragma unroll
-        for (int b = 0; b < G; ++b) {
-            butterfly1<El, FAST, LAZY>(a[b][0], a[b][1], N);
-            butterfly1<El, FAST, LAZY>(a[b][2], a[b][3], N);
-            butterfly1<El, FAST, LAZY>(a[b][0], a[b][2], N);
-            butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t01, N);
-            lds_put4<El>(&lds[wv][b][4 * lane], a[b]);
-        }
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            for (int b = 0; b < G; ++b)
+                block_steps(a[b], lds[wv][0]);
+        } else {
+            // step 0: stage 0 (unit twiddles), stage 1 (1 and w^(n/4))
 #pragma unroll
-        for (int b = 0; b < G; ++b) {
-            const El *s = lds[wv][b];
-            a[b][0] = s[base1];
-            a[b][1] = s[base1 + 128];
-            a[b][2] = s[base1 + 64];
-            a[b][3] = s[base1 + 192];
-        }
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-#pragma unroll
-        for (int b = 0; b < G; ++b) {
-            if constexpr (H2) {
-                butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][1], t10, N);
-                butterfly<R, V, FAST, LAZY>(red, a[b][2], a[b][3], t10, N);
+            for (int b = 0; b < G; ++b) {
+                butterfly1<El, FAST, LAZY>(a[b][0], a[b][1], N);
+                butterfly1<El, FAST, LAZY>(a[b][2], a[b][3], N);
+                butterfly1<El, FAST, LAZY>(a[b][0], a[b][2], N);
+                butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t01, N);
+                lds_put4<El>(&lds[wv][b][4 * lane], a[b]);
             }
-            if constexpr (H3) {
-                butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][2], t11, N);
-                butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t12, N);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+            for (int b = 0; b < G; ++b) {
+                const El *s = lds[wv][b];
+                a[b][0] = s[base1];
+                a[b][1] = s[base1 + 128];
+                a[b][2] = s[base1 + 64];
+                a[b][3] = s[base1 + 192];
             }
-            lds_put4<El>(&lds[wv][b][4 * lane], a[b]);
-        }
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
-        for (int b = 0; b < G; ++b)
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                a[b][k] = lds[wv][b][base2 + 64 * k];
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-#pragma unroll
-        for (int b = 0; b < G; ++b) {
-            if constexpr (H4) {
-                butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][1], t20, N);
-                butterfly<R, V, FAST, LAZY>(red, a[b][2], a[b][3], t20, N);
+            for (int b = 0; b < G; ++b) {
+                if constexpr (H2) {
+                    butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][1], t10, N);
+                    butterfly<R, V, FAST, LAZY>(red, a[b][2], a[b][3], t10, N);
+                }
+                if constexpr (H3) {
+                    butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][2], t11, N);
+                    butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t12, N);
+                }
+                lds_put4<El>(&lds[wv][b][4 * lane], a[b]);
             }
-            if constexpr (H5) {
-                butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][2], t21, N);
-                butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t22, N);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+            for (int b = 0; b < G; ++b)
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    a[b][k] = lds[wv][b][base2 + 64 * k];
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+            for (int b = 0; b < G; ++b) {
+                if constexpr (H4) {
+                    butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][1], t20, N);
+                    butterfly<R, V, FAST, LAZY>(red, a[b][2], a[b][3], t20, N);
+                }
+                if constexpr (H5) {
+                    butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][2], t21, N);
+                    butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t22, N);
+                }
+                lds_put4<El>(&lds[wv][b][4 * lane], a[b]);
             }
-            lds_put4<El>(&lds[wv][b][4 * lane], a[b]);
-        }
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
-        for (int b = 0; b < G; ++b)
+            for (int b = 0; b < G; ++b)
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                a[b][k] = lds[wv][b][base3 + 64 * k];
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                for (int k = 0; k < 4; ++k)
+                    a[b][k] = lds[wv][b][base3 + 64 * k];
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
-        for (int b = 0; b < G; ++b) {
-            if constexpr (H6) {
-                butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][1], t30, N);
-                butterfly<R, V, FAST, LAZY>(red, a[b][2], a[b][3], t30, N);
-            }
-            if constexpr (H7) {
-                butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][2], t31, N);
-                butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t32, N);
+            for (int b = 0; b < G; ++b) {
+                if constexpr (H6) {
+                    butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][1], t30, N);
+                    butterfly<R, V, FAST, LAZY>(red, a[b][2], a[b][3], t30, N);
+                }
+                if constexpr (H7) {
+                    butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][2], t31, N);
+                    butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t32, N);
+                }
             }
         }
         // the stages across blocks: position lane + 64 k of every block, in registers
@@ -524,6 +577,24 @@ __global__ void __launch_bounds__(BLOCK)
                 butterfly<R, V, FAST, LAZY>(red, a[2][k], a[3][k], u0[k], N);
                 butterfly<R, V, FAST, LAZY>(red, a[0][k], a[2][k], u1[k], N);
                 butterfly<R, V, FAST, LAZY>(red, a[1][k], a[3][k], u2[k], N);
+            } else if constexpr (G >= 8) {
+                // stage 8 + h pairs blocks b and b + 2^h at position j + 256 (b mod 2^h) mod 2^(8 + h);
+                // its 2^h twiddles per k are read from the table (cache-resident) for every unit:
+                // 4 (2^(log2 G) - 1) of them do not fit in registers.  z hides that the
+                // addresses do not change from unit to unit, so they are not kept in registers.
+                uint32_t z = 0;
+                asm volatile("" : "+v"(z));
+                const uint32_t j = lane + 64u * (uint32_t)k + z;
+#pragma unroll
+                for (int h = 0; (1 << h) < G; ++h) {
+#pragma unroll
+                    for (int b = 0; b < G; ++b) {
+                        if (b & (1 << h))
+                            continue;
+                        const uint32_t jj = j + 256u * (uint32_t)(b & ((1 << h) - 1));
+                        butterfly<R, V, FAST, LAZY>(red, a[b][k], a[b + (1 << h)][k], tw[jj << (L - 9 - h)], N);
+                    }
+                }
             }
         }
         El *y = (El *)data + t * UNIT + lane;
@@ -670,7 +741,9 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
     const dim3 grid((unsigned)batch), blk(block);
     const auto *twc = (const TwL<W, CLASSIC> *)t.dev;
     const auto *twp = (const TwL<W, PLANTARD> *)t.dev;
-    if (log2n >= 4 && log2n <= 10) {
+    // 64-bit words at lengths above 1024 would not fit the registers (the
+    // compiler spills): they take the workgroup kernel
+    if (log2n >= 4 && log2n <= (W == 64 ? 10u : 12u)) {
         // one wavefront per unit of max(n, 256) coefficients, waves looping over the units
         constexpr uint64_t WAVES = BLOCK / 64;
         const uint64_t nelem = (uint64_t)batch << log2n;
@@ -682,7 +755,9 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
         const uint32_t cv = (uintptr_t)data % chunk == 0 ? 1u : 0u;
         auto go = [&](auto lc) {
             constexpr int LL = decltype(lc)::value;
-            if (lazy)
+            if constexpr (W == 64 && LL > 10)
+                return;
+            else if (lazy)
                 hipLaunchKernelGGL((k_nttw<W, CLASSIC, true, true, LL>), g, b, 0, s, k, data, units, nelem, twc,
                                    t.scale, inv, cv);
             else if (variant == CLASSIC && fast)
@@ -705,7 +780,9 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
         case 7: go(std::integral_constant<int, 7>{}); break;
         case 8: go(std::integral_constant<int, 8>{}); break;
         case 9: go(std::integral_constant<int, 9>{}); break;
-        default: go(std::integral_constant<int, 10>{}); break;
+        case 10: go(std::integral_constant<int, 10>{}); break;
+        case 11: go(std::integral_constant<int, 11>{}); break;
+        default: go(std::integral_constant<int, 12>{}); break;
         }
         return hipGetLastError();
     }
