@@ -263,51 +263,65 @@ struct Ladder {
 
 // x^e mod N for U elements of one lane, in lockstep (U independent product
 // chains per wave): Montgomery form x R = REDC(x * (R^2 mod N)), a
-// left-to-right 2-bit fixed-window ladder of Montgomery products (every lane
-// runs the same 32 windows: no divergence); the caller converts back with one
-// REDC (Ladder::out).  The returned Montgomery-form values are below 2N
-// (mode 1), in (-N, N) (mode 3) or below N.  Element u's four window entries (1, x, x^2, x^3 in Montgomery
-// form) live in LDS at tab[u * BLOCK + j * stride], j = 0..3: one LDS read per
-// window instead of a 4-way register select.  Lanes of a wave use adjacent
-// words of each entry row, so the reads are free of bank conflicts.
-template <class R, int MODE, int U>
+// left-to-right WB-bit fixed-window ladder of Montgomery products (every lane
+// runs the same 64/WB windows: no divergence); the caller converts back with
+// one REDC (Ladder::out).  The returned Montgomery-form values are below 2N
+// (mode 1), in (-N, N) (mode 3) or below N.  Element u's 2^WB window entries
+// (x^j in Montgomery form, j = 0 .. 2^WB - 1) live in LDS at
+// tab[u * BLOCK + j * stride]: one LDS read per window instead of a register
+// select.  Lanes of a wave use adjacent words of each entry row, so the reads
+// are free of bank conflicts.  Per element: 2^WB - 2 products for the table,
+// (64/WB - 1) (WB squarings + 1 product) for the windows (the top one is a
+// table read) and one product into the Montgomery form: 97 products at WB = 2,
+// 90 at WB = 4, which also halves the window-index arithmetic.
+template <class R, int MODE, int U, int WB = 2>
 __device__ __forceinline__ void pow_lanes(const R &red, const typename R::E (&x)[U], const uint64_t (&k)[U],
                                           typename R::E r2, typename R::E one, typename R::E *tab, uint32_t stride,
                                           typename R::E (&y)[U])
 {
     using El = typename R::E;
     using L = Ladder<R, MODE>;
+    static_assert(WB == 2 || WB == 4, "2- or 4-bit windows");
+    constexpr int NE = 1 << WB;
+    constexpr uint32_t MASK = NE - 1;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
+        El e[NE];
+        e[0] = one;
+        e[1] = L::mul(red, x[u], r2);
+#pragma unroll
+        for (int j = 2; j < NE; ++j)
+            e[j] = (j & 1) ? L::mul(red, e[j - 1], e[1]) : L::sqr(red, e[j / 2]);
         El *t = tab + u * BLOCK;
-        const El x1 = L::mul(red, x[u], r2);
-        const El x2 = L::sqr(red, x1);
-        const El x3 = L::mul(red, x2, x1);
-        t[0] = one;
-        t[stride] = x1;
-        t[2 * stride] = x2;
-        t[3 * stride] = x3;
+#pragma unroll
+        for (int j = 0; j < NE; ++j)
+            t[j * stride] = e[j];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-        y[u] = tab[u * BLOCK + (uint32_t)(k[u] >> 62) * stride];
+        y[u] = tab[u * BLOCK + (uint32_t)(k[u] >> (64 - WB)) * stride];
 #pragma unroll 4
-    for (int s = 60; s >= 0; s -= 2) {
+    for (int s = 64 - 2 * WB; s >= 0; s -= WB) {
         El t[U];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            t[u] = tab[u * BLOCK + ((uint32_t)(k[u] >> s) & 3u) * stride];
+            t[u] = tab[u * BLOCK + ((uint32_t)(k[u] >> s) & MASK) * stride];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            y[u] = L::sqr(red, y[u]);
+        for (int q = 0; q < WB; ++q)
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            y[u] = L::sqr(red, y[u]);
+            for (int u = 0; u < U; ++u)
+                y[u] = L::sqr(red, y[u]);
 #pragma unroll
         for (int u = 0; u < U; ++u)
             y[u] = L::mul(red, y[u], t[u]);
     }
 }
+
+// Window width of the standalone exponentiation kernel: 4 bits for the 32-bit
+// signed ladder (a 16-entry table of 4-byte words per element), 2 bits where
+// the table entries are 8 bytes or the products are the general form.
+template <int MODE>
+constexpr int pow_window() { return MODE == 3 ? 4 : 2; }
 
 template <int W, int U, int MODE>
 __global__ void __launch_bounds__(BLOCK)
@@ -315,7 +329,8 @@ __global__ void __launch_bounds__(BLOCK)
 {
     using R = Red<W, CLASSIC>;
     using El = typename R::E;
-    __shared__ El tab[4 * BLOCK * U];
+    constexpr int WB = pow_window<MODE>();
+    __shared__ El tab[(1 << WB) * BLOCK * U];
     const R red(c);
     const El r2 = (El)c.r2, one = (El)c.rmodn;
     const El *px = (const El *)xin;
@@ -331,7 +346,7 @@ __global__ void __launch_bounds__(BLOCK)
             k[u] = i < n ? ein[i] : 0;
         }
         El y[U];
-        pow_lanes<R, MODE, U>(red, x, k, r2, one, tab + threadIdx.x, BLOCK * U, y);
+        pow_lanes<R, MODE, U, WB>(red, x, k, r2, one, tab + threadIdx.x, BLOCK * U, y);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint64_t i = base + (uint64_t)u * BLOCK;
