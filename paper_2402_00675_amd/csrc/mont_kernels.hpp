@@ -272,8 +272,9 @@ struct Ladder {
 // select.  Lanes of a wave use adjacent words of each entry row, so the reads
 // are free of bank conflicts.  Per element: 2^WB - 2 products for the table,
 // (64/WB - 1) (WB squarings + 1 product) for the windows (the top one is a
-// table read) and one product into the Montgomery form: 97 products at WB = 2,
-// 90 at WB = 4, which also halves the window-index arithmetic.
+// table read) and one product into the Montgomery form: 96 products at WB = 2,
+// 90 at WB = 4 (which also halves the window-index arithmetic), plus the
+// caller's REDC back.
 template <class R, int MODE, int U, int WB = 2>
 __device__ __forceinline__ void pow_lanes(const R &red, const typename R::E (&x)[U], const uint64_t (&k)[U],
                                           typename R::E r2, typename R::E one, typename R::E *tab, uint32_t stride,
