@@ -548,6 +548,23 @@ def test_crt_parity(k, kind):
     assert words_to_ints(got) == want
 
 
+@pytest.mark.parametrize("k", [1, 3, 8])
+def test_crt_small_and_edge_counts(k):
+    """Element counts around one workgroup (the output leaves through LDS in
+    16-byte chunks of the workgroup's words; an odd word count ends with one
+    8-byte store), for each form: 60-bit primes (Shoup steps), 64-bit primes,
+    moduli of mixed sizes."""
+    g = inp.rng(94, 200 + k)
+    for mods in (inp.random_primes(g, 60, k), inp.random_primes(g, 64, k),
+                 [3, 65537, (1 << 61) - 1, 1000000007, 127, 8191, 131071, (1 << 64) - 59][:k]):
+        ctxs = [mg.setup(m, 64) for m in mods]
+        for n in (1, 2, 255, 256, 257):
+            res = np.stack([g.integers(0, m, size=n, dtype=np.uint64) for m in mods])
+            got = mg.crt(ctxs, dev(res)).cpu().numpy()
+            want = orc.crt([[int(x) for x in res[j]] for j in range(k)], mods)
+            assert words_to_ints(got) == want, (mods[0], n)
+
+
 def test_crt_rejects_common_factor():
     ctxs = [mg.setup(15, 64), mg.setup(21, 64)]
     res = torch.zeros((2, 16), dtype=torch.uint64, device="cuda")
