@@ -61,6 +61,13 @@ class JobStream:
         own = set(range(njobs)) if distinct_outputs is True else set(distinct_outputs or ())
         if len(own) < njobs:
             self.sink = {32: _pinned(torch, P, torch.uint32), 64: _pinned(torch, P, torch.uint64)}
+        # the jobs' own outputs are slices of one pinned arena per word size (64-element aligned)
+        own_len = {32: 0, 64: 0}
+        for i in own:
+            own_len[64 if wide[i] else 32] += (int(lens[i]) + 63) // 64 * 64
+        self.arena = {w: _pinned(torch, max(own_len[w], 1), torch.uint32 if w == 32 else torch.uint64)
+                      for w in (32, 64)}
+        arena_at = {32: 0, 64: 0}
         esz = {32: 4, 64: 8}
         for i in range(njobs):
             w = 64 if wide[i] else 32
@@ -73,7 +80,8 @@ class JobStream:
             else:
                 op, in1 = _lib.OP_POW, self.exps.data_ptr() + o * 8
             if i in own:
-                out_t = _pinned(torch, n, torch.uint32 if w == 32 else torch.uint64)
+                out_t = self.arena[w][arena_at[w]:arena_at[w] + n]
+                arena_at[w] += (n + 63) // 64 * 64
                 self.outs[i] = out_t
                 out = out_t.data_ptr()
             else:
@@ -84,7 +92,7 @@ class JobStream:
     def pinned_buffers(self):
         """Every pinned host buffer the stream's jobs read or write."""
         bufs = [t for pair in self.pool.values() for t in pair] + [self.exps]
-        bufs += list(getattr(self, "sink", {}).values()) + list(self.outs.values())
+        bufs += list(getattr(self, "sink", {}).values()) + list(self.arena.values())
         return bufs
 
     def declare(self, server):

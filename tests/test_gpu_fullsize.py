@@ -102,41 +102,48 @@ def test_pow_bench_shape_sampled():
         assert np.array_equal(got[idx], orc.pow(w, N, x[idx], e[idx]))
 
 
-def test_serving_stream_sampled():
+def test_serving_stream_every_job():
     """The 10^5-job serving stream (60 % products, 40 % exponentiations with
     uniform 64-bit exponents, lengths log-uniform in [2^8, 2^18], odd 31- and
     62-bit moduli) through the server configuration the benchmark times, all
-    jobs submitted at once.  Every 97th job has its own output buffer (the rest
-    write a shared sink) and is checked: products in full, exponentiations on
-    their first and last element and 256 seeded ones."""
+    jobs submitted at once, replayed five times: each pass gives a different
+    fifth of the jobs outputs of their own (the rest write a shared sink), so
+    every job is checked once: products in full, exponentiations on their first
+    and last element and 256 seeded ones."""
     from paper_2402_00675_amd import serve
-    njobs = 100_000
-    stream = serve.JobStream(torch, njobs, distinct_outputs=range(0, njobs, 97))
-    srv = mg.Server(hbm_budget_bytes=8 << 30, streams=3, max_batch_jobs=512)
-    stream.declare(srv)
-    try:
-        done = serve.replay(srv, stream, np.zeros(njobs))
-    finally:
-        srv.close()
-    assert len(done) == njobs and all(d[1] == 0 for d in done)
+    njobs, passes = 100_000, 5
+    checked = {0: 0, 1: 0}
+    for c in range(passes):
+        stream = serve.JobStream(torch, njobs, distinct_outputs=range(c, njobs, passes))
+        srv = mg.Server(hbm_budget_bytes=8 << 30, streams=3, max_batch_jobs=512)
+        stream.declare(srv)
+        try:
+            done = serve.replay(srv, stream, np.zeros(njobs))
+        finally:
+            srv.close()
+        assert len(done) == njobs and all(d[1] == 0 for d in done)
 
-    def job_ok(i):
-        got = stream.outs[i].numpy()
-        x, y = stream.inputs_of(i)
-        w, N, n = (64 if stream.wide[i] else 32), int(stream.mods[i]), len(x)
-        if stream.ops[i] == 0:
-            return bool(np.array_equal(got, orc.mul("classic", w, N, x, y)))
-        pick = np.random.default_rng(i).integers(0, n, size=256)
-        idx = np.unique(np.concatenate([[0, n - 1], pick]))
-        return bool(np.array_equal(got[idx], orc.pow(w, N, x[idx], y[idx])))
+        def job_ok(i):
+            got = stream.outs[i].numpy()
+            x, y = stream.inputs_of(i)
+            w, N, n = (64 if stream.wide[i] else 32), int(stream.mods[i]), len(x)
+            if stream.ops[i] == 0:
+                return bool(np.array_equal(got, orc.mul("classic", w, N, x, y)))
+            pick = np.random.default_rng(i).integers(0, n, size=256)
+            idx = np.unique(np.concatenate([[0, n - 1], pick]))
+            return bool(np.array_equal(got[idx], orc.pow(w, N, x[idx], y[idx])))
 
-    sample = sorted(stream.outs)
-    with cf.ThreadPoolExecutor(WORKERS) as ex:
-        ok = list(ex.map(job_ok, sample))
-    bad = [i for i, v in zip(sample, ok) if not v]
-    assert not bad, bad[:10]
-    assert sum(1 for i in sample if stream.ops[i] == 0) > 400    # both kinds are well represented
-    assert sum(1 for i in sample if stream.ops[i] == 1) > 300
+        sample = sorted(stream.outs)
+        with cf.ThreadPoolExecutor(WORKERS) as ex:
+            ok = list(ex.map(job_ok, sample))
+        bad = [i for i, v in zip(sample, ok) if not v]
+        assert not bad, (c, bad[:10])
+        for i in sample:
+            checked[int(stream.ops[i])] += 1
+        print("pass %d: %d jobs checked" % (c, len(sample)), flush=True)
+        del stream
+    assert checked[0] + checked[1] == njobs
+    assert checked[0] > 55_000 and checked[1] > 35_000    # both kinds are well represented
 
 
 def test_crt_bench_shape_sampled():
