@@ -7,13 +7,14 @@
 // polynomials of n residues in [0, N) stored contiguously (natural order in
 // and out, in place).
 //
-// Lengths 16 to 4096, to 1024 for 64-bit words (k_nttw): one wavefront per max(n, 256) coefficients,
-// loaded from HBM straight into registers in bit-reversed order and exchanged
-// between radix-4 steps through a conflict-free LDS layout.  Other lengths (k_ntt):
-// one workgroup transforms one polynomial: coefficients are loaded into LDS
-// in bit-reversed order together with the compact twiddles, the log2(n)
-// radix-2 Cooley-Tukey stages run two at a time as radix-4 steps in registers
-// (a barrier between steps), and the result is written back (scaled by n^{-1}
+// Lengths 2 to 4096, to 1024 for 64-bit words (k_nttw): one wavefront per
+// max(n, 256) coefficients, loaded from HBM straight into registers in
+// bit-reversed order and exchanged between radix-4 steps through a
+// conflict-free LDS layout.  64-bit words at lengths 2048 and 4096 (k_ntt):
+// one workgroup transforms one polynomial: coefficients are loaded into LDS in
+// bit-reversed order together with the compact twiddles, the log2(n) radix-2
+// Cooley-Tukey stages run two at a time as radix-4 steps in registers (a
+// barrier between steps), and the result is written back (scaled by n^{-1}
 // for the inverse).  The
 // twiddle product is a product by a fixed operand:
 //   classic  -- Montgomery product with w^k R mod N;
@@ -287,7 +288,7 @@ __device__ __forceinline__ void lds_put4(El *p, const El (&a)[4])
     }
 }
 
-// Lengths n = 2^L, 4 <= L <= 12: one wavefront per unit of max(n, 256)
+// Lengths n = 2^L, 1 <= L <= 12: one wavefront per unit of max(n, 256)
 // consecutive coefficients, no workgroup barriers.
 //
 // A unit is one polynomial when n >= 256 and 256/n polynomials side by side
@@ -336,14 +337,14 @@ __global__ void __launch_bounds__(BLOCK)
     using R = Red<W, V>;
     using El = typename R::E;
     using T = TwL<W, V>;
-    static_assert(L >= 4 && L <= 12, "lengths 16 to 4096");
+    static_assert(L >= 1 && L <= 12, "lengths 2 to 4096");
     constexpr int G = L > 8 ? 1 << (L - 8) : 1;
     constexpr uint32_t UNIT = 256u * G;
     constexpr bool PREFETCH = G <= 4;  // registers: the next unit's G x 4 coefficients
     // LDS: one buffer per block when G <= 4 (their steps interleave); one per wave
     // when G >= 8, the blocks taking their steps in turn (G buffers would not fit)
     constexpr int NB = G <= 4 ? G : 1;
-    constexpr bool H2 = L > 2, H3 = L > 3, H4 = L > 4, H5 = L > 5, H6 = L > 6, H7 = L > 7;  // stage st exists
+    constexpr bool H1 = L > 1, H2 = L > 2, H3 = L > 3, H4 = L > 4, H5 = L > 5, H6 = L > 6, H7 = L > 7;  // stage st exists
     constexpr int WAVES = BLOCK / 64;
     __shared__ __align__(16) El lds[WAVES][NB][256];
     const R red(c);
@@ -357,7 +358,9 @@ __global__ void __launch_bounds__(BLOCK)
     const uint32_t base3 = f2 + 4 * f0 + 16 * f1;            // step-3 lane: F0 = f0, F1 = f1, F2 = f2
     const uint32_t j2 = f0 + 4 * f1;
     auto twi = [&](int st, uint32_t j) -> T { return tw[j << (L - 1 - st)]; };
-    const T t01 = twi(1, 1);
+    T t01{};
+    if constexpr (H1)
+        t01 = twi(1, 1);
     T t10{}, t11{}, t12{}, t20{}, t21{}, t22{}, t30{}, t31{}, t32{};
     if constexpr (H2)
         t10 = twi(2, f0);
@@ -503,8 +506,10 @@ __global__ void __launch_bounds__(BLOCK)
             for (int b = 0; b < G; ++b) {
                 butterfly1<El, FAST, LAZY>(a[b][0], a[b][1], N);
                 butterfly1<El, FAST, LAZY>(a[b][2], a[b][3], N);
-                butterfly1<El, FAST, LAZY>(a[b][0], a[b][2], N);
-                butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t01, N);
+                if constexpr (H1) {
+                    butterfly1<El, FAST, LAZY>(a[b][0], a[b][2], N);
+                    butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t01, N);
+                }
                 lds_put4<El>(&lds[wv][b][4 * lane], a[b]);
             }
             __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -743,7 +748,7 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
     const auto *twp = (const TwL<W, PLANTARD> *)t.dev;
     // 64-bit words at lengths above 1024 would not fit the registers (the
     // compiler spills): they take the workgroup kernel
-    if (log2n >= 4 && log2n <= (W == 64 ? 10u : 12u)) {
+    if (log2n <= (W == 64 ? 10u : 12u)) {
         // one wavefront per unit of max(n, 256) coefficients, waves looping over the units
         constexpr uint64_t WAVES = BLOCK / 64;
         const uint64_t nelem = (uint64_t)batch << log2n;
@@ -774,6 +779,9 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
                                    t.scale, inv, cv);
         };
         switch (log2n) {
+        case 1: go(std::integral_constant<int, 1>{}); break;
+        case 2: go(std::integral_constant<int, 2>{}); break;
+        case 3: go(std::integral_constant<int, 3>{}); break;
         case 4: go(std::integral_constant<int, 4>{}); break;
         case 5: go(std::integral_constant<int, 5>{}); break;
         case 6: go(std::integral_constant<int, 6>{}); break;
