@@ -164,8 +164,12 @@ mont_status_t mont_mul_rns(const mont_ctx_t *ctxs, uint32_t k, const void *a, co
  * little-endian uint64 words at out[i*k .. i*k + k) (out 16-byte aligned).
  * The multi-modulus Chinese Remainder Theorem (Section 2 derives the two-
  * modulus case from Theorem 2.1), computed by Garner's mixed-radix
- * conversion with Montgomery products.  MONT_E_DOMAIN if two moduli share a
- * factor; MONT_E_UNSUPPORTED for contexts that are not 64-bit.
+ * conversion: products by the constants N_j^{-1} mod N_i are Montgomery
+ * products, or Shoup's precomputed-quotient products when every modulus is
+ * below 2^62 and below twice every other one (results are identical).
+ * ctxs is a HOST array.  MONT_E_DOMAIN if two moduli share a factor;
+ * MONT_E_UNSUPPORTED for contexts that are not 64-bit; MONT_E_INVAL for k
+ * outside [1, 16], n > ld, or a null or misaligned pointer.
  */
 #define MONT_CRT_MAX 16
 mont_status_t mont_crt(const mont_ctx_t *ctxs, uint32_t k, const void *res, size_t n, size_t ld, void *out,
@@ -415,10 +419,11 @@ mont_status_t mont_stream_ref(const void *a, const void *b, void *out, size_t by
  * 4 v_add_u32, 5 v_lshl_add_u64, 6 v_cndmask_b32, 7 v_cmp_le_u64,
  * 8 v_lshrrev_b64, 9 v_sub_u32, 10 v_min_u32, 11 v_mov_b32, 12 v_and_or_b32,
  * 13 v_add3_u32, 14 v_add_co_u32, 15 v_addc_co_u32, 16 v_or_b32, 17 v_and_b32,
- * 18 v_lshlrev_b32, 19 v_alignbit_b32, 20 v_cmp_ne_u32, 21 v_mad_i64_i32.  `blocks` workgroups of 256 lanes each run iters x 32
- * instances of it in eight independent chains per lane and write one
- * uint64_t per lane to `out` (device memory, blocks * 256 entries).  A kind
- * above 21 returns MONT_E_INVAL.  Not part of the paper's method.
+ * 18 v_lshlrev_b32, 19 v_alignbit_b32, 20 v_cmp_ne_u32, 21 v_mad_i64_i32.
+ * `blocks` workgroups of 256 lanes each run iters x 32 instances of it in
+ * eight independent chains per lane and write one uint64_t per lane to `out`
+ * (device memory, blocks * 256 entries).  A kind above 21 returns
+ * MONT_E_INVAL.  Not part of the paper's method.
  */
 mont_status_t mont_valu_ref(uint32_t kind, uint32_t iters, uint32_t blocks, void *out, void *stream);
 
