@@ -324,16 +324,17 @@ def secondary(torch, mg, inp, args, sections):
                       "Gbutterfly_s": round(batch * n // 2 * log2n / (ms * 1e-3) / 1e9, 1),
                       "GB_s": round(8 * batch * n / (ms * 1e-3) / 1e9, 1)}
             log("ntt %s: %s" % (v, res[v]))
-        # the same coefficient count in 2^16 transforms of length 1024
-        n10 = 1 << 10
-        root10 = next(w for w in (pow(g, (N - 1) // n10, N) for g in range(2, 100)) if pow(w, n10 // 2, N) == N - 1)
-        d10 = d.view(batch * n // n10, n10)
-        for v in ("classic", "plantard"):
-            _, ms = timed_sec(lambda: mg.ntt(c32, d10, root10, variant=v), torch)
-            res["n1024_" + v] = {"ms": round(ms, 3), "batch": batch * n // n10,
-                                 "Gcoef_s": round(batch * n / (ms * 1e-3) / 1e9, 1),
-                                 "GB_s": round(8 * batch * n / (ms * 1e-3) / 1e9, 1)}
-            log("ntt n=1024 %s: %s" % (v, res["n1024_" + v]))
+        # the same coefficient count in 2^16 transforms of length 1024 and 2^14 of length 4096
+        for lg in (10, 12):
+            nl = 1 << lg
+            rl = next(w for w in (pow(g, (N - 1) // nl, N) for g in range(2, 100)) if pow(w, nl // 2, N) == N - 1)
+            dl = d.view(batch * n // nl, nl)
+            for v in ("classic", "plantard"):
+                _, ms = timed_sec(lambda: mg.ntt(c32, dl, rl, variant=v), torch)
+                res["n%d_%s" % (nl, v)] = {"ms": round(ms, 3), "batch": batch * n // nl,
+                                           "Gcoef_s": round(batch * n / (ms * 1e-3) / 1e9, 1),
+                                           "GB_s": round(8 * batch * n / (ms * 1e-3) / 1e9, 1)}
+                log("ntt n=%d %s: %s" % (nl, v, res["n%d_%s" % (nl, v)]))
         # the same shape over the 16-bit modulus N = 3329 (2^18 transforms of length 256)
         N16 = 3329
         c16 = mg.setup(N16, 16)

@@ -7,15 +7,12 @@
 // polynomials of n residues in [0, N) stored contiguously (natural order in
 // and out, in place).
 //
-// Lengths 2 to 4096, to 1024 for 64-bit words (k_nttw): one wavefront per
-// max(n, 256) coefficients, loaded from HBM straight into registers in
-// bit-reversed order and exchanged between radix-4 steps through a
-// conflict-free LDS layout.  64-bit words at lengths 2048 and 4096 (k_ntt):
-// one workgroup transforms one polynomial: coefficients are loaded into LDS in
-// bit-reversed order together with the compact twiddles, the log2(n) radix-2
-// Cooley-Tukey stages run two at a time as radix-4 steps in registers (a
-// barrier between steps), and the result is written back (scaled by n^{-1}
-// for the inverse).  The
+// Lengths 2 to 1024 (k_nttw): one wavefront per max(n, 256) coefficients,
+// loaded from HBM straight into registers in bit-reversed order and exchanged
+// between radix-4 steps through a conflict-free LDS layout.  Lengths 2048 and
+// 4096 (k_nttm): one workgroup of four wavefronts per polynomial, each taking
+// a quarter of the 256-position blocks through the same steps, then trading
+// through LDS so that the stages across blocks run in registers.  The
 // twiddle product is a product by a fixed operand:
 //   classic  -- Montgomery product with w^k R mod N;
 //   Plantard -- Plantard product with b = -w^k 2^(2w) mod N through the
@@ -154,103 +151,6 @@ __device__ __forceinline__ void butterfly(const R &red, typename R::E &u, typena
     }
 }
 
-// LDS: n coefficients, then n/2 twiddles.  Pairs of radix-2 stages run as one
-// radix-4 step in registers (4 loads, 4 butterflies, 4 stores per group,
-// one barrier per two stages); an odd stage count ends with a radix-2 step.
-// With VEC (16-byte aligned polynomials of at least 16 bytes) coefficients
-// move between HBM and LDS in 16-byte chunks; the bit-reversed LDS writes of
-// a chunk's lanes then fall on distinct words.
-template <int W, int V, bool FAST, bool LAZY>
-__global__ void __launch_bounds__(BLOCK)
-    k_ntt(KCtx c, void *__restrict__ data, uint32_t log2n, const TwL<W, V> *__restrict__ tw, KConst scale,
-          uint32_t do_scale, uint32_t vec)
-{
-    using R = Red<W, V>;
-    using El = typename R::E;
-    using T = TwL<W, V>;
-    constexpr int E = 16 / (int)sizeof(El);
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    const uint32_t n = 1u << log2n;
-    El *s = (El *)lds_raw;
-    T *ts = (T *)(lds_raw + ((n * sizeof(El) + 15) & ~(size_t)15));
-    const R red(c);
-    const El N = (El)c.N;
-    El *x = (El *)data + (uint64_t)blockIdx.x * n;
-    for (uint32_t i = threadIdx.x; i < n / 2; i += blockDim.x)
-        ts[i] = tw[i];
-    if (vec) {
-        for (uint32_t ci = threadIdx.x; ci < n / E; ci += blockDim.x) {
-            El v[E];
-            load_chunk<El, E, true>(x + ci * E, v);
-#pragma unroll
-            for (int e = 0; e < E; ++e)
-                s[__brev(ci * E + e) >> (32 - log2n)] = v[e];
-        }
-    } else {
-        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
-            s[__brev(i) >> (32 - log2n)] = x[i];
-    }
-    __syncthreads();
-    // at most six radix-4 steps (n <= 4096): unrolled, so lengths and shifts are constants
-    uint32_t done = 0;  // stages completed
-#pragma unroll
-    for (int st = 0; st < 6; ++st) {
-        const uint32_t lh = 2u * (uint32_t)st;
-        if (lh + 1 >= log2n)
-            break;
-        const uint32_t len = 1u << lh;
-        const uint32_t sh0 = log2n - 1 - lh, sh1 = log2n - 2 - lh;  // twiddle strides of the two stages
-        for (uint32_t g = threadIdx.x; g < n / 4; g += blockDim.x) {
-            const uint32_t j = g & (len - 1);
-            const uint32_t i0 = ((g >> lh) << (lh + 2)) + j;
-            El a0 = s[i0], a1 = s[i0 + len], a2 = s[i0 + 2 * len], a3 = s[i0 + 3 * len];
-            const T w0 = ts[j << sh0];
-            butterfly<R, V, FAST, LAZY>(red, a0, a1, w0, N);
-            butterfly<R, V, FAST, LAZY>(red, a2, a3, w0, N);
-            butterfly<R, V, FAST, LAZY>(red, a0, a2, ts[j << sh1], N);
-            butterfly<R, V, FAST, LAZY>(red, a1, a3, ts[(j + len) << sh1], N);
-            s[i0] = a0;
-            s[i0 + len] = a1;
-            s[i0 + 2 * len] = a2;
-            s[i0 + 3 * len] = a3;
-        }
-        __syncthreads();
-        done = lh + 2;
-    }
-    if (done < log2n) {  // one radix-2 stage left
-        const uint32_t lh = done;
-        const uint32_t len = 1u << lh;
-        for (uint32_t b = threadIdx.x; b < n / 2; b += blockDim.x) {
-            const uint32_t j = b & (len - 1);
-            const uint32_t i0 = ((b >> lh) << (lh + 1)) + j;
-            El u = s[i0], v = s[i0 + len];
-            butterfly<R, V, FAST, LAZY>(red, u, v, ts[j << (log2n - 1 - lh)], N);
-            s[i0] = u;
-            s[i0 + len] = v;
-        }
-        __syncthreads();
-    }
-    // the output value of a coefficient (scaled by n^{-1} for the inverse; LAZY: from [0, 4N) to [0, N))
-    auto outv = [&](El y) -> El {
-        if constexpr (LAZY)
-            return do_scale ? below<El>(lazy_mul(red, y, (El)scale.b), N) : below<El>(below<El>(y, (El)(2 * N)), N);
-        else
-            return do_scale ? tw_mul<R, V, FAST>(red, y, scale) : y;
-    };
-    if (vec) {
-        for (uint32_t ci = threadIdx.x; ci < n / E; ci += blockDim.x) {
-            El v[E];
-#pragma unroll
-            for (int e = 0; e < E; ++e)
-                v[e] = outv(s[ci * E + e]);
-            store_chunk<El, E, true>(x + ci * E, v);
-        }
-    } else {
-        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
-            x[i] = outv(s[i]);
-    }
-}
-
 // Butterfly by the unit twiddle (the first two stages of a bit-reversed
 // decimation-in-time transform multiply by 1 or by w^(n/4) only).  LAZY:
 // u, v < 2N give u + v < 4N and u - v + 2N in (0, 4N).
@@ -288,7 +188,93 @@ __device__ __forceinline__ void lds_put4(El *p, const El (&a)[4])
     }
 }
 
-// Lengths n = 2^L, 1 <= L <= 12: one wavefront per unit of max(n, 256)
+// The four radix-4 steps (stages 0..7, those below L) of NB blocks of 256
+// positions held by one wavefront, four positions per lane in each (lane maps
+// and LDS layout at k_nttw); block b goes through the 256 LDS words at
+// sb + 256 b, and the blocks' steps interleave.  tw9: the lane's twiddles of
+// stages 1..7 in the order t01, t10, t11, t12, t20, t21, t22, t30, t31, t32
+// (stage 0 and half of stage 1 multiply by 1).  On return a[b][k] holds
+// position lane + 64 k of block b.
+template <class R, int V, bool FAST, bool LAZY, int NB, int L, class T>
+__device__ __forceinline__ void block_steps(const R &red, typename R::E (&a)[NB][4], typename R::E *sb,
+                                            uint32_t lane, uint32_t base1, uint32_t base2, uint32_t base3,
+                                            const T (&tw9)[10], typename R::E N)
+{
+    using El = typename R::E;
+    constexpr bool H1 = L > 1, H2 = L > 2, H3 = L > 3, H4 = L > 4, H5 = L > 5, H6 = L > 6, H7 = L > 7;  // stage st exists
+    // step 0: stage 0 (unit twiddles), stage 1 (1 and w^(n/4))
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        butterfly1<El, FAST, LAZY>(a[b][0], a[b][1], N);
+        butterfly1<El, FAST, LAZY>(a[b][2], a[b][3], N);
+        if constexpr (H1) {
+            butterfly1<El, FAST, LAZY>(a[b][0], a[b][2], N);
+            butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], tw9[0], N);
+        }
+        lds_put4<El>(sb + 256 * b + 4 * lane, a[b]);
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const El *q = sb + 256 * b;
+        a[b][0] = q[base1];
+        a[b][1] = q[base1 + 128];
+        a[b][2] = q[base1 + 64];
+        a[b][3] = q[base1 + 192];
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if constexpr (H2) {
+            butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][1], tw9[1], N);
+            butterfly<R, V, FAST, LAZY>(red, a[b][2], a[b][3], tw9[1], N);
+        }
+        if constexpr (H3) {
+            butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][2], tw9[2], N);
+            butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], tw9[3], N);
+        }
+        lds_put4<El>(sb + 256 * b + 4 * lane, a[b]);
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            a[b][k] = sb[256 * b + base2 + 64 * k];
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if constexpr (H4) {
+            butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][1], tw9[4], N);
+            butterfly<R, V, FAST, LAZY>(red, a[b][2], a[b][3], tw9[4], N);
+        }
+        if constexpr (H5) {
+            butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][2], tw9[5], N);
+            butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], tw9[6], N);
+        }
+        lds_put4<El>(sb + 256 * b + 4 * lane, a[b]);
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            a[b][k] = sb[256 * b + base3 + 64 * k];
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if constexpr (H6) {
+            butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][1], tw9[7], N);
+            butterfly<R, V, FAST, LAZY>(red, a[b][2], a[b][3], tw9[7], N);
+        }
+        if constexpr (H7) {
+            butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][2], tw9[8], N);
+            butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], tw9[9], N);
+        }
+    }
+}
+
+// Lengths n = 2^L, 1 <= L <= 10: one wavefront per unit of max(n, 256)
 // consecutive coefficients, no workgroup barriers.
 //
 // A unit is one polynomial when n >= 256 and 256/n polynomials side by side
@@ -297,14 +283,13 @@ __device__ __forceinline__ void lds_put4(El *p, const El (&a)[4])
 // stage st pairs positions that differ in bit st, with the twiddle
 // w^(j n / 2^(st+1)) = tw[j << (L - 1 - st)] at position j mod 2^st.  Stages
 // L..7 do not exist when n < 256 and are skipped (the polynomials of a unit
-// never mix).  When n = 256 G, G = 2 to 16, the first eight stages act on G
+// never mix).  When n = 256 G, G = 2 or 4, the first eight stages act on G
 // separate blocks of 256 positions; block b holds the coefficients
 // x[brev(b) + G m], m = 0..255 (brev over log2 G bits), so the G values a
 // lane needs for one slot of all blocks are G consecutive words; after those
 // stages the remaining log2 G stages pair positions that differ only in the
 // block index, and a lane already holds every member of its groups: they run
-// in registers (G = 2^(L-8) up to 16; from G = 8 on the blocks take their
-// steps in turn through one LDS buffer and no unit is loaded ahead).
+// in registers.
 //
 // Within a block of 256, positions P split into four 2-bit fields F0..F3
 // (F_s = bits 2s, 2s+1); radix-4 step s runs stages 2s and 2s+1 on the groups
@@ -337,16 +322,11 @@ __global__ void __launch_bounds__(BLOCK)
     using R = Red<W, V>;
     using El = typename R::E;
     using T = TwL<W, V>;
-    static_assert(L >= 1 && L <= 12, "lengths 2 to 4096");
+    static_assert(L >= 1 && L <= 10, "lengths 2 to 1024");
     constexpr int G = L > 8 ? 1 << (L - 8) : 1;
     constexpr uint32_t UNIT = 256u * G;
-    constexpr bool PREFETCH = G <= 4;  // registers: the next unit's G x 4 coefficients
-    // LDS: one buffer per block when G <= 4 (their steps interleave); one per wave
-    // when G >= 8, the blocks taking their steps in turn (G buffers would not fit)
-    constexpr int NB = G <= 4 ? G : 1;
-    constexpr bool H1 = L > 1, H2 = L > 2, H3 = L > 3, H4 = L > 4, H5 = L > 5, H6 = L > 6, H7 = L > 7;  // stage st exists
     constexpr int WAVES = BLOCK / 64;
-    __shared__ __align__(16) El lds[WAVES][NB][256];
+    __shared__ __align__(16) El lds[WAVES][G][256];
     const R red(c);
     const El N = (El)c.N;
     const uint32_t lane = threadIdx.x & 63u;
@@ -358,27 +338,26 @@ __global__ void __launch_bounds__(BLOCK)
     const uint32_t base3 = f2 + 4 * f0 + 16 * f1;            // step-3 lane: F0 = f0, F1 = f1, F2 = f2
     const uint32_t j2 = f0 + 4 * f1;
     auto twi = [&](int st, uint32_t j) -> T { return tw[j << (L - 1 - st)]; };
-    T t01{};
-    if constexpr (H1)
-        t01 = twi(1, 1);
-    T t10{}, t11{}, t12{}, t20{}, t21{}, t22{}, t30{}, t31{}, t32{};
-    if constexpr (H2)
-        t10 = twi(2, f0);
-    if constexpr (H3) {
-        t11 = twi(3, f0);
-        t12 = twi(3, f0 + 4);
+    T tw9[10]{};  // t01, t10, t11, t12, t20, t21, t22, t30, t31, t32 (stages that exist)
+    if constexpr (L > 1)
+        tw9[0] = twi(1, 1);
+    if constexpr (L > 2)
+        tw9[1] = twi(2, f0);
+    if constexpr (L > 3) {
+        tw9[2] = twi(3, f0);
+        tw9[3] = twi(3, f0 + 4);
     }
-    if constexpr (H4)
-        t20 = twi(4, j2);
-    if constexpr (H5) {
-        t21 = twi(5, j2);
-        t22 = twi(5, j2 + 16);
+    if constexpr (L > 4)
+        tw9[4] = twi(4, j2);
+    if constexpr (L > 5) {
+        tw9[5] = twi(5, j2);
+        tw9[6] = twi(5, j2 + 16);
     }
-    if constexpr (H6)
-        t30 = twi(6, lane);
-    if constexpr (H7) {
-        t31 = twi(7, lane);
-        t32 = twi(7, lane + 64);
+    if constexpr (L > 6)
+        tw9[7] = twi(6, lane);
+    if constexpr (L > 7) {
+        tw9[8] = twi(7, lane);
+        tw9[9] = twi(7, lane + 64);
     }
     // stages across blocks (G > 1), at position j = lane + 64 k of the block: stage 8 uses
     // tw[j << (L - 9)], stage 9 (G = 4) tw[j] and tw[j + 256]
@@ -407,46 +386,6 @@ __global__ void __launch_bounds__(BLOCK)
             return do_scale ? below<El>(lazy_mul(red, y, (El)scale.b), N) : below<El>(below<El>(y, (El)(2 * N)), N);
         else
             return do_scale ? tw_mul<R, V, FAST>(red, y, scale) : y;
-    };
-    // the four radix-4 steps of one block through one LDS buffer (G >= 8)
-    auto block_steps = [&](El(&ab)[4], El *sb) {
-        butterfly1<El, FAST, LAZY>(ab[0], ab[1], N);
-        butterfly1<El, FAST, LAZY>(ab[2], ab[3], N);
-        butterfly1<El, FAST, LAZY>(ab[0], ab[2], N);
-        butterfly<R, V, FAST, LAZY>(red, ab[1], ab[3], t01, N);
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        lds_put4<El>(sb + 4 * lane, ab);
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        ab[0] = sb[base1];
-        ab[1] = sb[base1 + 128];
-        ab[2] = sb[base1 + 64];
-        ab[3] = sb[base1 + 192];
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        butterfly<R, V, FAST, LAZY>(red, ab[0], ab[1], t10, N);
-        butterfly<R, V, FAST, LAZY>(red, ab[2], ab[3], t10, N);
-        butterfly<R, V, FAST, LAZY>(red, ab[0], ab[2], t11, N);
-        butterfly<R, V, FAST, LAZY>(red, ab[1], ab[3], t12, N);
-        lds_put4<El>(sb + 4 * lane, ab);
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            ab[k] = sb[base2 + 64 * k];
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        butterfly<R, V, FAST, LAZY>(red, ab[0], ab[1], t20, N);
-        butterfly<R, V, FAST, LAZY>(red, ab[2], ab[3], t20, N);
-        butterfly<R, V, FAST, LAZY>(red, ab[0], ab[2], t21, N);
-        butterfly<R, V, FAST, LAZY>(red, ab[1], ab[3], t22, N);
-        lds_put4<El>(sb + 4 * lane, ab);
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            ab[k] = sb[base3 + 64 * k];
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        butterfly<R, V, FAST, LAZY>(red, ab[0], ab[1], t30, N);
-        butterfly<R, V, FAST, LAZY>(red, ab[2], ab[3], t30, N);
-        butterfly<R, V, FAST, LAZY>(red, ab[0], ab[2], t31, N);
-        butterfly<R, V, FAST, LAZY>(red, ab[1], ab[3], t32, N);
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
     };
     const uint64_t stride = (uint64_t)gridDim.x * WAVES;
     uint64_t t = (uint64_t)blockIdx.x * WAVES + wv;
@@ -483,95 +422,18 @@ __global__ void __launch_bounds__(BLOCK)
             }
         }
     };
-    if (PREFETCH && t < units)
+    if (t < units)
         fetch(t);
     for (; t < units; t += stride) {
-        if (!PREFETCH)
-            fetch(t);
         El a[G][4];
 #pragma unroll
         for (int b = 0; b < G; ++b)
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 a[b][k] = nx[b][k];
-        if (PREFETCH && t + stride < units)
+        if (t + stride < units)
             fetch(t + stride);
-        if constexpr (G >= 8) {
-#pragma unroll
-            for (int b = 0; b < G; ++b)
-                block_steps(a[b], lds[wv][0]);
-        } else {
-            // step 0: stage 0 (unit twiddles), stage 1 (1 and w^(n/4))
-#pragma unroll
-            for (int b = 0; b < G; ++b) {
-                butterfly1<El, FAST, LAZY>(a[b][0], a[b][1], N);
-                butterfly1<El, FAST, LAZY>(a[b][2], a[b][3], N);
-                if constexpr (H1) {
-                    butterfly1<El, FAST, LAZY>(a[b][0], a[b][2], N);
-                    butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t01, N);
-                }
-                lds_put4<El>(&lds[wv][b][4 * lane], a[b]);
-            }
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
-#pragma unroll
-            for (int b = 0; b < G; ++b) {
-                const El *s = lds[wv][b];
-                a[b][0] = s[base1];
-                a[b][1] = s[base1 + 128];
-                a[b][2] = s[base1 + 64];
-                a[b][3] = s[base1 + 192];
-            }
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
-#pragma unroll
-            for (int b = 0; b < G; ++b) {
-                if constexpr (H2) {
-                    butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][1], t10, N);
-                    butterfly<R, V, FAST, LAZY>(red, a[b][2], a[b][3], t10, N);
-                }
-                if constexpr (H3) {
-                    butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][2], t11, N);
-                    butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t12, N);
-                }
-                lds_put4<El>(&lds[wv][b][4 * lane], a[b]);
-            }
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
-#pragma unroll
-            for (int b = 0; b < G; ++b)
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    a[b][k] = lds[wv][b][base2 + 64 * k];
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
-#pragma unroll
-            for (int b = 0; b < G; ++b) {
-                if constexpr (H4) {
-                    butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][1], t20, N);
-                    butterfly<R, V, FAST, LAZY>(red, a[b][2], a[b][3], t20, N);
-                }
-                if constexpr (H5) {
-                    butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][2], t21, N);
-                    butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t22, N);
-                }
-                lds_put4<El>(&lds[wv][b][4 * lane], a[b]);
-            }
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
-#pragma unroll
-            for (int b = 0; b < G; ++b)
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    a[b][k] = lds[wv][b][base3 + 64 * k];
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
-#pragma unroll
-            for (int b = 0; b < G; ++b) {
-                if constexpr (H6) {
-                    butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][1], t30, N);
-                    butterfly<R, V, FAST, LAZY>(red, a[b][2], a[b][3], t30, N);
-                }
-                if constexpr (H7) {
-                    butterfly<R, V, FAST, LAZY>(red, a[b][0], a[b][2], t31, N);
-                    butterfly<R, V, FAST, LAZY>(red, a[b][1], a[b][3], t32, N);
-                }
-            }
-        }
+        block_steps<R, V, FAST, LAZY, G, L>(red, a, &lds[wv][0][0], lane, base1, base2, base3, tw9, N);
         // the stages across blocks: position lane + 64 k of every block, in registers
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -582,24 +444,6 @@ __global__ void __launch_bounds__(BLOCK)
                 butterfly<R, V, FAST, LAZY>(red, a[2][k], a[3][k], u0[k], N);
                 butterfly<R, V, FAST, LAZY>(red, a[0][k], a[2][k], u1[k], N);
                 butterfly<R, V, FAST, LAZY>(red, a[1][k], a[3][k], u2[k], N);
-            } else if constexpr (G >= 8) {
-                // stage 8 + h pairs blocks b and b + 2^h at position j + 256 (b mod 2^h) mod 2^(8 + h);
-                // its 2^h twiddles per k are read from the table (cache-resident) for every unit:
-                // 4 (2^(log2 G) - 1) of them do not fit in registers.  z hides that the
-                // addresses do not change from unit to unit, so they are not kept in registers.
-                uint32_t z = 0;
-                asm volatile("" : "+v"(z));
-                const uint32_t j = lane + 64u * (uint32_t)k + z;
-#pragma unroll
-                for (int h = 0; (1 << h) < G; ++h) {
-#pragma unroll
-                    for (int b = 0; b < G; ++b) {
-                        if (b & (1 << h))
-                            continue;
-                        const uint32_t jj = j + 256u * (uint32_t)(b & ((1 << h) - 1));
-                        butterfly<R, V, FAST, LAZY>(red, a[b][k], a[b + (1 << h)][k], tw[jj << (L - 9 - h)], N);
-                    }
-                }
             }
         }
         El *y = (El *)data + t * UNIT + lane;
@@ -615,6 +459,120 @@ __global__ void __launch_bounds__(BLOCK)
                 if (t * UNIT + lane + 64 * k < nelem)
                     y[64 * k] = outv(a[0][k]);
         }
+    }
+}
+
+// Lengths 2048 and 4096 (L = 11, 12): one workgroup of four wavefronts per
+// polynomial, workgroups looping over the batch.
+//
+// Positions, blocks and the radix-4 steps within a block are those of k_nttw:
+// G = 2^(L-8) blocks of 256 positions, block b holding x[brev(b) + G m].  Wave
+// v takes the G/4 blocks b with brev(b) = v G/4 + e, e < G/4, so for each slot
+// a lane loads G/4 consecutive words, and runs stages 0..7 on them, block e
+// through the 256 LDS words at 256 (v G/4 + e).  The waves then trade through
+// those same n words: each writes position lane + 64 k of its blocks in place,
+// and after a barrier lane l of wave v reads position 64 v + l of every block,
+// so the L - 8 stages across blocks run in its registers, with the G - 1
+// twiddles they take at that position held for the whole run.  Results leave
+// as 64 consecutive words per store.  A second barrier, before the next
+// polynomial's first LDS write, waits for every wave's reads.
+template <int W, int V, bool FAST, bool LAZY, int L>
+__global__ void __launch_bounds__(BLOCK)
+    k_nttm(KCtx c, void *__restrict__ data, uint64_t batch, const TwL<W, V> *__restrict__ tw, KConst scale,
+           uint32_t do_scale, uint32_t vec)
+{
+    using R = Red<W, V>;
+    using El = typename R::E;
+    using T = TwL<W, V>;
+    static_assert(L == 11 || L == 12, "lengths 2048 and 4096");
+    static_assert(BLOCK == 256, "four wavefronts per workgroup");
+    constexpr int LG = L - 8, G = 1 << LG, GW = G / 4;
+    constexpr uint32_t n = 1u << L;
+    __shared__ __align__(16) El sx[n];
+    const R red(c);
+    const El N = (El)c.N;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    auto br2 = [](uint32_t f) { return ((f & 1u) << 1) | (f >> 1); };
+    const uint32_t f0 = lane & 3u, f1 = (lane >> 2) & 3u, f2 = lane >> 4;
+    const uint32_t base1 = f0 + 4 * br2(f1) + 16 * br2(f2);
+    const uint32_t base2 = f1 + 4 * f0 + 16 * f2;
+    const uint32_t base3 = f2 + 4 * f0 + 16 * f1;
+    const uint32_t j2 = f0 + 4 * f1;
+    auto twi = [&](int st, uint32_t j) -> T { return tw[j << (L - 1 - st)]; };
+    const T tw9[10] = {twi(1, 1), twi(2, f0),   twi(3, f0),   twi(3, f0 + 4), twi(4, j2),
+                       twi(5, j2), twi(5, j2 + 16), twi(6, lane), twi(7, lane), twi(7, lane + 64)};
+    // stage 8 + h pairs blocks b and b + 2^h at position P = 64 v + l: twiddle
+    // tw[(P + 256 r) << (L - 9 - h)], r = b mod 2^h, kept at cx[2^h - 1 + r]
+    const uint32_t P = 64u * wv + lane;
+    T cx[G - 1];
+#pragma unroll
+    for (int h = 0; h < LG; ++h)
+#pragma unroll
+        for (int r = 0; r < (1 << h); ++r)
+            cx[(1 << h) - 1 + r] = tw[(P + 256u * (uint32_t)r) << (L - 9 - h)];
+    auto outv = [&](El y) -> El {
+        if constexpr (LAZY)
+            return do_scale ? below<El>(lazy_mul(red, y, (El)scale.b), N) : below<El>(below<El>(y, (El)(2 * N)), N);
+        else
+            return do_scale ? tw_mul<R, V, FAST>(red, y, scale) : y;
+    };
+    El nx[GW][4];
+    auto fetch = [&](uint64_t p) {
+        // block brev(v G/4 + e), slot k: x[v G/4 + e + G (lane + 64 brev2(k))]
+        const El *x = (const El *)data + p * n + (uint64_t)(G * lane + GW * wv);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const El *q = x + 64 * G * br2((uint32_t)k);
+            El v[GW];
+            if (vec) {
+                load_chunk<El, GW, false>(q, v);
+            } else {
+#pragma unroll
+                for (int e = 0; e < GW; ++e)
+                    v[e] = q[e];
+            }
+#pragma unroll
+            for (int e = 0; e < GW; ++e)
+                nx[e][k] = v[e];
+        }
+    };
+    El *sw = sx + 256u * GW * wv;  // this wave's blocks
+    uint64_t p = blockIdx.x;
+    if (p < batch)
+        fetch(p);
+    for (; p < batch; p += gridDim.x) {  // uniform over the workgroup: the barriers are safe
+        El a[GW][4];
+#pragma unroll
+        for (int e = 0; e < GW; ++e)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                a[e][k] = nx[e][k];
+        if (p + gridDim.x < batch)
+            fetch(p + gridDim.x);
+        __syncthreads();  // the previous polynomial's exchange reads are done
+        block_steps<R, V, FAST, LAZY, GW, L>(red, a, sw, lane, base1, base2, base3, tw9, N);
+#pragma unroll
+        for (int e = 0; e < GW; ++e)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                sw[256 * e + 64 * k + lane] = a[e][k];
+        __syncthreads();
+        El z[G];
+#pragma unroll
+        for (int b = 0; b < G; ++b)
+            z[b] = sx[256u * (__brev((uint32_t)b) >> (32 - LG)) + P];
+#pragma unroll
+        for (int h = 0; h < LG; ++h)
+#pragma unroll
+            for (int b = 0; b < G; ++b)
+                if (!(b & (1 << h)))
+                    butterfly<R, V, FAST, LAZY>(red, z[b], z[b + (1 << h)], cx[(1 << h) - 1 + (b & ((1 << h) - 1))],
+                                                N);
+        El *y = (El *)data + p * n + P;
+#pragma unroll
+        for (int b = 0; b < G; ++b)
+            y[256 * b] = outv(z[b]);
     }
 }
 
@@ -725,17 +683,29 @@ static mont_status_t twiddles(const mont_ctx_t &c, int variant, uint64_t root, u
     return MONT_OK;
 }
 
+// Workgroups of kernel K that one CU holds at once (registers and LDS), asked once.
+template <auto K>
+static unsigned resident_per_cu()
+{
+    static const unsigned v = [] {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void *>(K), BLOCK, 0) !=
+                hipSuccess ||
+            b < 1) {
+            (void)hipGetLastError();
+            b = 1;
+        }
+        return (unsigned)b;
+    }();
+    return v;
+}
+
 template <int W>
 static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, uint32_t log2n, const TwEntry &t,
                          int inverse, hipStream_t s)
 {
     using El = typename Red<W, CLASSIC>::E;
     const uint32_t n = 1u << log2n;
-    const unsigned block = (unsigned)std::min<uint32_t>(BLOCK, std::max<uint32_t>(n / 4, 64));
-    const size_t tsz = variant == CLASSIC || W < 64 ? 8 : 16;
-    const size_t lds = (((size_t)n * sizeof(El) + 15) & ~(size_t)15) + (size_t)(n / 2) * tsz;
-    // 16-byte chunks when every polynomial starts on a 16-byte boundary
-    const uint32_t vec = ((uintptr_t)data % 16 == 0 && ((size_t)n * sizeof(El)) % 16 == 0) ? 1u : 0u;
     const uint32_t inv = (uint32_t)inverse;
     // FAST needs N < 2^(w-1); classic twiddles at w >= 32 also the ladder's smaller-modulus bound;
     // LAZY (classic twiddles) needs 4N <= 2^w, with operands below 2^63 at w = 64
@@ -743,26 +713,22 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
     const bool fast = variant == CLASSIC && W != 16 ? fast_ladder<W>(k.N) : small;
     const bool lazy = variant == CLASSIC && ((W == 16 && k.N < (1ull << 14)) || (W == 32 && k.N < (1ull << 30)) ||
                                              (W == 64 && k.N < (1ull << 61)));
-    const dim3 grid((unsigned)batch), blk(block);
     const auto *twc = (const TwL<W, CLASSIC> *)t.dev;
     const auto *twp = (const TwL<W, PLANTARD> *)t.dev;
-    // 64-bit words at lengths above 1024 would not fit the registers (the
-    // compiler spills): they take the workgroup kernel
-    if (log2n <= (W == 64 ? 10u : 12u)) {
+    const dim3 b(BLOCK);
+    if (log2n <= 10) {
         // one wavefront per unit of max(n, 256) coefficients, waves looping over the units
         constexpr uint64_t WAVES = BLOCK / 64;
         const uint64_t nelem = (uint64_t)batch << log2n;
         const uint64_t units = log2n >= 8 ? (uint64_t)batch : (nelem + 255) / 256;
         const uint64_t blocks = std::min<uint64_t>((units + WAVES - 1) / WAVES, (uint64_t)device_cus() * NTTW_BPC);
-        const dim3 g((unsigned)blocks), b(BLOCK);
+        const dim3 g((unsigned)blocks);
         // chunk loads (n / 256 words per lane and slot) when the polynomials are aligned to them
         const size_t chunk = std::min<size_t>(16, std::max<size_t>(1, (size_t)n / 256) * sizeof(El));
         const uint32_t cv = (uintptr_t)data % chunk == 0 ? 1u : 0u;
         auto go = [&](auto lc) {
             constexpr int LL = decltype(lc)::value;
-            if constexpr (W == 64 && LL > 10)
-                return;
-            else if (lazy)
+            if (lazy)
                 hipLaunchKernelGGL((k_nttw<W, CLASSIC, true, true, LL>), g, b, 0, s, k, data, units, nelem, twc,
                                    t.scale, inv, cv);
             else if (variant == CLASSIC && fast)
@@ -788,28 +754,38 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
         case 7: go(std::integral_constant<int, 7>{}); break;
         case 8: go(std::integral_constant<int, 8>{}); break;
         case 9: go(std::integral_constant<int, 9>{}); break;
-        case 10: go(std::integral_constant<int, 10>{}); break;
-        case 11: go(std::integral_constant<int, 11>{}); break;
-        default: go(std::integral_constant<int, 12>{}); break;
+        default: go(std::integral_constant<int, 10>{}); break;
         }
         return hipGetLastError();
     }
-    if (lazy) {
-        hipLaunchKernelGGL((k_ntt<W, CLASSIC, true, true>), grid, blk, lds, s, k, data, log2n, twc, t.scale, inv, vec);
-        return hipGetLastError();
-    }
-    if (variant == CLASSIC && fast)
-        hipLaunchKernelGGL((k_ntt<W, CLASSIC, true, false>), grid, blk, lds, s, k, data, log2n, twc, t.scale, inv,
-                           vec);
-    else if (variant == CLASSIC)
-        hipLaunchKernelGGL((k_ntt<W, CLASSIC, false, false>), grid, blk, lds, s, k, data, log2n, twc, t.scale, inv,
-                           vec);
-    else if (fast)
-        hipLaunchKernelGGL((k_ntt<W, PLANTARD, true, false>), grid, blk, lds, s, k, data, log2n, twp, t.scale, inv,
-                           vec);
+    // one workgroup per polynomial, workgroups looping over the batch: as many as the CUs hold at once
+    // (registers decide: 64-bit words fit two per CU, narrower words four or more)
+    // chunk loads (n / 1024 words per lane and slot) when the polynomials are aligned to them
+    const size_t chunk = std::min<size_t>(16, (size_t)n / 1024 * sizeof(El));
+    const uint32_t cv = (uintptr_t)data % chunk == 0 ? 1u : 0u;
+    const uint64_t nb = batch;
+    auto grid = [&](unsigned per_cu) { return dim3((unsigned)std::min<uint64_t>(nb, (uint64_t)device_cus() * per_cu)); };
+#define MONT_NTTM(VV, F, Z, TWP)                                                                                   \
+    hipLaunchKernelGGL((k_nttm<W, VV, F, Z, LL>), grid(resident_per_cu<k_nttm<W, VV, F, Z, LL>>()), b, 0, s, k,  \
+                       data, nb, TWP, t.scale, inv, cv)
+    auto go = [&](auto lc) {
+        constexpr int LL = decltype(lc)::value;
+        if (lazy)
+            MONT_NTTM(CLASSIC, true, true, twc);
+        else if (variant == CLASSIC && fast)
+            MONT_NTTM(CLASSIC, true, false, twc);
+        else if (variant == CLASSIC)
+            MONT_NTTM(CLASSIC, false, false, twc);
+        else if (fast)
+            MONT_NTTM(PLANTARD, true, false, twp);
+        else
+            MONT_NTTM(PLANTARD, false, false, twp);
+    };
+#undef MONT_NTTM
+    if (log2n == 11)
+        go(std::integral_constant<int, 11>{});
     else
-        hipLaunchKernelGGL((k_ntt<W, PLANTARD, false, false>), grid, blk, lds, s, k, data, log2n, twp, t.scale, inv,
-                           vec);
+        go(std::integral_constant<int, 12>{});
     return hipGetLastError();
 }
 

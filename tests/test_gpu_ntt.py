@@ -33,13 +33,13 @@ CASES = [
     (16, 12289, [1, 3, 4, 8, 9, 10, 12]),               # below 2^14: lazy butterflies (so is 3329)
     (16, 3329, [2, 5, 8]),
     (16, 36097, [3, 6, 8]),                      # above 2^15: wrap-checked modular add/subtract (both twiddle forms)
-    (16, 40961, [4, 7, 8, 9, 10, 12]),                     # above 2^16/phi: classic only
+    (16, 40961, [4, 7, 8, 9, 10, 11, 12]),                 # above 2^16/phi: classic only
     (32, 8380417, [1, 4, 6, 7, 8, 9, 10, 12]),
-    (32, 2013265921, [5, 6, 8, 9, 10, 11]),
-    (32, 3221225473, [4, 5, 7, 8, 9, 10]),                # above 2^31: the general classic product
-    (64, prime_1_mod(62, 12, 1), [2, 4, 6, 8, 9, 10, 12]),
-    (64, prime_1_mod(60, 12, 1), [3, 5, 7, 8, 9, 10]),    # below 2^61: lazy butterflies (8380417 takes them at w = 32)
-    (64, GOLDILOCKS, [3, 4, 6, 8, 9, 10]),
+    (32, 2013265921, [5, 6, 8, 9, 10, 11, 12]),
+    (32, 3221225473, [4, 5, 7, 8, 9, 10, 11, 12]),        # above 2^31: the general classic product
+    (64, prime_1_mod(62, 12, 1), [2, 4, 6, 8, 9, 10, 11, 12]),
+    (64, prime_1_mod(60, 12, 1), [3, 5, 7, 8, 9, 10, 11, 12]),  # below 2^61: lazy butterflies (8380417 takes them at w = 32)
+    (64, GOLDILOCKS, [3, 4, 6, 8, 9, 10, 11, 12]),
 ]
 DT = {16: np.uint16, 32: np.uint32, 64: np.uint64}
 
@@ -86,7 +86,7 @@ def test_ntt_unaligned_rows(w, N):
     """Rows that do not start on a 16-byte boundary take the element-wise path."""
     c = mg.setup(N, w)
     g = inp.rng(93, 500 + w)
-    for n, batch in ((16, 7), (64, 5), (256, 6), (512, 3), (1024, 3)):
+    for n, batch in ((16, 7), (64, 5), (256, 6), (512, 3), (1024, 3), (2048, 3), (4096, 2)):
         wr = root(N, n)
         x = g.integers(0, N, size=(batch, n), dtype=np.uint64).astype(DT[w])
         want = np.stack([orc.dft(w, N, x[i], wr) for i in range(batch)])
@@ -103,15 +103,16 @@ def test_ntt_unaligned_rows(w, N):
 @pytest.mark.parametrize("w,N", [(16, 3329), (16, 12289), (16, 40961), (32, 8380417), (32, 3221225473),
                                  (64, prime_1_mod(60, 12, 1)), (64, GOLDILOCKS)])
 def test_ntt_many_per_wave(w, N):
-    """Batches of lengths 2 to 4096 (to 1024 at w = 64) larger than the resident
-    waves (each wave takes several units of max(n, 256) coefficients, up to
-    1024 with the next one's loads in flight; below 256 the last unit is
-    partial): 40 seeded rows and the last against the DFT, the whole batch
-    through the round trip."""
+    """Batches of lengths 2 to 4096 larger than the resident waves or
+    workgroups (up to 1024 each wave takes several units of max(n, 256)
+    coefficients, with the next one's loads in flight, and below 256 the last
+    unit is partial; at 2048 and 4096 each workgroup of four waves takes
+    several polynomials): 40 seeded rows and the last against the DFT, the
+    whole batch through the round trip."""
     c = mg.setup(N, w)
     g = inp.rng(93, 700 + w + N % 89)
     for n in (2, 8, 16, 64, 128, 256, 512, 1024, 2048, 4096):
-        if (N - 1) % n or (n > 1024 and w == 64):
+        if (N - 1) % n:
             continue
         batch = (3 * 8192 + 5) * 256 // n + (3 if n < 256 else 0) if n <= 1024 else 2 * 8192 + 5
         wr = root(N, n)
