@@ -115,6 +115,15 @@ struct TwL<64, PLANTARD> {
 // subtraction; then u + t and u - t + 2N both lie in [0, 4N) with no further
 // correction (the lazy butterfly of Harvey's NTT).  Results are reduced to
 // [0, N) once, when they are written out.
+//
+// LAZY = 2 (the same products, for moduli far below the word): u is not
+// reduced at all.  With t < 2N, u + t and u - t + 2N lie in (0, B + 2N) when
+// u lies in [0, B), so each stage raises the bound by 2N: inputs below N,
+// below 3N after stage 0 (no products), 5N after stage 1 (its products see
+// operands below 3N) and (2L + 1) N after L >= 2 stages.  Taken when that
+// final bound fits the word (and stays below 2^63 at w = 64, the product's
+// operand limit); the product then still ends below 2N (a b < R N), and the
+// results are reduced by one product with 1 or n^{-1} in Montgomery form.
 template <class R>
 __device__ __forceinline__ typename R::E lazy_mul(const R &red, typename R::E a, typename R::E b)
 {
@@ -133,14 +142,14 @@ __device__ __forceinline__ El below(El x, El m)  // x < 2m  ->  x mod m
     return d < x ? d : x;
 }
 
-template <class R, int V, bool FAST, bool LAZY, class T>
+template <class R, int V, bool FAST, int LAZY, class T>
 __device__ __forceinline__ void butterfly(const R &red, typename R::E &u, typename R::E &v, const T &w,
                                           typename R::E N)
 {
     using El = typename R::E;
     if constexpr (LAZY) {
         const El t = lazy_mul(red, v, (El)w.get().b);
-        const El x = below<El>(u, (El)(2 * N));
+        const El x = LAZY == 2 ? u : below<El>(u, (El)(2 * N));
         u = (El)(x + t);
         v = (El)((El)(x + 2 * N) - t);
     } else {
@@ -151,13 +160,13 @@ __device__ __forceinline__ void butterfly(const R &red, typename R::E &u, typena
     }
 }
 
-// Butterfly by the unit twiddle (the first two stages of a bit-reversed
-// decimation-in-time transform multiply by 1 or by w^(n/4) only).  LAZY:
-// u, v < 2N give u + v < 4N and u - v + 2N in (0, 4N).
 // Workgroups per CU for the one-wave-per-polynomial kernel (its waves loop over the batch).
 constexpr int NTTW_BPC = 8;
 
-template <class El, bool FAST, bool LAZY>
+// Butterfly by the unit twiddle (the first two stages of a bit-reversed
+// decimation-in-time transform multiply by 1 or by w^(n/4) only).  LAZY:
+// u, v < 2N give u + v < 4N and u - v + 2N in (0, 4N).
+template <class El, bool FAST, int LAZY>
 __device__ __forceinline__ void butterfly1(El &u, El &v, El N)
 {
     const El x = u;
@@ -195,7 +204,7 @@ __device__ __forceinline__ void lds_put4(El *p, const El (&a)[4])
 // stages 1..7 in the order t01, t10, t11, t12, t20, t21, t22, t30, t31, t32
 // (stage 0 and half of stage 1 multiply by 1).  On return a[b][k] holds
 // position lane + 64 k of block b.
-template <class R, int V, bool FAST, bool LAZY, int NB, int L, class T>
+template <class R, int V, bool FAST, int LAZY, int NB, int L, class T>
 __device__ __forceinline__ void block_steps(const R &red, typename R::E (&a)[NB][4], typename R::E *sb,
                                             uint32_t lane, uint32_t base1, uint32_t base2, uint32_t base3,
                                             const T (&tw9)[10], typename R::E N)
@@ -314,7 +323,7 @@ __device__ __forceinline__ void block_steps(const R &red, typename R::E (&a)[NB]
 // twiddles are the same for every unit and stay in registers; waves loop over
 // units (the next one's loads in flight).  `nelem` (the batch's coefficient
 // count) bounds the last unit when n < 256.
-template <int W, int V, bool FAST, bool LAZY, int L>
+template <int W, int V, bool FAST, int LAZY, int L>
 __global__ void __launch_bounds__(BLOCK)
     k_nttw(KCtx c, void *__restrict__ data, uint64_t units, uint64_t nelem, const TwL<W, V> *__restrict__ tw,
            KConst scale, uint32_t do_scale, uint32_t vec)
@@ -382,7 +391,9 @@ __global__ void __launch_bounds__(BLOCK)
         off[k] = (P - p) + (__brev(p) >> (32 - L));
     }
     auto outv = [&](El y) -> El {
-        if constexpr (LAZY)
+        if constexpr (LAZY == 2)  // scale: 1 or n^{-1}, times R mod N
+            return below<El>(lazy_mul(red, y, (El)scale.b), N);
+        else if constexpr (LAZY)
             return do_scale ? below<El>(lazy_mul(red, y, (El)scale.b), N) : below<El>(below<El>(y, (El)(2 * N)), N);
         else
             return do_scale ? tw_mul<R, V, FAST>(red, y, scale) : y;
@@ -476,7 +487,7 @@ __global__ void __launch_bounds__(BLOCK)
 // twiddles they take at that position held for the whole run.  Results leave
 // as 64 consecutive words per store.  A second barrier, before the next
 // polynomial's first LDS write, waits for every wave's reads.
-template <int W, int V, bool FAST, bool LAZY, int L>
+template <int W, int V, bool FAST, int LAZY, int L>
 __global__ void __launch_bounds__(BLOCK)
     k_nttm(KCtx c, void *__restrict__ data, uint64_t batch, const TwL<W, V> *__restrict__ tw, KConst scale,
            uint32_t do_scale, uint32_t vec)
@@ -512,7 +523,9 @@ __global__ void __launch_bounds__(BLOCK)
         for (int r = 0; r < (1 << h); ++r)
             cx[(1 << h) - 1 + r] = tw[(P + 256u * (uint32_t)r) << (L - 9 - h)];
     auto outv = [&](El y) -> El {
-        if constexpr (LAZY)
+        if constexpr (LAZY == 2)  // scale: 1 or n^{-1}, times R mod N
+            return below<El>(lazy_mul(red, y, (El)scale.b), N);
+        else if constexpr (LAZY)
             return do_scale ? below<El>(lazy_mul(red, y, (El)scale.b), N) : below<El>(below<El>(y, (El)(2 * N)), N);
         else
             return do_scale ? tw_mul<R, V, FAST>(red, y, scale) : y;
@@ -628,7 +641,8 @@ struct TwKey {
 
 struct TwEntry {
     void *dev = nullptr;  // n/2 compact twiddles (TwL of the width and variant)
-    KConst scale{};
+    KConst scale{};       // the product by n^{-1}
+    KConst one{};         // the product by 1
 };
 
 static std::mutex g_tw_mu;
@@ -658,6 +672,7 @@ static mont_status_t twiddles(const mont_ctx_t &c, int variant, uint64_t root, u
     // n^{-1} mod N: N odd, so (N + 1)/2 is 2^{-1}
     const uint64_t half = (uint64_t)(((u128)c.N + 1) / 2);
     e.scale = twiddle_const(c, variant, powmod(half, log2n, c.N));
+    e.one = twiddle_const(c, variant, 1);
     // compact device form: b (classic), b N^{-1} mod 2^(2w) (Plantard, w <= 32), its two words (w = 64)
     const bool two = variant != CLASSIC && c.w == 64;
     std::vector<uint64_t> hc;
@@ -713,6 +728,10 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
     const bool fast = variant == CLASSIC && W != 16 ? fast_ladder<W>(k.N) : small;
     const bool lazy = variant == CLASSIC && ((W == 16 && k.N < (1ull << 14)) || (W == 32 && k.N < (1ull << 30)) ||
                                              (W == 64 && k.N < (1ull << 61)));
+    // no reduction between stages when the final bound (2 log2n + 1) N fits the word (below 2^63 at w = 64)
+    const u128 bound2 = (u128)(2 * log2n + 1) * k.N;
+    const bool lazy2 = lazy && bound2 <= (W == 64 ? (u128)1 << 63 : (u128)1 << W);
+    const KConst sc2 = inverse ? t.scale : t.one;  // the output product of the lazy2 form
     const auto *twc = (const TwL<W, CLASSIC> *)t.dev;
     const auto *twp = (const TwL<W, PLANTARD> *)t.dev;
     const dim3 b(BLOCK);
@@ -728,20 +747,23 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
         const uint32_t cv = (uintptr_t)data % chunk == 0 ? 1u : 0u;
         auto go = [&](auto lc) {
             constexpr int LL = decltype(lc)::value;
-            if (lazy)
-                hipLaunchKernelGGL((k_nttw<W, CLASSIC, true, true, LL>), g, b, 0, s, k, data, units, nelem, twc,
+            if (lazy2)
+                hipLaunchKernelGGL((k_nttw<W, CLASSIC, true, 2, LL>), g, b, 0, s, k, data, units, nelem, twc, sc2,
+                                   inv, cv);
+            else if (lazy)
+                hipLaunchKernelGGL((k_nttw<W, CLASSIC, true, 1, LL>), g, b, 0, s, k, data, units, nelem, twc,
                                    t.scale, inv, cv);
             else if (variant == CLASSIC && fast)
-                hipLaunchKernelGGL((k_nttw<W, CLASSIC, true, false, LL>), g, b, 0, s, k, data, units, nelem, twc,
+                hipLaunchKernelGGL((k_nttw<W, CLASSIC, true, 0, LL>), g, b, 0, s, k, data, units, nelem, twc,
                                    t.scale, inv, cv);
             else if (variant == CLASSIC)
-                hipLaunchKernelGGL((k_nttw<W, CLASSIC, false, false, LL>), g, b, 0, s, k, data, units, nelem, twc,
+                hipLaunchKernelGGL((k_nttw<W, CLASSIC, false, 0, LL>), g, b, 0, s, k, data, units, nelem, twc,
                                    t.scale, inv, cv);
             else if (fast)
-                hipLaunchKernelGGL((k_nttw<W, PLANTARD, true, false, LL>), g, b, 0, s, k, data, units, nelem, twp,
+                hipLaunchKernelGGL((k_nttw<W, PLANTARD, true, 0, LL>), g, b, 0, s, k, data, units, nelem, twp,
                                    t.scale, inv, cv);
             else
-                hipLaunchKernelGGL((k_nttw<W, PLANTARD, false, false, LL>), g, b, 0, s, k, data, units, nelem, twp,
+                hipLaunchKernelGGL((k_nttw<W, PLANTARD, false, 0, LL>), g, b, 0, s, k, data, units, nelem, twp,
                                    t.scale, inv, cv);
         };
         switch (log2n) {
@@ -765,21 +787,23 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
     const uint32_t cv = (uintptr_t)data % chunk == 0 ? 1u : 0u;
     const uint64_t nb = batch;
     auto grid = [&](unsigned per_cu) { return dim3((unsigned)std::min<uint64_t>(nb, (uint64_t)device_cus() * per_cu)); };
-#define MONT_NTTM(VV, F, Z, TWP)                                                                                   \
+#define MONT_NTTM(VV, F, Z, TWP, SC)                                                                               \
     hipLaunchKernelGGL((k_nttm<W, VV, F, Z, LL>), grid(resident_per_cu<k_nttm<W, VV, F, Z, LL>>()), b, 0, s, k,  \
-                       data, nb, TWP, t.scale, inv, cv)
+                       data, nb, TWP, SC, inv, cv)
     auto go = [&](auto lc) {
         constexpr int LL = decltype(lc)::value;
-        if (lazy)
-            MONT_NTTM(CLASSIC, true, true, twc);
+        if (lazy2)
+            MONT_NTTM(CLASSIC, true, 2, twc, sc2);
+        else if (lazy)
+            MONT_NTTM(CLASSIC, true, 1, twc, t.scale);
         else if (variant == CLASSIC && fast)
-            MONT_NTTM(CLASSIC, true, false, twc);
+            MONT_NTTM(CLASSIC, true, 0, twc, t.scale);
         else if (variant == CLASSIC)
-            MONT_NTTM(CLASSIC, false, false, twc);
+            MONT_NTTM(CLASSIC, false, 0, twc, t.scale);
         else if (fast)
-            MONT_NTTM(PLANTARD, true, false, twp);
+            MONT_NTTM(PLANTARD, true, 0, twp, t.scale);
         else
-            MONT_NTTM(PLANTARD, false, false, twp);
+            MONT_NTTM(PLANTARD, false, 0, twp, t.scale);
     };
 #undef MONT_NTTM
     if (log2n == 11)
