@@ -124,6 +124,17 @@ struct TwL<64, PLANTARD> {
 // final bound fits the word (and stays below 2^63 at w = 64, the product's
 // operand limit); the product then still ends below 2N (a b < R N), and the
 // results are reduced by one product with 1 or n^{-1} in Montgomery form.
+//
+// LAZY = 3 (Plantard twiddles, N <= 2^(w-1)): the product by a fixed operand
+// (m = a (b N^{-1}) mod 2^(2w), r = floor((floor(m / 2^w) + 1) N / 2^w)) is
+// exact for every w-bit a, not only below N.  With k = (m N - T) / 2^(2w),
+// T = a b, k is an integer in [0, N), congruent to -T 2^(-2w), and
+// (floor(m / 2^w) + 1) N / 2^w lies in (k + T/2^(2w), k + T/2^(2w) + N/2^w],
+// inside (k, k + 1) when T < 2^w (2^w - N), which a < 2^w and b < N <= 2^(w-1)
+// guarantee: r = k.  So t is in [0, N), u + t and u - t + N need no
+// reduction, and each stage raises the bound by N (below 3N after stage 0,
+// 4N after stage 1, (L + 2) N after L stages).  Taken when that fits the word;
+// the outputs are reduced by the same product with 1 or n^{-1}.
 template <class R>
 __device__ __forceinline__ typename R::E lazy_mul(const R &red, typename R::E a, typename R::E b)
 {
@@ -147,7 +158,12 @@ __device__ __forceinline__ void butterfly(const R &red, typename R::E &u, typena
                                           typename R::E N)
 {
     using El = typename R::E;
-    if constexpr (LAZY) {
+    if constexpr (LAZY == 3) {
+        const El t = tw_mul<R, V, FAST>(red, v, w.get());
+        const El x = u;
+        u = (El)(x + t);
+        v = (El)((El)(x + N) - t);
+    } else if constexpr (LAZY) {
         const El t = lazy_mul(red, v, (El)w.get().b);
         const El x = LAZY == 2 ? u : below<El>(u, (El)(2 * N));
         u = (El)(x + t);
@@ -391,7 +407,9 @@ __global__ void __launch_bounds__(BLOCK)
         off[k] = (P - p) + (__brev(p) >> (32 - L));
     }
     auto outv = [&](El y) -> El {
-        if constexpr (LAZY == 2)  // scale: 1 or n^{-1}, times R mod N
+        if constexpr (LAZY == 3)  // scale: the product by 1 or n^{-1}
+            return tw_mul<R, V, FAST>(red, y, scale);
+        else if constexpr (LAZY == 2)  // scale: 1 or n^{-1}, times R mod N
             return below<El>(lazy_mul(red, y, (El)scale.b), N);
         else if constexpr (LAZY)
             return do_scale ? below<El>(lazy_mul(red, y, (El)scale.b), N) : below<El>(below<El>(y, (El)(2 * N)), N);
@@ -523,7 +541,9 @@ __global__ void __launch_bounds__(BLOCK)
         for (int r = 0; r < (1 << h); ++r)
             cx[(1 << h) - 1 + r] = tw[(P + 256u * (uint32_t)r) << (L - 9 - h)];
     auto outv = [&](El y) -> El {
-        if constexpr (LAZY == 2)  // scale: 1 or n^{-1}, times R mod N
+        if constexpr (LAZY == 3)  // scale: the product by 1 or n^{-1}
+            return tw_mul<R, V, FAST>(red, y, scale);
+        else if constexpr (LAZY == 2)  // scale: 1 or n^{-1}, times R mod N
             return below<El>(lazy_mul(red, y, (El)scale.b), N);
         else if constexpr (LAZY)
             return do_scale ? below<El>(lazy_mul(red, y, (El)scale.b), N) : below<El>(below<El>(y, (El)(2 * N)), N);
@@ -731,7 +751,9 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
     // no reduction between stages when the final bound (2 log2n + 1) N fits the word (below 2^63 at w = 64)
     const u128 bound2 = (u128)(2 * log2n + 1) * k.N;
     const bool lazy2 = lazy && bound2 <= (W == 64 ? (u128)1 << 63 : (u128)1 << W);
-    const KConst sc2 = inverse ? t.scale : t.one;  // the output product of the lazy2 form
+    // Plantard twiddles: no reduction between stages when (log2n + 2) N fits the word
+    const bool lazy3 = variant == PLANTARD && small && (u128)(log2n + 2) * k.N <= (u128)1 << W;
+    const KConst sc2 = inverse ? t.scale : t.one;  // the output product of the lazy2 and lazy3 forms
     const auto *twc = (const TwL<W, CLASSIC> *)t.dev;
     const auto *twp = (const TwL<W, PLANTARD> *)t.dev;
     const dim3 b(BLOCK);
@@ -759,6 +781,9 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
             else if (variant == CLASSIC)
                 hipLaunchKernelGGL((k_nttw<W, CLASSIC, false, 0, LL>), g, b, 0, s, k, data, units, nelem, twc,
                                    t.scale, inv, cv);
+            else if (lazy3)
+                hipLaunchKernelGGL((k_nttw<W, PLANTARD, true, 3, LL>), g, b, 0, s, k, data, units, nelem, twp, sc2,
+                                   inv, cv);
             else if (fast)
                 hipLaunchKernelGGL((k_nttw<W, PLANTARD, true, 0, LL>), g, b, 0, s, k, data, units, nelem, twp,
                                    t.scale, inv, cv);
@@ -800,6 +825,8 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
             MONT_NTTM(CLASSIC, true, 0, twc, t.scale);
         else if (variant == CLASSIC)
             MONT_NTTM(CLASSIC, false, 0, twc, t.scale);
+        else if (lazy3)
+            MONT_NTTM(PLANTARD, true, 3, twp, sc2);
         else if (fast)
             MONT_NTTM(PLANTARD, true, 0, twp, t.scale);
         else
