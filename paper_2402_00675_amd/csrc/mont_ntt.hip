@@ -107,14 +107,16 @@ struct TwL<64, PLANTARD> {
     }
 };
 
-// LAZY (classic twiddles, 4N <= 2^w: N < 2^14 at w = 16, N < 2^30 at w = 32,
-// N < 2^61 at w = 64, the latter so that operands stay below 2^63):
-// coefficients live in [0, 4N)
-// between stages.  The twiddle product without its final subtraction is
-// below 4N^2/R + N <= 2N; u is brought below 2N by one conditional
-// subtraction; then u + t and u - t + 2N both lie in [0, 4N) with no further
-// correction (the lazy butterfly of Harvey's NTT).  Results are reduced to
-// [0, N) once, when they are written out.
+// The kernels' LAZY argument picks the butterfly.  LAZY = 0: every sum and
+// difference reduced modulo N.
+//
+// LAZY = 1 (classic twiddles, 4N <= 2^w: N < 2^14 at w = 16, N < 2^30 at
+// w = 32, N < 2^61 at w = 64, the latter so that operands stay below 2^63):
+// coefficients live in [0, 4N) between stages.  The twiddle product without
+// its final subtraction is below 4N^2/R + N <= 2N; u is brought below 2N by
+// one conditional subtraction; then u + t and u - t + 2N both lie in [0, 4N)
+// with no further correction (the lazy butterfly of Harvey's NTT).  Results
+// are reduced to [0, N) once, when they are written out.
 //
 // LAZY = 2 (the same products, for moduli far below the word): u is not
 // reduced at all.  With t < 2N, u + t and u - t + 2N lie in (0, B + 2N) when
