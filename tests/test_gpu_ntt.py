@@ -32,13 +32,14 @@ def prime_1_mod(bits, log2n, seed):
 CASES = [
     (16, 12289, [1, 3, 4, 8, 9, 10, 12]),               # below 2^14: lazy butterflies (so is 3329)
     (16, 3329, [2, 5, 8]),
+    (16, 18433, [1, 3, 6, 8, 10, 11]),                   # 2^14 < N < 2^15: reduced sums, smaller-modulus product
     (16, 36097, [3, 6, 8]),                      # above 2^15: wrap-checked modular add/subtract (both twiddle forms)
     (16, 40961, [4, 7, 8, 9, 10, 11, 12]),                 # above 2^16/phi: classic only
     (32, 8380417, [1, 4, 6, 7, 8, 9, 10, 12]),           # (2 log2n + 1) N < 2^32: no reduction between stages
     (32, 1073692673, [1, 2, 3, 8, 9, 10, 11, 12]),       # below 2^30, 5N > 2^32: lazy, one subtraction per stage
-    (32, 2013265921, [5, 6, 8, 9, 10, 11, 12]),
+    (32, 2013265921, [5, 6, 8, 9, 10, 11, 12]),          # 2^30 < N < 2^31: reduced sums, smaller-modulus product
     (32, 3221225473, [4, 5, 7, 8, 9, 10, 11, 12]),        # above 2^31: the general classic product
-    (64, prime_1_mod(62, 12, 1), [2, 4, 6, 8, 9, 10, 11, 12]),
+    (64, prime_1_mod(62, 12, 1), [2, 4, 6, 8, 9, 10, 11, 12]),  # 2^61 < N < 2^62: reduced sums, smaller-modulus product
     (64, prime_1_mod(60, 12, 1), [3, 5, 7, 8, 9, 10, 11, 12]),  # below 2^61: lazy butterflies (8380417 takes them at w = 32)
     (64, GOLDILOCKS, [3, 4, 6, 8, 9, 10, 11, 12]),
     (64, 1125899906826241, [2, 6, 9, 10, 12]),          # 50-bit: no reduction between stages
@@ -102,9 +103,9 @@ def test_ntt_unaligned_rows(w, N):
             assert np.array_equal(dv.cpu().numpy(), want), (v, n)
 
 
-@pytest.mark.parametrize("w,N", [(16, 3329), (16, 12289), (16, 40961), (32, 8380417), (32, 1073692673),
-                                 (32, 3221225473), (64, prime_1_mod(60, 12, 1)), (64, GOLDILOCKS),
-                                 (64, 1125899906826241)])
+@pytest.mark.parametrize("w,N", [(16, 3329), (16, 12289), (16, 18433), (16, 40961), (32, 8380417), (32, 1073692673),
+                                 (32, 2013265921), (32, 3221225473), (64, prime_1_mod(62, 12, 1)),
+                                 (64, prime_1_mod(60, 12, 1)), (64, GOLDILOCKS), (64, 1125899906826241)])
 def test_ntt_many_per_wave(w, N):
     """Batches of lengths 2 to 4096 larger than the resident waves or
     workgroups (up to 1024 each wave takes several units of max(n, 256)
