@@ -38,7 +38,8 @@ namespace mont {
 // FAST: N < 2^(w-1), so sums of two residues fit a word (branch-free modular
 // add and subtract below); with classic twiddles it also means N < 2^31 at
 // w = 32 or N < 2^62 at w = 64, the ladder's smaller-modulus products (the
-// 64-bit one is lazy, below 2N, so one conditional subtraction follows).
+// 64-bit one is lazy, below 2N, so one conditional subtraction follows), and
+// at w = 16 the three-instruction lazy product and one subtraction.
 template <class R, int V, bool FAST>
 __device__ __forceinline__ typename R::E tw_mul(const R &red, typename R::E a, const KConst &w)
 {
@@ -48,6 +49,10 @@ __device__ __forceinline__ typename R::E tw_mul(const R &red, typename R::E a, c
         return u >= red.N ? u - red.N : u;
     } else if constexpr (V == CLASSIC && FAST && sizeof(El) == 4) {
         return red.mul_fast(a, (El)w.b);
+    } else if constexpr (V == CLASSIC && FAST && sizeof(El) == 2) {
+        // N < 2^15, a, b < N: T + mN < 2^30 + 2^31 fits 32 bits and the quotient is below 2N
+        const El t = red.mul_lazy(a, (El)w.b), d = (El)(t - (El)red.N);
+        return d < t ? d : t;
     } else if constexpr (V == CLASSIC) {
         return red.mul(a, (El)w.b);
     } else {
