@@ -43,7 +43,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--sections", default=None,
                    help="comma list of secondary measurements to run (default: all unless --quick): "
-                        "copy,r32,const,crt,ntt,r16,valu,pow,ragged,serving")
+                        "copy,r32,const,crt,ntt,r16,valu,pow,ragged,serving; opt-in: ntt_lengths "
+                        "(every transform length at each width)")
     p.add_argument("--ragged-segments", type=int, default=4096)
     p.add_argument("--serve-jobs", type=int, default=100_000)
     return p.parse_args()
@@ -348,6 +349,30 @@ def secondary(torch, mg, inp, args, sections):
             log("ntt w16 N=3329 %s: %s" % (v, res["w16_N3329_" + v]))
         ex["ntt"] = res
         del d, d16
+
+    if "ntt_lengths" in sections:
+        # every transform length over 2^26 coefficients (2^25 at w = 64), both twiddle forms:
+        # w = 32 mod 8380417, w = 16 mod 12289, w = 64 mod a 50-bit and a 62-bit prime
+        res = {}
+        for w, N, logs in ((32, 8380417, range(1, 13)), (16, 12289, range(1, 13)),
+                           (64, 1125899906826241, (4, 8, 10, 11, 12)), (64, 4611686018326724609, (8, 10, 12))):
+            c = mg.setup(N, w)
+            dt = {16: np.uint16, 32: np.uint32, 64: np.uint64}[w]
+            count = 1 << (26 if w < 64 else 25)
+            d = torch.from_numpy(inp.uniform_residues(inp.rng(inp.W_R32, 11), N, count, dt)).to(dev)
+            row = {}
+            for lg in logs:
+                nl = 1 << lg
+                rl = next(r for r in (pow(g, (N - 1) // nl, N) for g in range(2, 1000)) if pow(r, nl // 2, N) == N - 1)
+                dl = d.view(count // nl, nl)
+                row["n%d" % nl] = {}
+                for v in ("classic", "plantard"):
+                    _, ms = timed_sec(lambda: mg.ntt(c, dl, rl, variant=v), torch)
+                    row["n%d" % nl][v] = {"ms": round(ms, 4), "GB_s": round(2 * count * w / 8 / (ms * 1e-3) / 1e9, 1)}
+                log("ntt w=%d N=%d n=%d: %s" % (w, N, nl, row["n%d" % nl]))
+            res["w%d_N%d" % (w, N)] = row
+            del d
+        ex["ntt_lengths"] = res
 
     if "r16" in sections:
         # 16-bit workload: N = 3329, 2^20 residues + the exhaustive REDC sweep
