@@ -177,25 +177,35 @@ def main():
     cpu = None
     if not args.no_cpu:
         import concurrent.futures as cf
-        cores = min(16, len(os.sched_getaffinity(0)))
+        # every core this process may run on, within the CPU share the host grants one GPU's
+        # job ($OMP_NUM_THREADS where it is set): both counts are reported
+        avail = len(os.sched_getaffinity(0))
+        share = int(os.environ.get("OMP_NUM_THREADS") or avail)
+        cores = max(1, min(avail, share))
         chunks = [(i, s, min(s + (1 << 22), wl.n)) for i in range(wl.k) for s in range(0, wl.n, 1 << 22)]
 
         def work(c):
             i, s, e = c
             orc.mul("classic", 64, wl.moduli[i], a_h[i, s:e], b_h[i, s:e])
 
-        t0 = time.perf_counter()
+        # the whole headline workload, five passes (a pass takes well under a second on 16
+        # threads); the median pass is reported
+        passes = []
         with cf.ThreadPoolExecutor(cores) as ex:
-            list(ex.map(work, chunks))
-        dt = time.perf_counter() - t0
+            for _ in range(5):
+                t0 = time.perf_counter()
+                list(ex.map(work, chunks))
+                passes.append(time.perf_counter() - t0)
+        dt = float(np.median(passes))
         # one thread over one chunk (2^22 products of row 0)
         t1 = time.perf_counter()
         work(chunks[0])
         dt1 = time.perf_counter() - t1
         n1 = chunks[0][2] - chunks[0][1]
         cpu = {"value": round(units / dt / 1e9, 4), "unit": "Gmodmul/s", "cores": cores, "kind": "oracle",
+               "cores_available": avail, "cpu_share": share,
                "sample": "the whole headline workload (8 x 2^25 classic 64-bit products), "
-                         "128-bit '%%' oracle, %d threads, %.2f s" % (cores, dt),
+                         "128-bit '%%' oracle, %d threads, median of 5 passes: %.3f s" % (cores, dt),
                "single_thread_value": round(n1 / dt1 / 1e9, 4),
                "single_thread_sample": "2^22 products of row 0, %.3f s" % dt1}
         log("cpu oracle: %.3f Gmodmul/s on %d threads (%.2f s), %.3f Gmodmul/s on one thread"
@@ -520,6 +530,10 @@ def _mismatch(o32, e32, o64, e64):
 
 
 def ragged(torch, mg, inp, nseg):
+    """The ragged batch in one launch, by grid kind, against one launch per vector.
+
+    Every launch shape's output pools are compared in full with those of the
+    per-vector launches (themselves checked against the oracle by the tests)."""
     dev = torch.device("cuda:0")
     wl = inp.RaggedWorkload(nseg=nseg)
     lens, wide, mods = wl.segments()
@@ -534,55 +548,78 @@ def ragged(torch, mg, inp, nseg):
     P = mg.pools([None, d["a32"], d["a64"]], [None, d["b32"], d["b64"]], [None, o32, o64])
     nbytes = 12 * int(sum(n for n, wd in zip(lens, wide) if not wd)) + 24 * int(sum(n for n, wd in zip(lens, wide) if wd))
     res = {"segments": nseg, "elements": int(lens.sum()), "bytes": nbytes}
-    for name, flags in (("persistent_graph", mg.BATCH_GRAPH | mg.BATCH_TUNE),):
-        bt = mg.Batch(ctxs, segs, flags=flags)
-        bt.run(P)  # tunes
-        torch.cuda.synchronize()
-        _, ms = timed_sec(lambda: bt.run(P), torch)
-        res[name] = {"ms": round(ms, 3), "GB_s": round(nbytes / (ms * 1e-3) / 1e9, 1), "info": bt.info()}
-        o32h, o64h = o32.cpu().numpy(), o64.cpu().numpy()
-        _, ms_pv = timed_sec(lambda: bt.run_pervector(P), torch)
-        res["per_vector_launches"] = {"ms": round(ms_pv, 3)}
-        if not (np.array_equal(o32h, o32.cpu().numpy()) and np.array_equal(o64h, o64.cpu().numpy())):
-            raise SystemExit("bench: ragged persistent and per-vector results differ")
-        res["speedup_vs_per_vector"] = round(ms_pv / ms, 2)
-        # the same per-vector launches replayed from one captured graph (no host launch cost)
+
+    # one launch per vector: the reference results and the baseline time
+    bt = mg.Batch(ctxs, segs, flags=mg.BATCH_GRAPH)
+    bt.run_pervector(P)
+    torch.cuda.synchronize()
+    o32h, o64h = o32.cpu().numpy(), o64.cpu().numpy()
+    _, ms_pv = timed_sec(lambda: bt.run_pervector(P), torch)
+    res["per_vector_launches"] = {"ms": round(ms_pv, 3), "launches": len(segs)}
+
+    def shape_run(name, flags, shape):
+        b2 = mg.Batch(ctxs, segs, flags=flags)
+        if shape is not None:
+            b2.set_shape(**shape)
         o32.zero_()
         o64.zero_()
-        g = torch.cuda.CUDAGraph()
-        s = torch.cuda.Stream()
-        s.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(s):
-            bt.run_pervector(P)              # warm, outside the capture
-            torch.cuda.synchronize()
-            with torch.cuda.graph(g, stream=s):
-                bt.run_pervector(P, stream=s)
-        torch.cuda.current_stream().wait_stream(s)
+        b2.run(P)  # the first run tunes when asked
         torch.cuda.synchronize()
-        # every replay is checked against the eager results, with eager work between replays
-        bad = []
-        for _ in range(3):
-            o32.zero_()
-            o64.zero_()
-            g.replay()
-            torch.cuda.synchronize()
-            bad.append(_mismatch(o32, o32h, o64, o64h))
-        _, ms_pg = timed_sec(lambda: g.replay(), torch)
-        bad.append(_mismatch(o32, o32h, o64, o64h))
-        bt.run_pervector(P)
+        bad = _mismatch(o32, o32h, o64, o64h)
+        if bad["count"]:
+            raise SystemExit("bench: ragged %s results differ from the per-vector launches: %s" % (name, bad))
+        _, ms = timed_sec(lambda: b2.run(P), torch)
+        info = b2.info()
+        b2.close()
+        kind = "one_pass" if not info["blocks_per_cu"] else "persistent_%s" % (
+            "dynamic" if info["flags"] & mg.BATCH_DYNAMIC else "static")
+        r = {"ms": round(ms, 3), "GB_s": round(nbytes / (ms * 1e-3) / 1e9, 1), "grid_kind": kind,
+             "speedup_vs_per_vector": round(ms_pv / ms, 2), "info": info}
+        log("ragged %s: %s" % (name, r))
+        return r
+
+    # the tuned launch (the tuner picks tile size x grid kind x schedule), then each grid kind
+    # at a fixed shape, all replayed from a hipGraph
+    res["tuned_graph"] = shape_run("tuned_graph", mg.BATCH_GRAPH | mg.BATCH_TUNE, None)
+    res["one_pass_graph"] = shape_run("one_pass_graph", mg.BATCH_GRAPH,
+                                      dict(tile_elems=4096, blocks_per_cu=0, dynamic=False))
+    for bpc in (2, 4, 8):
+        for dyn in (False, True):
+            nm = "persistent_%s_bpc%d_graph" % ("dynamic" if dyn else "static", bpc)
+            res[nm] = shape_run(nm, mg.BATCH_GRAPH, dict(tile_elems=4096, blocks_per_cu=bpc, dynamic=dyn))
+    res["speedup_vs_per_vector"] = res["tuned_graph"]["speedup_vs_per_vector"]
+
+    # the same per-vector launches replayed from one captured graph (no host launch cost)
+    o32.zero_()
+    o64.zero_()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        bt.run_pervector(P)              # warm, outside the capture
         torch.cuda.synchronize()
-        eager_after = _mismatch(o32, o32h, o64, o64h)
-        rep = {"ms": round(ms_pg, 3), "nodes": len(segs), "results_match": True}
-        if any(b["count"] for b in bad) or eager_after["count"]:
-            # recorded, not fatal: this is the comparison baseline, not the library's batched path
-            rep.update(results_match=False, mismatch_per_replay=bad, eager_after=eager_after)
-            log("ragged: graph-replayed per-vector results differ: %s, eager afterwards %s" % (bad, eager_after))
-        else:
-            res["speedup_vs_per_vector_graph"] = round(ms_pg / ms, 2)
-        res["per_vector_graph_replay"] = rep
-        del g
-        bt.close()
-    log("ragged: %s" % res)
+        with torch.cuda.graph(g, stream=s):
+            bt.run_pervector(P, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    # every replay is checked against the eager results, with eager work between replays
+    for _ in range(3):
+        o32.zero_()
+        o64.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        bad = _mismatch(o32, o32h, o64, o64h)
+        if bad["count"]:
+            raise SystemExit("bench: graph-replayed per-vector results differ: %s" % bad)
+    _, ms_pg = timed_sec(lambda: g.replay(), torch)
+    bad = _mismatch(o32, o32h, o64, o64h)
+    if bad["count"]:
+        raise SystemExit("bench: graph-replayed per-vector results differ after timing: %s" % bad)
+    res["per_vector_graph_replay"] = {"ms": round(ms_pg, 3), "nodes": len(segs)}
+    res["speedup_vs_per_vector_graph"] = round(ms_pg / res["tuned_graph"]["ms"], 2)
+    del g
+    bt.close()
+    log("ragged: %s" % {k: v for k, v in res.items() if not isinstance(v, dict)})
     return res
 
 

@@ -250,7 +250,9 @@ typedef struct mont_batch mont_batch_t;
 /* batch flags */
 #define MONT_BATCH_GRAPH 1u   /* replay the launch from a hipGraph */
 #define MONT_BATCH_DYNAMIC 2u /* tiles taken from an atomic counter (else static round-robin) */
-#define MONT_BATCH_TUNE 4u    /* autotune tile size and grid on the first run */
+#define MONT_BATCH_TUNE 4u    /* autotune tile size and grid on the first run; the candidate
+                                 runs read the caller's input pools and write library-owned
+                                 output pools, so in-place batches stay exact */
 #define MONT_BATCH_NONTEMPORAL 8u /* reported by mont_batch_info: the launch uses non-temporal
                                      loads and stores (chosen by the tuner; set by default) */
 
@@ -291,14 +293,42 @@ typedef struct mont_batch_info {
     uint64_t ntiles;
     uint64_t elements;
     uint32_t tile_elems; /* elements per tile for 32-bit mul/redc (others scale by bytes) */
-    uint32_t grid;       /* workgroups of the persistent launch */
+    uint32_t grid;       /* workgroups of the launch */
     uint32_t block;
     uint32_t flags;      /* the batch's flags, plus MONT_BATCH_NONTEMPORAL when it applies */
+    uint32_t blocks_per_cu; /* 0: one workgroup per tile; else the persistent grid is CUs x this */
+    uint32_t pow_tile;   /* elements per exponentiation tile */
 } mont_batch_info_t;
 mont_status_t mont_batch_info(const mont_batch_t *batch, mont_batch_info_t *info);
 
+/*
+ * mont_batch_set_shape -- fixes the launch shape of a batch, in place of (or
+ * after) MONT_BATCH_TUNE, and rebuilds its tile table on `stream` (the call
+ * waits for that upload):
+ *   tile_elems     elements per tile of 32-bit products and reductions
+ *                  (16-bit tiles hold twice as many, 64-bit tiles half), a
+ *                  power of two in [256, 2^20];
+ *   blocks_per_cu  0: one pass, one workgroup per tile; 1..64: a persistent
+ *                  grid of (compute units x blocks_per_cu) workgroups, capped
+ *                  at the tile count, each looping over tiles;
+ *   dynamic        1: each workgroup takes its next tile from an atomic
+ *                  counter (the kernel leaves the counter zeroed for the next
+ *                  run); 0: static round-robin over the tile table;
+ *   nontemporal    1: non-temporal loads and stores.
+ * Results do not depend on the shape.  MONT_E_INVAL for values outside these
+ * ranges; the batch must not be running (its earlier runs completed).
+ */
+typedef struct mont_batch_shape {
+    uint32_t tile_elems;
+    uint32_t blocks_per_cu;
+    uint32_t dynamic;
+    uint32_t nontemporal;
+} mont_batch_shape_t;
+mont_status_t mont_batch_set_shape(mont_batch_t *batch, const mont_batch_shape_t *shape, void *stream);
+
 /* Frees the batch's device tables and graph (after its runs completed). */
 void mont_batch_destroy(mont_batch_t *batch);
+
 
 /* --------------------------------------------------------------------------
  * Launch-shape tuning for the streaming kernels.
@@ -310,10 +340,16 @@ typedef struct mont_launch {
 } mont_launch_t;
 
 /*
- * mont_tune -- times the candidate launch shapes of mont_mul for this
- * (w, variant) on n elements of the given device buffers with HIP events and
- * keeps the fastest for later calls in this process (and in the JSON file
- * named by $MONT_TUNE_CACHE, if set).  Buffers are overwritten with results.
+ * mont_tune_mul -- times the candidate launch shapes of mont_mul (unroll x
+ * non-temporal x grid) for this (w, variant) on n elements of the given
+ * device buffers with HIP events, keeps the fastest for later calls in this
+ * process, and appends it to the JSON-lines file named by $MONT_TUNE_CACHE
+ * (if set).  A shape already recorded there (or earlier in this process) for
+ * the same device architecture, library version, w, variant and size class
+ * (floor(log2 n)) is applied without timing.  The candidates write a
+ * library-owned buffer (MONT_E_NOMEM if it cannot be allocated): a and b are
+ * only read, and out receives one mont_mul of the chosen shape, so
+ * out == a or out == b is allowed.  *best (may be NULL) gets the shape.
  */
 mont_status_t mont_tune_mul(const mont_ctx_t *ctx, const void *a, const void *b, void *out, size_t n,
                             mont_variant_t variant, mont_launch_t *best, void *stream);

@@ -72,13 +72,12 @@ def _load():
         lib.orc_mul.argtypes = [i32, u32, u32, u64, vp, vp, vp, sz]
         lib.orc_redc_i64.argtypes = [i32, u32, u32, u64, vp, vp, sz]
         lib.orc_pow.argtypes = [u32, u64, vp, vp, vp, sz]
-        lib.orc_mulmod.argtypes = [u32, u64, vp, vp, vp, sz]
         lib.orc_dft.argtypes = [u32, u64, vp, u64, u32, i32, vp]
         lib.orc_dft.restype = i32
         lib.orc_inv_mod.argtypes = [u64, u64]
         lib.orc_inv_mod.restype = u64
         lib.orc_last_bad_index.restype = ctypes.c_int64
-        for f in (lib.orc_redc, lib.orc_mul, lib.orc_redc_i64, lib.orc_pow, lib.orc_mulmod):
+        for f in (lib.orc_redc, lib.orc_mul, lib.orc_redc_i64, lib.orc_pow):
             f.restype = i32
         _lib = lib
     return _lib
@@ -145,15 +144,6 @@ def pow(w: int, N: int, x: np.ndarray, e: np.ndarray) -> np.ndarray:  # noqa: A0
     assert x.shape == e.shape
     out = np.empty_like(x)
     _check(_load().orc_pow(w, N, _ptr(x), _ptr(e), _ptr(out), x.shape[0]), "pow")
-    return out
-
-
-def mulmod(w: int, N: int, a: np.ndarray, b: np.ndarray) -> np.ndarray:
-    """Ordinary a[i] * b[i] mod N."""
-    a = np.ascontiguousarray(a)
-    b = np.ascontiguousarray(b)
-    out = np.empty_like(a)
-    _check(_load().orc_mulmod(w, N, _ptr(a), _ptr(b), _ptr(out), a.shape[0]), "mulmod")
     return out
 
 

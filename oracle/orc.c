@@ -407,18 +407,6 @@ int orc_pow(unsigned cw, uint64_t N, const void *x, const uint64_t *e, void *out
     return ORC_OK;
 }
 
-/* a * b mod N for plain residues (the ordinary modular product). */
-int orc_mulmod(unsigned cw, uint64_t N, const void *a, const void *b, void *out, size_t n)
-{
-    if ((cw != 16 && cw != 32 && cw != 64) || N < 2)
-        return ORC_EARG;
-    for (size_t i = 0; i < n; ++i) {
-        u128 p = (u128)(uint64_t)load_elem(a, i, cw, 0) * (uint64_t)load_elem(b, i, cw, 0);
-        store_elem(out, i, cw, (uint64_t)(p % N));
-    }
-    return ORC_OK;
-}
-
 /*
  * Discrete Fourier transform over Z_N by its definition (O(n^2)):
  * forward X_k = sum_j x_j w^(j k) mod N; inverse x_j = n^{-1} sum_k X_k w^(-j k)

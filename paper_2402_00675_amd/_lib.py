@@ -55,7 +55,13 @@ class PoolsStruct(ctypes.Structure):
 
 class BatchInfoStruct(ctypes.Structure):
     _fields_ = [("ntiles", ctypes.c_uint64), ("elements", ctypes.c_uint64), ("tile_elems", ctypes.c_uint32),
-                ("grid", ctypes.c_uint32), ("block", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+                ("grid", ctypes.c_uint32), ("block", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("blocks_per_cu", ctypes.c_uint32), ("pow_tile", ctypes.c_uint32)]
+
+
+class BatchShapeStruct(ctypes.Structure):
+    _fields_ = [("tile_elems", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32), ("dynamic", ctypes.c_uint32),
+                ("nontemporal", ctypes.c_uint32)]
 
 
 class LaunchStruct(ctypes.Structure):
@@ -124,6 +130,7 @@ def _open(path: str):
         "mont_redc_ragged": (i32, [vp, P(PoolsStruct), vp]),
         "mont_pow_ragged": (i32, [vp, P(PoolsStruct), vp]),
         "mont_batch_info": (i32, [vp, P(BatchInfoStruct)]),
+        "mont_batch_set_shape": (i32, [vp, P(BatchShapeStruct), vp]),
         "mont_batch_destroy": (None, [vp]),
         "mont_tune_mul": (i32, [P(CtxStruct), vp, vp, vp, sz, i32, P(LaunchStruct), vp]),
         "mont_set_launch": (i32, [u32, u32, i32, P(LaunchStruct)]),
@@ -140,6 +147,11 @@ def _open(path: str):
         f.argtypes = args
     _opened[path] = lib
     return lib
+
+
+def version() -> int:
+    """mont_version(): the library version (ABI revision in the low 16 bits)."""
+    return int(load().mont_version())
 
 
 def header_functions(path: str = HEADER) -> list:
@@ -392,6 +404,11 @@ class Batch:
     def run_op(self, op: int, p: PoolsStruct, stream=None):
         f = {OP_MUL: load().mont_mul_ragged, OP_REDC: load().mont_redc_ragged, OP_POW: load().mont_pow_ragged}[op]
         check(f(self.h, ctypes.byref(p), _stream(stream)))
+
+    def set_shape(self, tile_elems=4096, blocks_per_cu=0, dynamic=False, nontemporal=True, stream=None):
+        """Fixes the launch shape (mont_batch_set_shape): one pass (blocks_per_cu = 0) or a persistent grid."""
+        sh = BatchShapeStruct(tile_elems, blocks_per_cu, 1 if dynamic else 0, 1 if nontemporal else 0)
+        check(load().mont_batch_set_shape(self.h, ctypes.byref(sh), _stream(stream)))
 
     def info(self):
         i = BatchInfoStruct()

@@ -33,6 +33,7 @@ SOURCES = [
     "mont_capi.cpp",
     "mont_setup.cpp",
     "mont_serve.cpp",
+    "mont_tunecache.cpp",
 ]
 
 # The MONT_DEBUG library: these sources again with -DMONT_DEBUG (precondition

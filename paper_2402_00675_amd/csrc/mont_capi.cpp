@@ -143,7 +143,7 @@ extern "C" {
 
 const char *mont_last_error(void) { return g_err.c_str(); }
 
-uint32_t mont_version(void) { return (1u << 16) | 1u; }
+uint32_t mont_version(void) { return (1u << 16) | 2u; }
 
 mont_status_t mont_setup(uint64_t N, uint32_t log2R, mont_ctx_t *ctx) { return setup_ctx(N, log2R, ctx); }
 
@@ -373,19 +373,14 @@ mont_status_t mont_get_launch(uint32_t op, uint32_t w, mont_variant_t variant, m
 
 namespace mont {
 
-static void save_tuned(int op, uint32_t w, int variant, const Launch &L, float ms)
+static std::string mul_tune_key(uint32_t w, int variant, size_t n)
 {
-    const char *path = std::getenv("MONT_TUNE_CACHE");
-    if (!path || !*path)
-        return;
-    FILE *f = std::fopen(path, "a");
-    if (!f)
-        return;
-    std::fprintf(f,
-                 "{\"op\": %d, \"w\": %u, \"variant\": %d, \"unroll\": %d, \"nontemporal\": %d, "
-                 "\"blocks_per_cu\": %d, \"ms\": %.5f}\n",
-                 op, w, variant, L.unroll, L.nontemporal, L.blocks_per_cu, ms);
-    std::fclose(f);
+    int lg = 0;
+    while ((n >> lg) > 1)
+        ++lg;
+    char k[96];
+    snprintf(k, sizeof k, "mul:w%u:v%d:log2n%d", w, variant, lg);
+    return tune_key_prefix() + k;
 }
 
 }  // namespace mont
@@ -402,63 +397,88 @@ extern "C" mont_status_t mont_tune_mul(const mont_ctx_t *ctx, const void *a, con
     if (n == 0 || !a || !b || !out)
         return fail(MONT_E_INVAL, "tuning needs non-empty device buffers");
     hipStream_t s = (hipStream_t)stream;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-        if (e0)
-            (void)hipEventDestroy(e0);
-        return fail(MONT_E_DEVICE, "event create");
-    }
     const int wc = width_class(ctx->w);
+    const std::string key = mul_tune_key(ctx->w, variant, n);
     const Launch saved = get_launch(0, wc, variant);
     Launch bestL = saved;
-    float best_ms = 1e30f;
-    const int unrolls[] = {1, 2, 4};
-    const int bpcs[] = {0, 4, 8, 16};
-    // clocks to their loaded state first (about 25 ms of the current shape)
-    {
-        const auto t0 = std::chrono::steady_clock::now();
-        do {
-            for (int r = 0; r < 4 && !rc; ++r)
-                rc = mont_mul(ctx, a, b, out, n, variant, stream);
-            if (!rc && hipStreamSynchronize(s) != hipSuccess)
-                rc = fail(MONT_E_DEVICE, "tuning warm-up failed");
-        } while (!rc && std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(25));
-    }
-    // every candidate shape: unroll x non-temporal x workgroups per CU; the first failure ends the sweep
-    for (int c = 0; c < 3 * 2 * 4 && !rc; ++c) {
-        Launch L;
-        L.unroll = unrolls[c / 8];
-        L.nontemporal = (c / 4) % 2;
-        L.blocks_per_cu = bpcs[c % 4];
-        set_launch(0, wc, variant, L);
-        rc = mont_mul(ctx, a, b, out, n, variant, stream);  // warm
-        if (!rc && hipEventRecord(e0, s) != hipSuccess)
-            rc = fail(MONT_E_DEVICE, "event record");
-        for (int r = 0; r < 5 && !rc; ++r)
-            rc = mont_mul(ctx, a, b, out, n, variant, stream);
-        if (!rc && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
-            rc = fail(MONT_E_DEVICE, "tuning run failed");
-        if (rc)
-            break;
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best_ms) {
-            best_ms = ms;
-            bestL = L;
+    TuneRecord rec;
+    if (tune_lookup(key, rec) && rec.count("unroll") && rec.count("nontemporal") && rec.count("blocks_per_cu")) {
+        // a shape tuned earlier for this device, library version, width, variant and size class
+        bestL.unroll = (int)rec["unroll"];
+        bestL.nontemporal = (int)rec["nontemporal"];
+        bestL.blocks_per_cu = (int)rec["blocks_per_cu"];
+        if (bestL.unroll != 1 && bestL.unroll != 2 && bestL.unroll != 4)
+            bestL = saved;
+        set_launch(0, wc, variant, bestL);
+    } else {
+        // Candidates write a library-owned buffer: a and b are only read, so an
+        // in-place call (out == a or out == b) is exact.
+        void *scratch = nullptr;
+        if (hipMalloc(&scratch, n * (ctx->w / 8)) != hipSuccess)
+            return fail(MONT_E_NOMEM, "tuning output of %zu elements", n);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            if (e0)
+                (void)hipEventDestroy(e0);
+            (void)hipFree(scratch);
+            return fail(MONT_E_DEVICE, "event create");
         }
+        float best_ms = 1e30f;
+        const int unrolls[] = {1, 2, 4};
+        const int bpcs[] = {0, 4, 8, 16};
+        // clocks to their loaded state first (about 25 ms of the current shape)
+        {
+            const auto t0 = std::chrono::steady_clock::now();
+            do {
+                for (int r = 0; r < 4 && !rc; ++r)
+                    rc = mont_mul(ctx, a, b, scratch, n, variant, stream);
+                if (!rc && hipStreamSynchronize(s) != hipSuccess)
+                    rc = fail(MONT_E_DEVICE, "tuning warm-up failed");
+            } while (!rc && std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(25));
+        }
+        // every candidate shape: unroll x non-temporal x workgroups per CU; the first failure ends the sweep
+        for (int c = 0; c < 3 * 2 * 4 && !rc; ++c) {
+            Launch L;
+            L.unroll = unrolls[c / 8];
+            L.nontemporal = (c / 4) % 2;
+            L.blocks_per_cu = bpcs[c % 4];
+            set_launch(0, wc, variant, L);
+            rc = mont_mul(ctx, a, b, scratch, n, variant, stream);  // warm
+            if (!rc && hipEventRecord(e0, s) != hipSuccess)
+                rc = fail(MONT_E_DEVICE, "event record");
+            for (int r = 0; r < 5 && !rc; ++r)
+                rc = mont_mul(ctx, a, b, scratch, n, variant, stream);
+            if (!rc && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                rc = fail(MONT_E_DEVICE, "tuning run failed");
+            if (rc)
+                break;
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) {
+                best_ms = ms;
+                bestL = L;
+            }
+        }
+        if (hipStreamSynchronize(s) != hipSuccess && !rc)
+            rc = fail(MONT_E_DEVICE, "tuning runs failed");
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        (void)hipFree(scratch);
+        set_launch(0, wc, variant, rc ? saved : bestL);
+        if (rc)
+            return rc;
+        tune_store(key, {{"unroll", (double)bestL.unroll},
+                         {"nontemporal", (double)bestL.nontemporal},
+                         {"blocks_per_cu", (double)bestL.blocks_per_cu},
+                         {"ms", best_ms / 5}});
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    set_launch(0, wc, variant, rc ? saved : bestL);
-    if (rc)
-        return rc;
-    save_tuned(0, ctx->w, variant, bestL, best_ms / 5);
     if (best) {
         best->unroll = (uint32_t)bestL.unroll;
         best->nontemporal = (uint32_t)bestL.nontemporal;
         best->blocks_per_cu = (uint32_t)bestL.blocks_per_cu;
     }
-    return MONT_OK;
+    // the caller's out receives one product with the chosen shape
+    return mont_mul(ctx, a, b, out, n, variant, stream);
 }
 
 #ifndef MONT_DEBUG

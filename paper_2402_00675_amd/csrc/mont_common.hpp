@@ -3,6 +3,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <string>
+
 #include "../../include/mont.h"
 #include "mont_kernels.hpp"
 
@@ -17,5 +20,11 @@ mont_status_t check_ctx(const mont_ctx_t *ctx);
 mont_status_t check_variant(const mont_ctx_t *ctx, int variant);
 Launch get_launch(int op, int wc, int variant);
 void set_launch(int op, int wc, int variant, const Launch &l);
+
+// Tuned shapes, persisted as JSON lines in $MONT_TUNE_CACHE (mont_tunecache.cpp).
+using TuneRecord = std::map<std::string, double>;
+std::string tune_key_prefix();  // "<gfx arch>:v<mont_version()>:"
+bool tune_lookup(const std::string &key, TuneRecord &out);
+void tune_store(const std::string &key, const TuneRecord &r);
 
 }  // namespace mont

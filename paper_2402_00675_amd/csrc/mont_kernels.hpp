@@ -127,11 +127,12 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t g)
 }
 
 // out[i] = red.mul(a[i], b[i]) (OP 0), red.redc(T[i]) (OP 1) or
-// red.mul_const(a[i], kc) (OP 2), per row.
+// red.mul_const(a[i], kc) (OP 2), per row.  out may be in0 or in1 (in-place
+// calls): every element is read and written by the same lane, reads first,
+// so the pointers carry no __restrict__.
 template <int W, int V, int OP, int E, int U, bool NT, int NR>
 __global__ void __launch_bounds__(BLOCK)
-    k_map(KTab<NR> tab, const void *__restrict__ in0, const void *__restrict__ in1, void *__restrict__ out,
-          uint64_t n, uint64_t ld, KConst kc)
+    k_map(KTab<NR> tab, const void *in0, const void *in1, void *out, uint64_t n, uint64_t ld, KConst kc)
 {
     using R = Red<W, V>;
     using El = typename R::E;
@@ -326,7 +327,7 @@ constexpr int pow_window() { return MODE == 3 ? 4 : 2; }
 
 template <int W, int U, int MODE>
 __global__ void __launch_bounds__(BLOCK)
-    k_pow(KCtx c, const void *__restrict__ xin, const uint64_t *__restrict__ ein, void *__restrict__ out, uint64_t n)
+    k_pow(KCtx c, const void *xin, const uint64_t *ein, void *out, uint64_t n)  // out may be xin (in place)
 {
     using R = Red<W, CLASSIC>;
     using El = typename R::E;

@@ -220,6 +220,18 @@ __device__ __forceinline__ void lds_put4(El *p, const El (&a)[4])
     }
 }
 
+// Between exchange steps the lanes of one wavefront read LDS words other lanes
+// of the same wavefront wrote: a release fence, the wavefront barrier and an
+// acquire fence, all at wavefront scope, order those writes before the reads
+// under the memory model (a wave's LDS accesses complete in order, so this
+// costs no wait; it keeps the compiler from moving the accesses across it).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // The four radix-4 steps (stages 0..7, those below L) of NB blocks of 256
 // positions held by one wavefront, four positions per lane in each (lane maps
 // and LDS layout at k_nttw); block b goes through the 256 LDS words at
@@ -245,7 +257,7 @@ __device__ __forceinline__ void block_steps(const R &red, typename R::E (&a)[NB]
         }
         lds_put4<El>(sb + 256 * b + 4 * lane, a[b]);
     }
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    wave_lds_sync();
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const El *q = sb + 256 * b;
@@ -254,7 +266,7 @@ __device__ __forceinline__ void block_steps(const R &red, typename R::E (&a)[NB]
         a[b][2] = q[base1 + 64];
         a[b][3] = q[base1 + 192];
     }
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    wave_lds_sync();
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         if constexpr (H2) {
@@ -267,13 +279,13 @@ __device__ __forceinline__ void block_steps(const R &red, typename R::E (&a)[NB]
         }
         lds_put4<El>(sb + 256 * b + 4 * lane, a[b]);
     }
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    wave_lds_sync();
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             a[b][k] = sb[256 * b + base2 + 64 * k];
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    wave_lds_sync();
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         if constexpr (H4) {
@@ -286,13 +298,13 @@ __device__ __forceinline__ void block_steps(const R &red, typename R::E (&a)[NB]
         }
         lds_put4<El>(sb + 256 * b + 4 * lane, a[b]);
     }
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    wave_lds_sync();
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             a[b][k] = sb[256 * b + base3 + 64 * k];
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    wave_lds_sync();
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         if constexpr (H6) {

@@ -265,12 +265,47 @@ struct mont_batch {
 
 namespace mont {
 
-static uint32_t tile_elems(const mont_batch &b, uint32_t wc, uint32_t op)
+mont_status_t make_dseg(const mont_ctx_t *ctxs, uint32_t nctx, const mont_seg_t &sg, uint32_t i, DSeg &d)
+{
+    mont_status_t rc = MONT_OK;
+    if (sg.ctx >= nctx)
+        rc = fail(MONT_E_INVAL, "segment %u: context index %u out of range", i, sg.ctx);
+    else if (sg.op > MONT_OP_POW)
+        rc = fail(MONT_E_INVAL, "segment %u: unknown op %u", i, (unsigned)sg.op);
+    else if (sg.op == MONT_OP_POW && sg.variant != MONT_CLASSIC)
+        rc = fail(MONT_E_UNSUPPORTED, "segment %u: exponentiation uses the classic variant", i);
+    else if (sg.n >= (1ull << 40) || sg.off >= (1ull << 48) || sg.off1 >= (1ull << 48))
+        rc = fail(MONT_E_INVAL, "segment %u: size or offset too large", i);
+    else if (sg.op == MONT_OP_MUL && ((sg.off1 - sg.off) & (uint64_t)(128 / ctxs[sg.ctx].w - 1)) != 0)
+        rc = fail(MONT_E_INVAL, "segment %u: off1 - off must be a multiple of %u", i, 128 / ctxs[sg.ctx].w);
+    else {
+        rc = check_variant(&ctxs[sg.ctx], sg.variant);
+        if (rc)
+            rc = fail(rc, "segment %u: %s", i, mont_last_error());
+    }
+    if (rc)
+        return rc;
+    std::memset(&d, 0, sizeof d);
+    d.c = to_kctx(ctxs[sg.ctx]);
+    d.off = sg.off;
+    d.off1 = sg.off1;
+    d.op = sg.op;
+    d.variant = sg.variant;
+    d.wc = (uint32_t)width_class(ctxs[sg.ctx].w);
+    return MONT_OK;
+}
+
+uint32_t seg_tile_elems(uint32_t tile_base, uint32_t pow_tile, uint32_t wc, uint32_t op)
 {
     if (op == MONT_OP_POW)
-        return b.pow_tile;
+        return pow_tile;
     // equal output bytes per tile: 16-bit tiles have twice the elements of 32-bit ones
-    return wc == 0 ? b.tile_base * 2 : wc == 1 ? b.tile_base : b.tile_base / 2;
+    return wc == 0 ? tile_base * 2 : wc == 1 ? tile_base : tile_base / 2;
+}
+
+static uint32_t tile_elems(const mont_batch &b, uint32_t wc, uint32_t op)
+{
+    return seg_tile_elems(b.tile_base, b.pow_tile, wc, op);
 }
 
 static mont_status_t build_tiles(mont_batch &b, hipStream_t s)
@@ -310,7 +345,7 @@ static mont_status_t build_tiles(mont_batch &b, hipStream_t s)
     // XCD x walks the x-th eighth of the table (xcd_block, when the tile count
     // is a multiple of 8): store logical tile 8p + x at x * (n/8) + p, so that
     // the XCDs, advancing together, visit the logical order above.
-    if (!b.blocks_per_cu && all.size() % 8 == 0 && !all.empty()) {
+    if (!b.blocks_per_cu && !(b.flags & MONT_BATCH_DYNAMIC) && all.size() % 8 == 0 && !all.empty()) {
         const size_t c = all.size() / 8;
         std::vector<DTile> perm(all.size());
         for (size_t p = 0; p < c; ++p)
@@ -442,8 +477,6 @@ static mont_status_t run_once(mont_batch &b, const DPools &P, hipStream_t s)
 struct RaggedTune {
     uint32_t tile_base, blocks_per_cu, dynamic, nt;
 };
-static std::mutex g_rt_mu;
-static std::unordered_map<std::string, RaggedTune> g_rt_cache;
 
 static std::string tune_key(const mont_batch &b)
 {
@@ -456,23 +489,65 @@ static std::string tune_key(const mont_batch &b)
         ++lg;
     snprintf(k, sizeof k, "ragged:nseg=%zu:log2n=%d:mul=%d:redc=%d:pow=%d", b.segs.size() >= 1024 ? 1024 : b.segs.size(),
              lg, ops[0] > 0, ops[1] > 0, ops[2] > 0);
-    return k;
+    return tune_key_prefix() + k;
 }
 
-static mont_status_t tune(mont_batch &b, const DPools &P, hipStream_t s)
+// Library-owned output pools of the batch's extent per width class: the tuner
+// writes its candidate runs there, so the caller's buffers are only read
+// (a batch whose outputs overwrite its inputs stays correct).
+struct ScratchOut {
+    void *p[3] = {nullptr, nullptr, nullptr};
+    ~ScratchOut()
+    {
+        for (void *q : p)
+            if (q)
+                (void)hipFree(q);
+    }
+};
+
+static mont_status_t scratch_outputs(const mont_batch &b, const DPools &P, ScratchOut &so, DPools &Pt)
+{
+    static const size_t esz[3] = {2, 4, 8};
+    uint64_t ext[3] = {0, 0, 0};
+    for (size_t i = 0; i < b.segs.size(); ++i) {
+        const mont_seg_t &sg = b.segs[i];
+        if (sg.n)
+            ext[b.hsegs[i].wc] = std::max<uint64_t>(ext[b.hsegs[i].wc], sg.off + sg.n);
+    }
+    Pt = P;
+    for (int wc = 0; wc < 3; ++wc) {
+        if (!ext[wc])
+            continue;
+        if (hipMalloc(&so.p[wc], ext[wc] * esz[wc]) != hipSuccess)
+            return fail(MONT_E_NOMEM, "tuning output pool of %llu bytes", (unsigned long long)(ext[wc] * esz[wc]));
+        Pt.out[wc] = so.p[wc];
+    }
+    return MONT_OK;
+}
+
+static mont_status_t tune(mont_batch &b, const DPools &Pcaller, hipStream_t s)
 {
     const std::string key = tune_key(b);
     {
-        std::lock_guard<std::mutex> g(g_rt_mu);
-        auto it = g_rt_cache.find(key);
-        if (it != g_rt_cache.end()) {
-            b.tile_base = it->second.tile_base;
-            b.blocks_per_cu = it->second.blocks_per_cu;
-            b.nt = it->second.nt != 0;
-            b.flags = (b.flags & ~MONT_BATCH_DYNAMIC) | (it->second.dynamic ? MONT_BATCH_DYNAMIC : 0u);
-            return build_tiles(b, s);
+        // a shape tuned earlier (this process, or $MONT_TUNE_CACHE) for this device,
+        // library version and batch class
+        TuneRecord r;
+        if (tune_lookup(key, r) && r.count("tile_elems") && r.count("blocks_per_cu") && r.count("dynamic") &&
+            r.count("nontemporal")) {
+            const uint32_t t = (uint32_t)r["tile_elems"], bpc = (uint32_t)r["blocks_per_cu"];
+            if (t >= 256 && t <= (1u << 20) && !(t & (t - 1)) && bpc <= 64) {
+                b.tile_base = t;
+                b.blocks_per_cu = bpc;
+                b.nt = r["nontemporal"] != 0;
+                b.flags = (b.flags & ~MONT_BATCH_DYNAMIC) | (r["dynamic"] != 0 ? MONT_BATCH_DYNAMIC : 0u);
+                return build_tiles(b, s);
+            }
         }
     }
+    ScratchOut so;
+    DPools P;
+    if (mont_status_t rs = scratch_outputs(b, Pcaller, so, P))
+        return rs;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         if (e0)
@@ -535,6 +610,9 @@ static mont_status_t tune(mont_batch &b, const DPools &P, hipStream_t s)
         }
     }
 done:
+    // the scratch pools are freed on return; nothing of the sweep may still run then
+    if (hipStreamSynchronize(s) != hipSuccess && !rc)
+        rc = fail(MONT_E_DEVICE, "tuning runs failed");
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     // the best shape so far (the starting one if none was timed), also after a failure
@@ -546,10 +624,11 @@ done:
         (void)build_tiles(b, s);
         return rc;
     }
-    {
-        std::lock_guard<std::mutex> g(g_rt_mu);
-        g_rt_cache[key] = bt;
-    }
+    tune_store(key, {{"tile_elems", (double)bt.tile_base},
+                     {"blocks_per_cu", (double)bt.blocks_per_cu},
+                     {"dynamic", (double)bt.dynamic},
+                     {"nontemporal", (double)bt.nt},
+                     {"ms", best / 5}});
     return build_tiles(b, s);
 }
 
@@ -579,34 +658,10 @@ mont_status_t mont_batch_create(const mont_ctx_t *ctxs, uint32_t nctx, const mon
     b->hsegs.resize(nseg);
     for (uint32_t i = 0; i < nseg; ++i) {
         const mont_seg_t &sg = segs[i];
-        mont_status_t rc = MONT_OK;
-        if (sg.ctx >= nctx)
-            rc = fail(MONT_E_INVAL, "segment %u: context index %u out of range", i, sg.ctx);
-        else if (sg.op > MONT_OP_POW)
-            rc = fail(MONT_E_INVAL, "segment %u: unknown op %u", i, (unsigned)sg.op);
-        else if (sg.op == MONT_OP_POW && sg.variant != MONT_CLASSIC)
-            rc = fail(MONT_E_UNSUPPORTED, "segment %u: exponentiation uses the classic variant", i);
-        else if (sg.n >= (1ull << 40) || sg.off >= (1ull << 48) || sg.off1 >= (1ull << 48))
-            rc = fail(MONT_E_INVAL, "segment %u: size or offset too large", i);
-        else if (sg.op == MONT_OP_MUL && ((sg.off1 - sg.off) & (uint64_t)(128 / ctxs[sg.ctx].w - 1)) != 0)
-            rc = fail(MONT_E_INVAL, "segment %u: off1 - off must be a multiple of %u", i, 128 / ctxs[sg.ctx].w);
-        else {
-            rc = check_variant(&ctxs[sg.ctx], sg.variant);
-            if (rc)
-                rc = fail(rc, "segment %u: %s", i, mont_last_error());
-        }
-        if (rc) {
+        if (mont_status_t rc = make_dseg(ctxs, nctx, sg, i, b->hsegs[i])) {
             delete b;
             return rc;
         }
-        DSeg &d = b->hsegs[i];
-        std::memset(&d, 0, sizeof d);
-        d.c = to_kctx(ctxs[sg.ctx]);
-        d.off = sg.off;
-        d.off1 = sg.off1;
-        d.op = sg.op;
-        d.variant = sg.variant;
-        d.wc = (uint32_t)width_class(ctxs[sg.ctx].w);
         b->elements += sg.n;
         b->op_mask |= 1u << sg.op;
     }
@@ -726,7 +781,28 @@ mont_status_t mont_batch_info(const mont_batch_t *b, mont_batch_info_t *info)
     info->grid = b->grid;
     info->block = BLOCK;
     info->flags = b->flags | (b->nt ? MONT_BATCH_NONTEMPORAL : 0u);
+    info->blocks_per_cu = b->blocks_per_cu;
+    info->pow_tile = b->pow_tile;
     return MONT_OK;
+}
+
+mont_status_t mont_batch_set_shape(mont_batch_t *b, const mont_batch_shape_t *sh, void *stream)
+{
+    if (!b || !sh)
+        return fail(MONT_E_INVAL, "null argument");
+    const uint32_t t = sh->tile_elems;
+    if (t < 256 || t > (1u << 20) || (t & (t - 1)))
+        return fail(MONT_E_INVAL, "tile_elems must be a power of two in [256, 2^20]");
+    if (sh->blocks_per_cu > 64)
+        return fail(MONT_E_INVAL, "blocks_per_cu must be at most 64");
+    if (sh->dynamic > 1 || sh->nontemporal > 1)
+        return fail(MONT_E_INVAL, "dynamic and nontemporal are 0 or 1");
+    b->tile_base = t;
+    b->blocks_per_cu = sh->blocks_per_cu;
+    b->nt = sh->nontemporal != 0;
+    b->flags = (b->flags & ~MONT_BATCH_DYNAMIC) | (sh->dynamic ? MONT_BATCH_DYNAMIC : 0u);
+    b->tuned = true;  // an explicit shape replaces tuning
+    return build_tiles(*b, (hipStream_t)stream);
 }
 
 void mont_batch_destroy(mont_batch_t *b)

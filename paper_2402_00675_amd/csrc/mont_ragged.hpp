@@ -2,6 +2,7 @@
 // and the serving loop.
 #pragma once
 
+#include "../../include/mont.h"
 #include "mont_kernels.hpp"
 
 namespace mont {
@@ -35,5 +36,11 @@ struct DPools {
 hipError_t launch_ragged(const DSeg *segs, const DTile *tiles, uint32_t ntiles, const DPools &P, uint32_t *ctr,
                          uint32_t dyn, uint32_t grid, bool nt, hipStream_t s);
 void *ragged_kernel_ptr(bool nt);
+
+// Validates segment i of a batch (context index, op, variant, sizes, operand
+// alignment) and fills its device descriptor; the error text names the segment.
+mont_status_t make_dseg(const mont_ctx_t *ctxs, uint32_t nctx, const mont_seg_t &sg, uint32_t i, DSeg &d);
+// Elements per tile of a segment of width class wc and operation op.
+uint32_t seg_tile_elems(uint32_t tile_base, uint32_t pow_tile, uint32_t wc, uint32_t op);
 
 }  // namespace mont

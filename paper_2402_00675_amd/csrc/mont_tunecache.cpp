@@ -1,0 +1,121 @@
+// Persistent cache of tuned launch shapes: JSON lines in the file named by
+// $MONT_TUNE_CACHE, one record per tuning, e.g.
+//   {"key": "gfx950:v65538:mul:w32:v2:log2n22", "unroll": 1, "nontemporal": 1, ...}
+// Keys start with the device's architecture and the library version, so a
+// cache written by another GPU or another build of the library is never
+// applied.  A lookup reads the file again (tunings are rare and the file is
+// small) and takes the last record with the key; records this process
+// writes are also kept in memory for when no file is named.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "mont_common.hpp"
+
+namespace mont {
+
+static std::mutex g_tc_mu;
+static std::map<std::string, TuneRecord> g_tc_mem;
+
+std::string tune_key_prefix()
+{
+    int dev = 0;
+    hipDeviceProp_t p;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess) {
+        arch = p.gcnArchName;
+        const size_t c = arch.find(':');
+        if (c != std::string::npos)
+            arch.resize(c);
+    }
+    char v[32];
+    snprintf(v, sizeof v, ":v%u:", mont_version());
+    return arch + v;
+}
+
+// Parses one line written by tune_store: the key string, then "name": integer pairs.
+static bool parse_line(const char *s, std::string &key, TuneRecord &r)
+{
+    const char *k = std::strstr(s, "\"key\"");
+    if (!k)
+        return false;
+    k = std::strchr(k + 5, '"');
+    if (!k)
+        return false;
+    const char *e = std::strchr(k + 1, '"');
+    if (!e)
+        return false;
+    key.assign(k + 1, e);
+    r.clear();
+    const char *p = e + 1;
+    while ((p = std::strchr(p, '"')) != nullptr) {
+        const char *q = std::strchr(p + 1, '"');
+        if (!q)
+            break;
+        std::string name(p + 1, q);
+        const char *c = q + 1;
+        while (*c == ' ' || *c == ':')
+            ++c;
+        char *end = nullptr;
+        const double v = std::strtod(c, &end);
+        if (end != c)
+            r[name] = v;
+        p = end && end != c ? end : q + 1;
+    }
+    return true;
+}
+
+bool tune_lookup(const std::string &key, TuneRecord &out)
+{
+    std::lock_guard<std::mutex> g(g_tc_mu);
+    const char *path = std::getenv("MONT_TUNE_CACHE");
+    bool found = false;
+    if (path && *path) {
+        if (FILE *f = std::fopen(path, "r")) {
+            char line[1024];
+            std::string k;
+            TuneRecord r;
+            while (std::fgets(line, sizeof line, f))
+                if (parse_line(line, k, r) && k == key) {
+                    out = r;
+                    found = true;
+                }
+            std::fclose(f);
+        }
+        if (found)
+            return true;
+    }
+    auto it = g_tc_mem.find(key);
+    if (it == g_tc_mem.end())
+        return false;
+    out = it->second;
+    return true;
+}
+
+void tune_store(const std::string &key, const TuneRecord &r)
+{
+    std::lock_guard<std::mutex> g(g_tc_mu);
+    g_tc_mem[key] = r;
+    const char *path = std::getenv("MONT_TUNE_CACHE");
+    if (!path || !*path)
+        return;
+    FILE *f = std::fopen(path, "a");
+    if (!f)
+        return;
+    std::string line = "{\"key\": \"" + key + "\"";
+    char buf[96];
+    for (const auto &kv : r) {
+        snprintf(buf, sizeof buf, ", \"%s\": %.6g", kv.first.c_str(), kv.second);
+        line += buf;
+    }
+    line += "}\n";
+    std::fputs(line.c_str(), f);
+    std::fclose(f);
+}
+
+}  // namespace mont

@@ -144,6 +144,96 @@ def test_redc_parity(w, N, variant):
                                                                            want[bad[0]])
 
 
+def edge_T(variant, w, N, seed, alpha=1):
+    """T values at the corners of each algorithm's intermediate quantities, from closed forms.
+
+    Classic and signed (R = 2^w, T = a1 R + a0): low words a0 = 0, 1, R/2, R - 1 (for Algorithm 1
+    a0 = R/2 gives the mods tie m0 = a0 N^{-1} mods R = -R/2, since (R/2) N = R/2 mod R), high words
+    at both ends of the range, T = N j (t = (T + mN)/R is exactly N before the correction: m = R - j),
+    and the largest |T|.  Plantard family (R = 2^(2n), m = T N^{-1} mod R or mods R, q = floor(m/2^n)):
+    T = N j (m = j), the largest reachable q for T <= N^2 (T = 2^(2n) - N D with
+    D = ceil((2^(2n) - N^2)/N): q = 2^n - ceil(D/2^n), which reaches 2^n - 2 for N close to 2^n/phi
+    and never 2^n - 1, the dead branch of Algorithm 2's remark), low halves of m at 0, 2^(n-1)
+    (the round-half-up tie of Algorithm 3's first rounding) and 2^n - 1, q at both ends of its
+    signed range (Algorithms 3 and 4), and the largest |T|.  Values outside the Require range
+    are dropped.
+    """
+    rnd = random.Random(seed)
+    lo, hi = t_bounds(variant, w, N, alpha)
+    out = []
+
+    def add(t):
+        if lo <= t <= hi and (variant != "signed" or abs(t) < N * (1 << w) // 2):
+            out.append(t)
+
+    if variant in ("classic", "signed"):
+        R = 1 << w
+        h = (N - 1) // 2
+        a1s = [0, 1, 2, N - 1, N - 2, h, h - 1] if variant == "classic" else [0, 1, -1, h - 1, h - 2, -h, -h - 1]
+        a1s += [rnd.randint(-h if variant == "signed" else 0, N - 1 if variant == "classic" else h - 1)
+                for _ in range(8)]
+        for a1 in a1s:
+            for a0 in (0, 1, R // 2, R // 2 - 1, R // 2 + 1, R - 1):
+                add(a1 * R + a0)
+        for j in [1, 2, R - 1, R - 2, R // 2] + [rnd.randrange(1, R) for _ in range(8)]:
+            add(N * j)
+            add(-N * j)
+        add(hi)
+        add(lo)
+        return out
+    n = w
+    R2 = 1 << (2 * n)
+    sgn = variant != "plantard"
+
+    def from_m(m):
+        t = (m % R2) * N % R2
+        if sgn and t >= R2 // 2:
+            t -= R2
+        return t
+
+    for j in [0, 1, 2, 3, N - 1, N] + [rnd.randrange(N) for _ in range(6)]:
+        add(N * j)
+        add(-N * j)
+    if not sgn:
+        D = -(-(R2 - N * N) // N)
+        for k in range(8):
+            add(R2 - N * (D + k))
+        add(N * N)
+        add(N * N - 1)
+    qs = ([(1 << n) - 1, (1 << n) - 2, 0, 1] if not sgn else
+          [(1 << (n - 1)) - 1, (1 << (n - 1)) - 2, -(1 << (n - 1)), -(1 << (n - 1)) + 1, 0, -1])
+    for l in (0, 1 << (n - 1), (1 << n) - 1):
+        for _ in range(300):
+            q = rnd.randrange(1 << n) if not sgn else rnd.randrange(-(1 << (n - 1)), 1 << (n - 1))
+            add(from_m(q * (1 << n) + l))
+    for q in qs:
+        for _ in range(300):
+            add(from_m(q * (1 << n) + rnd.randrange(1 << n)))
+    add(hi)
+    add(lo)
+    return out
+
+
+# the largest odd moduli below 2^w / phi (Algorithm 2's bound): the quotient q reaches 2^n - 2
+PHI_EDGE = [(32, 2654435769, "plantard"), (64, 11400714819323198485, "plantard")]
+EDGE_CASES = [c for c in CASES if c[0] > 16] + PHI_EDGE
+
+
+@pytest.mark.parametrize("w,N,variant", EDGE_CASES, ids=["w%d-N%d-%s" % c for c in EDGE_CASES])
+def test_redc_edge_vectors(w, N, variant):
+    """The closed-form edge values of edge_T at 32 and 64 bits, element by element."""
+    c = mg.setup(N, w)
+    assert c.valid(variant)
+    vals = edge_T(variant, w, N, seed=w + N % 991, alpha=c.s.alpha)
+    assert len(vals) > 15
+    T = pack_T(vals, variant, w)
+    got = host(mg.redc(c, dev(T), n=len(vals), variant=variant))
+    want = orc.redc(variant, w, N, T, alpha=c.s.alpha)
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, "first mismatch at %d: T=%d got %d want %d" % (bad[0], vals[bad[0]], got[bad[0]],
+                                                                           want[bad[0]])
+
+
 @pytest.mark.parametrize("w,N,variant", CASES, ids=["w%d-N%d-%s" % c for c in CASES])
 def test_mul_const_parity(w, N, variant):
     """Fixed-operand product equals the product with b broadcast, for edge and random b."""
@@ -603,6 +693,6 @@ def test_tune_mul_and_cache(tmp_path, monkeypatch):
         got = host(mg.mul(c, da, db, variant="plantard"))
         assert np.array_equal(got, orc.mul("plantard", w, N, a, b))
         rec = [json.loads(l) for l in cache.read_text().splitlines()]
-        assert rec[-1]["w"] == 32 and rec[-1]["variant"] == 2 and rec[-1]["unroll"] == best["unroll"]
+        assert ":mul:w32:v2:log2n22" in rec[-1]["key"] and rec[-1]["unroll"] == best["unroll"]
     finally:
         mg.set_launch(mg.OP_MUL, w, "plantard", **saved)
