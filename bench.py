@@ -43,7 +43,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--sections", default=None,
                    help="comma list of secondary measurements to run (default: all unless --quick): "
-                        "copy,r32,const,crt,ntt,r16,valu,pow,ragged,serving; opt-in: ntt_lengths "
+                        "copy,ceiling,r32,const,crt,ntt,r16,valu,pow,ragged,serving; opt-in: ntt_lengths "
                         "(every transform length at each width)")
     p.add_argument("--ragged-segments", type=int, default=4096)
     p.add_argument("--serve-jobs", type=int, default=100_000)
@@ -259,7 +259,43 @@ def copy_ceiling(torch):
     return {"torch_copy_GBs": copy, "ref_2r1w_GBs": ref}
 
 
-SECTIONS = ("copy", "r32", "const", "crt", "ntt", "r16", "valu", "pow", "ragged", "serving")
+SECTIONS = ("copy", "ceiling", "r32", "const", "crt", "ntt", "r16", "valu", "pow", "ragged", "serving")
+
+
+def ceiling(torch, mg, inp):
+    """The 2-read/1-write stream at equal bytes per launch, 2^24 to 2^29 64-bit RNS products
+    (0.4 to 12.9 GB): the XOR reference kernel, the 32-bit classic product over twice as many
+    elements and the 64-bit RNS product (8 rows), each timed with HIP events after warm-up.
+    Working sets from 0.4 GB (partly held by the 256 MB last-level cache) to 12.9 GB (not)."""
+    dev = torch.device("cuda:0")
+    wl = inp.RNS64Workload()
+    ctxs = [mg.setup(N, 64) for N in wl.moduli]
+    c32 = mg.setup(8380417, 32)
+    res = {}
+    for lg in range(24, 30):
+        E = 1 << lg
+        row = {"bytes_per_launch": 24 * E}
+        # 64-bit RNS product: 8 rows of E/8 residues below 2^59 (every modulus exceeds 2^59)
+        a = torch.randint(0, 1 << 59, (8, E // 8), dtype=torch.int64, device=dev).view(torch.uint64)
+        b = torch.randint(0, 1 << 59, (8, E // 8), dtype=torch.int64, device=dev).view(torch.uint64)
+        o = torch.empty_like(a)
+        _, ms = timed_sec(lambda: mg.mul_rns(ctxs, a, b, out=o), torch)
+        row["rns64_GB_s"] = round(24 * E / (ms * 1e-3) / 1e9, 1)
+        # the XOR reference over the same three buffers
+        _, ms = timed_sec(lambda: mg.stream_ref(a, b, o), torch)
+        row["xor_ref_GB_s"] = round(24 * E / (ms * 1e-3) / 1e9, 1)
+        del a, b, o
+        # 32-bit classic product over 2E residues below N = 8380417
+        a = torch.randint(0, 8380417, (2 * E,), dtype=torch.int32, device=dev).view(torch.uint32)
+        b = torch.randint(0, 8380417, (2 * E,), dtype=torch.int32, device=dev).view(torch.uint32)
+        o = torch.empty_like(a)
+        _, ms = timed_sec(lambda: mg.mul(c32, a, b, out=o), torch)
+        row["r32_classic_GB_s"] = round(24 * E / (ms * 1e-3) / 1e9, 1)
+        del a, b, o
+        torch.cuda.empty_cache()
+        res["E2^%d" % lg] = row
+        log("ceiling 2^%d: %s" % (lg, row))
+    return res
 
 
 def secondary(torch, mg, inp, args, sections):
@@ -267,6 +303,8 @@ def secondary(torch, mg, inp, args, sections):
     ex = {}
     if "copy" in sections:
         ex["hbm_ceiling"] = copy_ceiling(torch)
+    if "ceiling" in sections:
+        ex["stream_by_size"] = ceiling(torch, mg, inp)
 
     if "r32" in sections:
         # 32-bit workload: N = 8380417, 2^26 residues, the variants at R = 2^32 (Plantard family 2^64)

@@ -72,6 +72,7 @@ typedef int32_t mont_status_t;
 #define MONT_E_NOMEM (-4)       /* library-owned device/host memory could not be allocated */
 #define MONT_E_DEVICE (-5)      /* HIP runtime error; see mont_last_error() */
 #define MONT_E_BUSY (-6)        /* resource held by another call (serving loop) */
+#define MONT_E_CANCELED (-7)    /* serving job cancelled before its launch */
 
 typedef enum {
     MONT_CLASSIC = 0,
@@ -365,9 +366,17 @@ mont_status_t mont_get_launch(uint32_t op, uint32_t w, mont_variant_t variant, m
  * operands and results fit a fixed device-memory budget, and fused into
  * ragged batches that run as one persistent launch each; up to `streams`
  * batches are in flight at once, so work that arrives while the device is
- * busy joins the next batch.  Per-modulus constants are cached on the host
- * and travel inside each batch's segment table.  A service thread does the
- * admission, copies, launches and completion polling.
+ * busy joins the next batch.  Per-modulus constants stay resident in a
+ * device table that the batches' segment descriptors index: a modulus's
+ * constants are computed and uploaded once, when it is first seen (or seen
+ * again after its entry was reused for another modulus).  A service thread
+ * does the admission, copies, launches and completion polling.
+ *
+ * A batch not finished deadline_us after its launch is given up: its jobs
+ * complete with MONT_E_DEVICE, the stream is replaced by a new one, and the
+ * batch's device memory stays reserved until the abandoned work is seen to
+ * end (a stream that cannot be replaced leaves service; with none left,
+ * every waiting job completes with MONT_E_DEVICE).
  */
 typedef struct mont_server mont_server_t;
 
@@ -378,6 +387,8 @@ typedef struct mont_server_cfg {
     uint32_t streams;            /* batches in flight, one HIP stream each (0: 3) */
     uint32_t max_batch_jobs;     /* jobs fused into one launch (0: 512) */
     uint32_t tile_elems;         /* 32-bit product tile in elements (0: 8192) */
+    uint32_t deadline_us;        /* per-batch completion deadline, microseconds (0: 30 s) */
+    uint32_t reserved;
 } mont_server_cfg_t;
 
 typedef struct mont_job {
@@ -394,7 +405,8 @@ typedef struct mont_job {
 
 typedef struct mont_completion {
     uint64_t id;
-    int32_t status;  /* MONT_OK, or MONT_E_DEVICE if the batch failed */
+    int32_t status;  /* MONT_OK; MONT_E_DEVICE if the batch failed or missed its deadline;
+                        MONT_E_CANCELED after mont_serve_cancel */
     uint32_t reserved;
     double t_submit; /* mont_serve_now() clock, seconds */
     double t_admit;  /* device memory reserved */
@@ -407,6 +419,12 @@ typedef struct mont_server_stats {
     uint64_t queued, staged, in_flight;
     uint64_t bytes_in_use, peak_bytes_in_use;
     uint64_t enqueue_ns; /* service-thread time spent enqueueing batches (copies, tables, launch) */
+    uint64_t canceled;   /* jobs completed by mont_serve_cancel */
+    uint64_t timed_out;  /* jobs of batches that missed the deadline */
+    uint64_t quarantined_bytes; /* device memory of abandoned batches not yet seen to end */
+    uint64_t dead_streams;      /* streams that could not be replaced */
+    uint64_t ctx_uploads;       /* per-modulus constant entries uploaded to the resident table */
+    uint64_t ctx_hits;          /* jobs whose modulus was already resident */
 } mont_server_stats_t;
 
 /* Allocates the device arena and starts the service thread on the current device. */
@@ -432,6 +450,13 @@ int64_t mont_serve_poll(mont_server_t *s, mont_completion_t *out, uint32_t max, 
  * MONT_E_BUSY on timeout. */
 mont_status_t mont_serve_drain(mont_server_t *s, int32_t timeout_ms);
 mont_status_t mont_serve_stats(const mont_server_t *s, mont_server_stats_t *st);
+/* Cancels the job with this id if it has not been launched yet (still queued,
+ * or admitted and waiting for a launch slot): it completes with
+ * MONT_E_CANCELED, its device memory is released and its out buffer is not
+ * written.  MONT_E_BUSY if it is in a launched batch (it completes normally),
+ * MONT_E_INVAL if no job with this id is waiting.  Blocks until the service
+ * thread has handled the request. */
+mont_status_t mont_serve_cancel(mont_server_t *s, uint64_t id);
 double mont_serve_now(void);
 /* Stops the service thread after in-flight batches finish and frees the arena. */
 void mont_serve_destroy(mont_server_t *s);

@@ -28,7 +28,8 @@ OP_MUL, OP_REDC, OP_POW = 0, 1, 2
 BATCH_GRAPH, BATCH_DYNAMIC, BATCH_TUNE, BATCH_NONTEMPORAL = 1, 2, 4, 8
 
 STATUS = {0: "MONT_OK", -1: "MONT_E_INVAL", -2: "MONT_E_DOMAIN", -3: "MONT_E_UNSUPPORTED",
-          -4: "MONT_E_NOMEM", -5: "MONT_E_DEVICE", -6: "MONT_E_BUSY"}
+          -4: "MONT_E_NOMEM", -5: "MONT_E_DEVICE", -6: "MONT_E_BUSY", -7: "MONT_E_CANCELED"}
+E_INVAL, E_DEVICE, E_BUSY, E_CANCELED = -1, -5, -6, -7
 
 
 class MontError(RuntimeError):
@@ -437,7 +438,8 @@ def as_numpy_u64(t) -> np.ndarray:
 
 class ServerCfgStruct(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_jobs_in_flight", ctypes.c_uint32),
-                ("streams", ctypes.c_uint32), ("max_batch_jobs", ctypes.c_uint32), ("tile_elems", ctypes.c_uint32)]
+                ("streams", ctypes.c_uint32), ("max_batch_jobs", ctypes.c_uint32), ("tile_elems", ctypes.c_uint32),
+                ("deadline_us", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class JobStruct(ctypes.Structure):
@@ -454,7 +456,8 @@ class CompletionStruct(ctypes.Structure):
 class ServerStatsStruct(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in ("submitted", "completed", "rejected", "launches", "jobs_launched",
                                                  "queued", "staged", "in_flight", "bytes_in_use",
-                                                 "peak_bytes_in_use", "enqueue_ns")]
+                                                 "peak_bytes_in_use", "enqueue_ns", "canceled", "timed_out",
+                                                 "quarantined_bytes", "dead_streams", "ctx_uploads", "ctx_hits")]
 
 
 _SERVE_SIG = {
@@ -469,6 +472,7 @@ _SERVE_SIG = {
     "mont_serve_now": (ctypes.c_double, []),
     "mont_serve_host_region": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "mont_serve_destroy": (None, [ctypes.c_void_p]),
+    "mont_serve_cancel": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64]),
 }
 
 
@@ -498,9 +502,10 @@ class Server:
     """The continuous-batching request loop (mont_serve_*)."""
 
     def __init__(self, hbm_budget_bytes=8 << 30, max_jobs_in_flight=4096, streams=3, max_batch_jobs=512,
-                 tile_elems=0):
+                 tile_elems=0, deadline_us=0):
         lib = _serve_lib()
-        cfg = ServerCfgStruct(hbm_budget_bytes, max_jobs_in_flight, streams, max_batch_jobs, tile_elems)
+        cfg = ServerCfgStruct(hbm_budget_bytes, max_jobs_in_flight, streams, max_batch_jobs, tile_elems,
+                              deadline_us, 0)
         self.h = ctypes.c_void_p()
         check(lib.mont_serve_create(ctypes.byref(cfg), ctypes.byref(self.h)))
         self._keep = {}
@@ -544,6 +549,13 @@ class Server:
             self._keep.pop(c.id, None)
             out.append((c.id, c.status, c.t_submit, c.t_admit, c.t_launch, c.t_done))
         return out
+
+    def cancel(self, id_) -> int:
+        """mont_serve_cancel: 0 (cancelled), E_BUSY (already launched) or E_INVAL (not waiting)."""
+        rc = int(_serve_lib().mont_serve_cancel(self.h, id_))
+        if rc not in (0, E_BUSY, E_INVAL):
+            check(rc)
+        return rc
 
     def drain(self, timeout_ms=-1):
         check(_serve_lib().mont_serve_drain(self.h, timeout_ms))

@@ -177,8 +177,8 @@ __device__ __forceinline__ void tile_width(uint32_t op, uint32_t variant, const 
 
 template <bool NT>
 __global__ void __launch_bounds__(BLOCK)
-    k_ragged(const DSeg *__restrict__ segs, const DTile *__restrict__ tiles, uint32_t ntiles, DPools P,
-             uint32_t *__restrict__ ctr, uint32_t dynamic)
+    k_ragged(const KCtx *__restrict__ ctab, const DSeg *__restrict__ segs, const DTile *__restrict__ tiles,
+             uint32_t ntiles, DPools P, uint32_t *__restrict__ ctr, uint32_t dynamic)
 {
     __shared__ uint32_t s_next[2];
     uint32_t t;
@@ -197,15 +197,16 @@ __global__ void __launch_bounds__(BLOCK)
             s_next[buf ^ 1] = atomicAdd(&ctr[0], 1u);  // fetch the next tile while this one runs
         const DTile td = tiles[t];
         const DSeg &sd = segs[td.seg];
+        const KCtx &kc = ctab[sd.ctx];
         const uint64_t g0 = sd.off + td.start;
         const uint64_t g1 = sd.off1 + td.start;
         const uint32_t wc = sd.wc;
         if (wc == 0)
-            tile_width<16, NT>(sd.op, sd.variant, sd.c, P, g0, g1, td.cnt);
+            tile_width<16, NT>(sd.op, sd.variant, kc, P, g0, g1, td.cnt);
         else if (wc == 1)
-            tile_width<32, NT>(sd.op, sd.variant, sd.c, P, g0, g1, td.cnt);
+            tile_width<32, NT>(sd.op, sd.variant, kc, P, g0, g1, td.cnt);
         else
-            tile_width<64, NT>(sd.op, sd.variant, sd.c, P, g0, g1, td.cnt);
+            tile_width<64, NT>(sd.op, sd.variant, kc, P, g0, g1, td.cnt);
         if (dynamic) {
             __syncthreads();  // s_next[buf^1] written; everyone done with s_next[buf]
             buf ^= 1;
@@ -241,6 +242,7 @@ struct mont_batch {
     std::vector<mont_seg_t> segs;
     std::vector<DSeg> hsegs;
     DSeg *dsegs = nullptr;
+    KCtx *dctx = nullptr;        // the batch's per-modulus constants, indexed by the segments
     DTile *dtiles = nullptr;
     uint32_t *dctr = nullptr;
     size_t tiles_cap = 0;
@@ -286,7 +288,7 @@ mont_status_t make_dseg(const mont_ctx_t *ctxs, uint32_t nctx, const mont_seg_t 
     if (rc)
         return rc;
     std::memset(&d, 0, sizeof d);
-    d.c = to_kctx(ctxs[sg.ctx]);
+    d.ctx = sg.ctx;
     d.off = sg.off;
     d.off1 = sg.off1;
     d.op = sg.op;
@@ -409,30 +411,31 @@ static mont_status_t check_pools(const mont_batch &b, const mont_pools_t *p)
 
 void *ragged_kernel_ptr(bool nt) { return nt ? (void *)k_ragged<true> : (void *)k_ragged<false>; }
 
-hipError_t launch_ragged(const DSeg *segs, const DTile *tiles, uint32_t ntiles, const DPools &P, uint32_t *ctr,
-                         uint32_t dyn, uint32_t grid, bool nt, hipStream_t s)
+hipError_t launch_ragged(const KCtx *ctab, const DSeg *segs, const DTile *tiles, uint32_t ntiles, const DPools &P,
+                         uint32_t *ctr, uint32_t dyn, uint32_t grid, bool nt, hipStream_t s)
 {
     if (nt)
-        hipLaunchKernelGGL(k_ragged<true>, dim3(grid), dim3(BLOCK), 0, s, segs, tiles, ntiles, P, ctr, dyn);
+        hipLaunchKernelGGL(k_ragged<true>, dim3(grid), dim3(BLOCK), 0, s, ctab, segs, tiles, ntiles, P, ctr, dyn);
     else
-        hipLaunchKernelGGL(k_ragged<false>, dim3(grid), dim3(BLOCK), 0, s, segs, tiles, ntiles, P, ctr, dyn);
+        hipLaunchKernelGGL(k_ragged<false>, dim3(grid), dim3(BLOCK), 0, s, ctab, segs, tiles, ntiles, P, ctr, dyn);
     return hipGetLastError();
 }
 
 static mont_status_t launch_direct(mont_batch &b, const DPools &P, hipStream_t s, uint32_t dyn)
 {
-    const hipError_t e = launch_ragged(b.dsegs, b.dtiles, b.ntiles, P, b.dctr, dyn, b.grid, b.nt, s);
+    const hipError_t e = launch_ragged(b.dctx, b.dsegs, b.dtiles, b.ntiles, P, b.dctr, dyn, b.grid, b.nt, s);
     return e == hipSuccess ? MONT_OK : hip_fail(e, "ragged launch");
 }
 
 static mont_status_t launch_graph(mont_batch &b, const DPools &P, hipStream_t s, uint32_t dyn)
 {
     DPools Pc = P;
+    KCtx *ctab = b.dctx;
     DSeg *segs = b.dsegs;
     DTile *tiles = b.dtiles;
     uint32_t nt = b.ntiles;
     uint32_t *ctr = b.dctr;
-    void *args[] = {&segs, &tiles, &nt, &Pc, &ctr, &dyn};
+    void *args[] = {&ctab, &segs, &tiles, &nt, &Pc, &ctr, &dyn};
     hipKernelNodeParams kp{};
     kp.func = ragged_kernel_ptr(b.nt);
     kp.gridDim = dim3(b.grid);
@@ -669,13 +672,22 @@ mont_status_t mont_batch_create(const mont_ctx_t *ctxs, uint32_t nctx, const mon
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMalloc(&b->dsegs, std::max<size_t>(nseg, 1) * sizeof(DSeg));
     if (e == hipSuccess)
+        e = hipMalloc(&b->dctx, std::max<size_t>(nctx, 1) * sizeof(KCtx));
+    if (e == hipSuccess)
         e = hipMalloc(&b->dctr, 64);
     if (e != hipSuccess) {
         mont_batch_destroy(b);
         return fail(MONT_E_NOMEM, "batch tables");
     }
+    std::vector<KCtx> kctx(nctx);
+    for (uint32_t i = 0; i < nctx; ++i)
+        kctx[i] = to_kctx(ctxs[i]);
     if (nseg)
         e = hipMemcpyAsync(b->dsegs, b->hsegs.data(), nseg * sizeof(DSeg), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && nctx)
+        e = hipMemcpyAsync(b->dctx, kctx.data(), nctx * sizeof(KCtx), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);  // the host tables die here
     if (e == hipSuccess)
         e = hipMemsetAsync(b->dctr, 0, 64, s);
     if (e != hipSuccess) {
@@ -815,6 +827,8 @@ void mont_batch_destroy(mont_batch_t *b)
         (void)hipGraphDestroy(b->graph);
     if (b->dsegs)
         (void)hipFree(b->dsegs);
+    if (b->dctx)
+        (void)hipFree(b->dctx);
     if (b->dtiles)
         (void)hipFree(b->dtiles);
     if (b->dctr)

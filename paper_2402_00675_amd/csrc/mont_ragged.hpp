@@ -8,15 +8,14 @@
 namespace mont {
 
 struct DSeg {
-    KCtx c;          // 64 B
     uint64_t off;    // element offset of in0 / out in the pools of its width
     uint64_t off1;   // element offset of in1 (b as w-bit elements; exponents as uint64)
     uint32_t op;
     uint32_t variant;
     uint32_t wc;     // width class 0/1/2 = 16/32/64 bits
-    uint32_t pad;
+    uint32_t ctx;    // index of the segment's constants in the launch's KCtx table
 };
-static_assert(sizeof(DSeg) == 96, "segment descriptor layout");
+static_assert(sizeof(DSeg) == 32, "segment descriptor layout");
 
 struct DTile {
     uint32_t seg;
@@ -30,11 +29,11 @@ struct DPools {
     void *out[3];
 };
 
-// One persistent launch over `ntiles` tiles (ctr: two zeroed uint32 that the
-// kernel leaves zeroed again when dyn = 1).
-// nt selects non-temporal loads and stores.
-hipError_t launch_ragged(const DSeg *segs, const DTile *tiles, uint32_t ntiles, const DPools &P, uint32_t *ctr,
-                         uint32_t dyn, uint32_t grid, bool nt, hipStream_t s);
+// One persistent launch over `ntiles` tiles; segment i reduces with the
+// constants ctab[segs[i].ctx] (ctr: two zeroed uint32 that the kernel leaves
+// zeroed again when dyn = 1).  nt selects non-temporal loads and stores.
+hipError_t launch_ragged(const KCtx *ctab, const DSeg *segs, const DTile *tiles, uint32_t ntiles, const DPools &P,
+                         uint32_t *ctr, uint32_t dyn, uint32_t grid, bool nt, hipStream_t s);
 void *ragged_kernel_ptr(bool nt);
 
 // Validates segment i of a batch (context index, op, variant, sizes, operand

@@ -14,6 +14,15 @@
 // behind it, so large jobs cannot starve); admitted jobs are fused into one
 // batch as soon as a launch slot is free; up to `slots` batches are in flight
 // at once, so jobs arriving while the device is busy join the next batch.
+//
+// Robustness: a batch not finished `deadline_s` after its launch is given up:
+// its jobs complete with E_DEVICE at once, the backend retires the slot's
+// stream (fresh resources take its place) and the batch's device memory stays
+// reserved ("quarantined") until the retired work is seen to finish, so no
+// later job is placed where a late kernel could still write.  A slot that
+// cannot be renewed leaves service; with no slot left every waiting job fails.
+// Jobs that are queued or admitted but not yet launched can be cancelled
+// (E_CANCELED); a launched job cannot (E_BUSY).
 #pragma once
 
 #include <algorithm>
@@ -27,7 +36,7 @@ namespace mont_sched {
 
 constexpr uint64_t ALIGN = 64;  // element slots; keeps every pool address 16-byte aligned
 
-enum { OK = 0, E_INVAL = -1, E_DOMAIN = -2, E_DEVICE = -5 };
+enum { OK = 0, E_INVAL = -1, E_DOMAIN = -2, E_DEVICE = -5, E_BUSY = -6, E_CANCELED = -7 };
 enum { OP_MUL = 0, OP_POW = 2 };
 
 class Arena {
@@ -114,18 +123,27 @@ class Backend {
     // 1: the slot's batch finished, 0: still running, < 0: failed.
     virtual int poll(int slot) = 0;
     virtual double now() = 0;
+    // The slot's batch missed its deadline: give the slot fresh resources and
+    // keep the old ones until that batch ends.  Returns a ticket (>= 0) for
+    // poll_retired, or < 0 when the slot cannot be renewed.
+    virtual int retire(int slot) = 0;
+    // 0 while the retired batch still runs; otherwise it has ended (1) or
+    // failed (< 0) and its resources are released.
+    virtual int poll_retired(int ticket) = 0;
 };
 
 struct Config {
     uint64_t cap[2] = {0, 0};  // element slots per class
     uint32_t max_in_flight = 4096;
     uint32_t max_batch_jobs = 512;
+    double deadline_s = 0;     // per-batch completion deadline (0: none)
 };
 
 struct Stats {
     uint64_t submitted = 0, completed = 0, rejected = 0, launches = 0, jobs_launched = 0;
     uint64_t used_slots[2] = {0, 0}, peak_slots[2] = {0, 0};
     uint64_t queued = 0, staged = 0, in_flight = 0;
+    uint64_t canceled = 0, timed_out = 0, quarantined_slots[2] = {0, 0}, dead_slots = 0;
 };
 
 class Scheduler {
@@ -135,6 +153,8 @@ class Scheduler {
         arena_[0].reset(c.cap[0]);
         arena_[1].reset(c.cap[1]);
         slot_jobs_.resize(b->slots());
+        slot_t_.assign(b->slots(), 0.0);
+        slot_dead_.assign(b->slots(), false);
     }
 
     // Validates and queues a job (n == 0 completes at once).
@@ -160,20 +180,74 @@ class Scheduler {
             finish(j, OK, be_->now());
             return OK;
         }
+        if (live_slots() == 0) {
+            ++st_.completed;
+            finish(j, E_DEVICE, be_->now());
+            return OK;
+        }
         queue_.push_back(j);
         return OK;
+    }
+
+    // Cancels job `id` if it has not been launched: OK (it completes with
+    // E_CANCELED), E_BUSY (it is in a launched batch) or E_INVAL (no such job
+    // is waiting).
+    int cancel(uint64_t id)
+    {
+        for (auto it = queue_.begin(); it != queue_.end(); ++it)
+            if (it->id == id) {
+                Job j = *it;
+                queue_.erase(it);
+                ++st_.completed;
+                ++st_.canceled;
+                finish(j, E_CANCELED, be_->now());
+                return OK;
+            }
+        for (auto it = staged_.begin(); it != staged_.end(); ++it)
+            if (it->id == id) {
+                Job j = *it;
+                staged_.erase(it);
+                arena_[j.cls].release(j.off, j.n);
+                --in_flight_;
+                ++st_.completed;
+                ++st_.canceled;
+                finish(j, E_CANCELED, be_->now());
+                return OK;
+            }
+        for (const auto &sj : slot_jobs_)
+            for (const Job &j : sj)
+                if (j.id == id)
+                    return E_BUSY;
+        return E_INVAL;
     }
 
     // One pass: collect finished batches, admit waiting jobs, launch a batch.
     bool step()
     {
         bool did = false;
+        for (size_t q = 0; q < quarantine_.size();) {
+            if (quarantine_[q].ticket < 0 || be_->poll_retired(quarantine_[q].ticket) == 0) {
+                ++q;
+                continue;
+            }
+            for (const Span &sp : quarantine_[q].spans) {
+                arena_[sp.cls].release(sp.off, sp.n);
+                quarantined_[sp.cls] -= Arena::span(sp.n);
+            }
+            quarantine_.erase(quarantine_.begin() + q);
+            did = true;
+        }
         for (size_t s = 0; s < slot_jobs_.size(); ++s) {
             if (slot_jobs_[s].empty())
                 continue;
             const int r = be_->poll((int)s);
-            if (r == 0)
+            if (r == 0) {
+                if (cfg_.deadline_s > 0 && be_->now() - slot_t_[s] > cfg_.deadline_s) {
+                    expire((int)s);
+                    did = true;
+                }
                 continue;
+            }
             const double t = be_->now();
             for (Job &j : slot_jobs_[s]) {
                 arena_[j.cls].release(j.off, j.n);
@@ -198,10 +272,27 @@ class Scheduler {
         }
         for (int k = 0; k < 2; ++k)
             st_.peak_slots[k] = std::max(st_.peak_slots[k], arena_[k].used());
+        if (live_slots() == 0 && (!queue_.empty() || !staged_.empty())) {
+            // no launch slot left: nothing waiting can run
+            const double t = be_->now();
+            for (Job &j : staged_) {
+                arena_[j.cls].release(j.off, j.n);
+                --in_flight_;
+                ++st_.completed;
+                finish(j, E_DEVICE, t);
+            }
+            staged_.clear();
+            for (Job &j : queue_) {
+                ++st_.completed;
+                finish(j, E_DEVICE, t);
+            }
+            queue_.clear();
+            did = true;
+        }
         if (!staged_.empty()) {
             int slot = -1;
             for (size_t s = 0; s < slot_jobs_.size(); ++s)
-                if (slot_jobs_[s].empty()) {
+                if (slot_jobs_[s].empty() && !slot_dead_[s]) {
                     slot = (int)s;
                     break;
                 }
@@ -213,6 +304,7 @@ class Scheduler {
                 std::vector<Job *> ptrs;
                 ptrs.reserve(sj.size());
                 const double t = be_->now();
+                slot_t_[slot] = t;
                 for (Job &j : sj) {
                     j.t_launch = t;
                     ptrs.push_back(&j);
@@ -246,6 +338,7 @@ class Scheduler {
     }
     size_t pending_completions() const { return done_.size(); }
 
+    // No job waits or runs (memory of retired batches may still be quarantined).
     bool idle() const
     {
         if (!queue_.empty() || !staged_.empty())
@@ -255,8 +348,12 @@ class Scheduler {
                 return false;
         return true;
     }
+    // Work on the device to poll: launched batches or retired ones still running.
     bool device_busy() const
     {
+        for (const Quarantine &q : quarantine_)
+            if (q.ticket >= 0)
+                return true;
         for (const auto &s : slot_jobs_)
             if (!s.empty())
                 return true;
@@ -271,11 +368,46 @@ class Scheduler {
         s.queued = queue_.size();
         s.staged = staged_.size();
         s.in_flight = in_flight_;
+        s.quarantined_slots[0] = quarantined_[0];
+        s.quarantined_slots[1] = quarantined_[1];
+        s.dead_slots = (uint64_t)std::count(slot_dead_.begin(), slot_dead_.end(), true);
         return s;
     }
     const Arena &arena(int k) const { return arena_[k]; }
 
   private:
+    struct Span {
+        uint32_t cls;
+        uint64_t off, n;
+    };
+    struct Quarantine {
+        int ticket;
+        std::vector<Span> spans;
+    };
+
+    int live_slots() const { return (int)std::count(slot_dead_.begin(), slot_dead_.end(), false); }
+
+    // Slot s's batch missed its deadline: its jobs fail now, its memory waits
+    // for the retired work to end (forever if the slot cannot be renewed).
+    void expire(int s)
+    {
+        const double t = be_->now();
+        Quarantine q;
+        for (Job &j : slot_jobs_[s]) {
+            q.spans.push_back({j.cls, j.off, j.n});
+            quarantined_[j.cls] += Arena::span(j.n);
+            --in_flight_;
+            ++st_.completed;
+            ++st_.timed_out;
+            finish(j, E_DEVICE, t);
+        }
+        slot_jobs_[s].clear();
+        q.ticket = be_->retire(s);
+        if (q.ticket < 0)
+            slot_dead_[s] = true;
+        quarantine_.push_back(std::move(q));
+    }
+
     void finish(Job &j, int status, double t)
     {
         j.status = status;
@@ -289,6 +421,10 @@ class Scheduler {
     std::deque<Job> queue_;
     std::vector<Job> staged_;
     std::vector<std::vector<Job>> slot_jobs_;
+    std::vector<double> slot_t_;  // launch time of the slot's batch
+    std::vector<bool> slot_dead_;
+    std::vector<Quarantine> quarantine_;
+    uint64_t quarantined_[2] = {0, 0};
     std::deque<Completion> done_;
     uint64_t in_flight_ = 0;
     Stats st_;

@@ -13,14 +13,25 @@
 // device copies of them, a self-resetting tile counter and a completion
 // event; a slot is reused only after its event fired.
 //
+// Per-modulus constants are resident: one device table of KCtx entries that
+// the segment descriptors index.  A modulus's entry is computed and
+// installed (by a small kernel, from the batch's staging upload) the first
+// time a batch needs it; entries used by launched batches are pinned by
+// reference counts, unpinned ones stay cached and the least recently used is
+// reused when the table is full.  Installs happen on the installing batch's
+// stream ahead of its other work and are followed by an event that every
+// later batch's stream waits for, so no kernel reads an entry before it is
+// written; a pinned entry is never rewritten.
+//
 // Staging.  A job whose host buffers lie in a region the caller declared as
 // pinned, device-mapped host memory (mont_serve_host_region, verified with
 // hipPointerGetAttributes) is copied into the arena and back by two copy
 // kernels per batch that read and write host memory through its device
 // mapping: one launch for all of a batch's inputs and one for all its
 // results, instead of three DMA copies per job.  Other buffers take
-// hipMemcpyAsync.  Per batch the stream runs: DMA inputs, one table upload,
-// gather kernel, ragged kernel, scatter kernel, DMA results, event.
+// hipMemcpyAsync.  Per batch the stream runs: one table upload, a wait for
+// the latest constant install, this batch's installs, DMA inputs, gather
+// kernel, ragged kernel, scatter kernel, DMA results, event.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,7 +40,9 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
+#include <set>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -94,9 +107,19 @@ __global__ void __launch_bounds__(BLOCK) k_xfer(const XDesc *__restrict__ d, con
     }
 }
 
+// Writes new resident constant entries: tab[idx[i]] = src[i].
+__global__ void __launch_bounds__(BLOCK) k_install(KCtx *__restrict__ tab, const KCtx *__restrict__ src,
+                                                   const uint32_t *__restrict__ idx, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i < n)
+        tab[idx[i]] = src[i];
+}
+
 struct ServeSlot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    std::vector<uint32_t> pinned;     // resident constant entries its batch uses
     unsigned char *hstage = nullptr;  // pinned: [segs][tiles][xin desc][xin tiles][xout desc][xout tiles]
     unsigned char *dstage = nullptr;  // device copy
     size_t stage_cap = 0;
@@ -114,7 +137,24 @@ class GpuBackend : public mont_sched::Backend {
     void *in0[2] = {nullptr, nullptr}, *in1[2] = {nullptr, nullptr}, *out[2] = {nullptr, nullptr};
     std::vector<ServeSlot> slot;
     uint32_t tile_base = 8192, pow_tile = 1024, grid_max = 0;
-    std::unordered_map<uint64_t, mont_ctx_t> ctx_cache[2];
+    // resident constants
+    KCtx *dctab = nullptr;
+    struct CEnt {
+        uint64_t N = 0;
+        uint32_t cls = 0, refs = 0;
+        uint64_t tick = 0;
+        bool used = false;
+    };
+    std::vector<CEnt> cent;
+    std::unordered_map<uint64_t, uint32_t> cidx[2];  // N -> entry, per word-size class
+    std::vector<uint32_t> cfree;
+    std::set<std::pair<uint64_t, uint32_t>> clru;  // (last use, entry) of unpinned entries
+    uint64_t ctick = 0;
+    hipEvent_t tab_ev = nullptr;  // recorded after the latest install
+    bool tab_ev_valid = false;
+    std::vector<KCtx> newc;
+    std::vector<uint32_t> newi;
+    std::atomic<uint64_t> ctx_uploads{0}, ctx_hits{0};
     // scratch for building a batch's tables
     std::vector<DTile> tiles;
     std::vector<XDesc> xin, xout;
@@ -186,23 +226,88 @@ class GpuBackend : public mont_sched::Backend {
         if (c.tile_elems)
             tile_base = c.tile_elems;
         grid_max = (uint32_t)device_cus() * 8;
+        // every in-flight job pins at most one entry; batches abandoned at their
+        // deadline keep theirs until they end, hence the margin
+        const uint32_t ncent = 2 * c.max_jobs_in_flight + 65536;
+        if (hipMalloc(&dctab, (size_t)ncent * sizeof(KCtx)) != hipSuccess)
+            return fail(MONT_E_NOMEM, "resident constant table");
+        cent.resize(ncent);
+        cfree.reserve(ncent);
+        for (uint32_t i = ncent; i-- > 0;)
+            cfree.push_back(i);
+        if (hipEventCreateWithFlags(&tab_ev, hipEventDisableTiming) != hipSuccess)
+            return fail(MONT_E_DEVICE, "table event");
         slot.resize(nslots);
         const size_t max_jobs = c.max_batch_jobs;
-        for (ServeSlot &s : slot) {
-            hipError_t e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
-            if (e == hipSuccess)
-                e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
-            if (e == hipSuccess)
-                e = hipMalloc(&s.dctr, 64);
-            if (e == hipSuccess)
-                e = hipMemset(s.dctr, 0, 64);
-            if (e != hipSuccess)
-                return hip_fail(e, "serving slot");
-            mont_status_t rc = reserve(s, max_jobs * (sizeof(DSeg) + 64 * sizeof(DTile) + 96 * sizeof(XDesc)));
-            if (rc)
+        for (ServeSlot &s : slot)
+            if (mont_status_t rc = make_slot(s, max_jobs * (sizeof(KCtx) + 4 + sizeof(DSeg) + 64 * sizeof(DTile) +
+                                                            96 * sizeof(XDesc))))
                 return rc;
-        }
         return MONT_OK;
+    }
+
+    // A stream, completion event, tile counter and staging tables for one slot.
+    mont_status_t make_slot(ServeSlot &s, size_t stage_bytes)
+    {
+        hipError_t e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipMalloc(&s.dctr, 64);
+        if (e == hipSuccess)
+            e = hipMemsetAsync(s.dctr, 0, 64, s.stream);
+        if (e != hipSuccess)
+            return hip_fail(e, "serving slot");
+        return reserve(s, stage_bytes);
+    }
+
+    // Releases a slot's resources; waits for its stream first.
+    static void free_slot(ServeSlot &s)
+    {
+        if (s.stream)
+            (void)hipStreamSynchronize(s.stream);
+        if (s.done)
+            (void)hipEventDestroy(s.done);
+        if (s.stream)
+            (void)hipStreamDestroy(s.stream);
+        if (s.hstage)
+            (void)hipHostFree(s.hstage);
+        if (s.dstage)
+            (void)hipFree(s.dstage);
+        if (s.dctr)
+            (void)hipFree(s.dctr);
+        s = ServeSlot{};
+    }
+
+    // Slots whose batch missed its deadline, kept until that batch ends.
+    std::map<int, ServeSlot> retired;
+    int next_ticket = 0;
+
+    int retire(int si) override
+    {
+        ServeSlot fresh;
+        if (make_slot(fresh, slot[si].stage_cap) != MONT_OK) {
+            free_slot(fresh);
+            return -1;
+        }
+        const int t = next_ticket++;
+        retired[t] = slot[si];
+        slot[si] = fresh;
+        return t;
+    }
+
+    int poll_retired(int t) override
+    {
+        auto it = retired.find(t);
+        if (it == retired.end())
+            return 1;
+        const hipError_t e = hipEventQuery(it->second.done);
+        if (e == hipErrorNotReady)
+            return 0;
+        unpin(it->second.pinned);
+        free_slot(it->second);
+        retired.erase(it);
+        return e == hipSuccess ? 1 : -1;
     }
 
     // Grows the slot's staging buffers (only while the slot is idle).
@@ -227,20 +332,14 @@ class GpuBackend : public mont_sched::Backend {
 
     ~GpuBackend() override
     {
-        for (ServeSlot &s : slot) {
-            if (s.stream)
-                (void)hipStreamSynchronize(s.stream);
-            if (s.done)
-                (void)hipEventDestroy(s.done);
-            if (s.stream)
-                (void)hipStreamDestroy(s.stream);
-            if (s.hstage)
-                (void)hipHostFree(s.hstage);
-            if (s.dstage)
-                (void)hipFree(s.dstage);
-            if (s.dctr)
-                (void)hipFree(s.dctr);
-        }
+        for (ServeSlot &s : slot)
+            free_slot(s);
+        for (auto &r : retired)
+            free_slot(r.second);
+        if (tab_ev)
+            (void)hipEventDestroy(tab_ev);
+        if (dctab)
+            (void)hipFree(dctab);
         for (int k = 0; k < 2; ++k) {
             if (in0[k])
                 (void)hipFree(in0[k]);
@@ -254,16 +353,52 @@ class GpuBackend : public mont_sched::Backend {
     int slots() const override { return (int)slot.size(); }
     double now() override { return now_s(); }
 
-    const mont_ctx_t *ctx_of(uint64_t N, uint32_t w)
+    // The resident entry of (N, w), pinned for the caller; a new entry's
+    // constants are queued in newc/newi for this batch's install.  -1 when
+    // every entry is pinned or the modulus is invalid.
+    int64_t acquire(uint64_t N, uint32_t w)
     {
-        auto &m = ctx_cache[w == 64 ? 1 : 0];
-        auto it = m.find(N);
-        if (it != m.end())
-            return &it->second;
+        const uint32_t k = w == 64 ? 1 : 0;
+        auto it = cidx[k].find(N);
+        if (it != cidx[k].end()) {
+            CEnt &e = cent[it->second];
+            if (e.refs++ == 0)
+                clru.erase({e.tick, it->second});
+            ++ctx_hits;
+            return it->second;
+        }
         mont_ctx_t c;
         if (setup_ctx(N, w, &c) != MONT_OK)
-            return nullptr;
-        return &m.emplace(N, c).first->second;
+            return -1;
+        uint32_t i;
+        if (!cfree.empty()) {
+            i = cfree.back();
+            cfree.pop_back();
+        } else if (!clru.empty()) {
+            i = clru.begin()->second;
+            clru.erase(clru.begin());
+            cidx[cent[i].cls].erase(cent[i].N);
+        } else {
+            return -1;
+        }
+        cent[i] = CEnt{N, k, 1, 0, true};
+        cidx[k][N] = i;
+        newc.push_back(to_kctx(c));
+        newi.push_back(i);
+        ++ctx_uploads;
+        return i;
+    }
+
+    void unpin(std::vector<uint32_t> &v)
+    {
+        for (uint32_t i : v) {
+            CEnt &e = cent[i];
+            if (--e.refs == 0) {
+                e.tick = ++ctick;
+                clru.insert({e.tick, i});
+            }
+        }
+        v.clear();
     }
 
     std::atomic<uint64_t> enqueue_ns{0};
@@ -285,6 +420,27 @@ class GpuBackend : public mont_sched::Backend {
     }
 
     int enqueue(int si, const std::vector<mont_sched::Job *> &jobs)
+    {
+        ServeSlot &s = slot[si];
+        newc.clear();
+        newi.clear();
+        s.pinned.clear();
+        for (const mont_sched::Job *jp : jobs) {
+            const int64_t ci = acquire(jp->N, jp->w);
+            if (ci < 0) {
+                unpin(s.pinned);
+                fail(MONT_E_NOMEM, "resident constant table full");
+                return -1;
+            }
+            s.pinned.push_back((uint32_t)ci);
+        }
+        const int rc = enqueue_pinned(si, jobs);
+        if (rc)
+            unpin(s.pinned);
+        return rc;
+    }
+
+    int enqueue_pinned(int si, const std::vector<mont_sched::Job *> &jobs)
     {
         ServeSlot &s = slot[si];
         tiles.clear();
@@ -330,7 +486,9 @@ class GpuBackend : public mont_sched::Backend {
         for (uint32_t d = 0; d < xout.size(); ++d)
             split(xtout, d, xout[d].words);
         // one packed table upload per batch
-        const size_t o_seg = 0;
+        const size_t o_newc = 0;
+        const size_t o_newi = up16(o_newc + newc.size() * sizeof(KCtx));
+        const size_t o_seg = up16(o_newi + newi.size() * sizeof(uint32_t));
         const size_t o_tile = up16(o_seg + jobs.size() * sizeof(DSeg));
         const size_t o_xin = up16(o_tile + tiles.size() * sizeof(DTile));
         const size_t o_xtin = up16(o_xin + xin.size() * sizeof(XDesc));
@@ -339,15 +497,14 @@ class GpuBackend : public mont_sched::Backend {
         const size_t total = up16(o_xtout + xtout.size() * sizeof(XTile));
         if (reserve(s, total))
             return -1;
+        std::memcpy(s.hstage + o_newc, newc.data(), newc.size() * sizeof(KCtx));
+        std::memcpy(s.hstage + o_newi, newi.data(), newi.size() * sizeof(uint32_t));
         DSeg *hsegs = (DSeg *)(s.hstage + o_seg);
         for (uint32_t i = 0; i < jobs.size(); ++i) {
             const mont_sched::Job &j = *jobs[i];
-            const mont_ctx_t *c = ctx_of(j.N, j.w);
-            if (!c)
-                return -1;
             DSeg &d = hsegs[i];
             std::memset(&d, 0, sizeof d);
-            d.c = to_kctx(*c);
+            d.ctx = s.pinned[i];
             d.off = j.off;
             // in1 slot = 8 bytes: exponents index uint64 at off, products index w-bit b at off * 8 / es
             d.off1 = j.op == mont_sched::OP_POW ? j.off : j.off * (8 / es[j.cls]);
@@ -361,12 +518,24 @@ class GpuBackend : public mont_sched::Backend {
         std::memcpy(s.hstage + o_xout, xout.data(), xout.size() * sizeof(XDesc));
         std::memcpy(s.hstage + o_xtout, xtout.data(), xtout.size() * sizeof(XTile));
 
-        hipError_t e = hipSuccess;
+        // tables first, then the constants this batch installs (after every earlier
+        // install: the entries it reuses may have been installed by another stream)
+        hipError_t e = hipMemcpyAsync(s.dstage, s.hstage, total, hipMemcpyHostToDevice, s.stream);
+        if (e == hipSuccess && tab_ev_valid)
+            e = hipStreamWaitEvent(s.stream, tab_ev, 0);
+        if (e == hipSuccess && !newc.empty()) {
+            hipLaunchKernelGGL(k_install, dim3((unsigned)((newc.size() + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
+                               s.stream, dctab, (const KCtx *)(s.dstage + o_newc),
+                               (const uint32_t *)(s.dstage + o_newi), (uint32_t)newc.size());
+            e = hipGetLastError();
+            if (e == hipSuccess)
+                e = hipEventRecord(tab_ev, s.stream);
+            if (e == hipSuccess)
+                tab_ev_valid = true;
+        }
         for (const Dma &m : dma_in)
             if (e == hipSuccess)
                 e = hipMemcpyAsync(m.dst, m.src, m.bytes, hipMemcpyHostToDevice, s.stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(s.dstage, s.hstage, total, hipMemcpyHostToDevice, s.stream);
         if (e == hipSuccess && !xtin.empty()) {
             hipLaunchKernelGGL(k_xfer, dim3((unsigned)xtin.size()), dim3(BLOCK), 0, s.stream,
                                (const XDesc *)(s.dstage + o_xin), (const XTile *)(s.dstage + o_xtin),
@@ -382,7 +551,7 @@ class GpuBackend : public mont_sched::Backend {
             P.in1[2] = in1[1];
             P.out[2] = out[1];
             const uint32_t grid = (uint32_t)std::max<size_t>(1, std::min<size_t>(tiles.size(), grid_max));
-            e = launch_ragged((const DSeg *)(s.dstage + o_seg), (const DTile *)(s.dstage + o_tile),
+            e = launch_ragged(dctab, (const DSeg *)(s.dstage + o_seg), (const DTile *)(s.dstage + o_tile),
                               (uint32_t)tiles.size(), P, s.dctr, 1u, grid, true, s.stream);
         }
         if (e == hipSuccess && !xtout.empty()) {
@@ -406,17 +575,23 @@ class GpuBackend : public mont_sched::Backend {
     int poll(int si) override
     {
         const hipError_t e = hipEventQuery(slot[si].done);
-        if (e == hipSuccess)
-            return 1;
         if (e == hipErrorNotReady)
             return 0;
-        return -1;
+        unpin(slot[si].pinned);
+        return e == hipSuccess ? 1 : -1;
     }
 };
 
 }  // namespace mont
 
 using namespace mont;
+
+// A cancellation request handed to the service thread (which owns the scheduler).
+struct CancelReq {
+    uint64_t id;
+    mont_status_t result;
+    bool pending;
+};
 
 struct mont_server {
     GpuBackend *be = nullptr;
@@ -425,9 +600,10 @@ struct mont_server {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::vector<mont_sched::Job> inbox;
+    std::vector<CancelReq *> cancels;
     std::deque<mont_sched::Completion> outbox;
     bool stop = false;
-    uint64_t accepted = 0, finished = 0, rejected = 0;
+    uint64_t accepted = 0, finished = 0, rejected = 0, canceled_inbox = 0;
     mont_sched::Stats last{};
     uint64_t cap[2] = {0, 0};
     int dev = 0;
@@ -437,20 +613,29 @@ static void service(mont_server *S)
 {
     (void)hipSetDevice(S->dev);
     std::vector<mont_sched::Job> local;
+    std::vector<CancelReq *> creq;
     std::vector<mont_sched::Completion> comp(1024);
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            if (S->inbox.empty() && S->sched->idle() && S->sched->pending_completions() == 0) {
+            if (S->inbox.empty() && S->cancels.empty() && S->sched->idle() &&
+                S->sched->pending_completions() == 0) {
                 if (S->stop)
                     break;
-                S->cv_work.wait(lk, [S] { return S->stop || !S->inbox.empty(); });
+                auto ready = [S] { return S->stop || !S->inbox.empty() || !S->cancels.empty(); };
+                if (S->sched->device_busy())  // retired batches still running: keep polling them
+                    S->cv_work.wait_for(lk, std::chrono::milliseconds(1), ready);
+                else
+                    S->cv_work.wait(lk, ready);
             }
             local.swap(S->inbox);
+            creq.swap(S->cancels);
         }
         for (auto &j : local)
             S->sched->submit(j);
         local.clear();
+        for (CancelReq *r : creq)
+            r->result = S->sched->cancel(r->id);
         const bool did = S->sched->step();
         size_t k;
         {
@@ -459,8 +644,11 @@ static void service(mont_server *S)
                 S->outbox.insert(S->outbox.end(), comp.begin(), comp.begin() + k);
                 S->finished += k;
             }
+            for (CancelReq *r : creq)
+                r->pending = false;
             S->last = S->sched->stats();
         }
+        creq.clear();
         S->cv_done.notify_all();
         if (!did && S->sched->device_busy())
             std::this_thread::sleep_for(std::chrono::microseconds(20));
@@ -536,6 +724,7 @@ mont_status_t mont_serve_create(const mont_server_cfg_t *cfg, mont_server_t **ou
     sc.cap[1] = S->cap[1];
     sc.max_in_flight = c.max_jobs_in_flight;
     sc.max_batch_jobs = c.max_batch_jobs;
+    sc.deadline_s = (c.deadline_us ? c.deadline_us : 30000000u) * 1e-6;
     S->sched = new mont_sched::Scheduler(sc, S->be);
     S->th = std::thread(service, S);
     *out = S;
@@ -666,6 +855,40 @@ mont_status_t mont_serve_stats(const mont_server_t *S, mont_server_stats_t *st)
     st->bytes_in_use = x.used_slots[0] * 16 + x.used_slots[1] * 24;
     st->peak_bytes_in_use = x.peak_slots[0] * 16 + x.peak_slots[1] * 24;
     st->enqueue_ns = M->be->enqueue_ns.load();
+    st->canceled = x.canceled + M->canceled_inbox;
+    st->timed_out = x.timed_out;
+    st->quarantined_bytes = x.quarantined_slots[0] * 16 + x.quarantined_slots[1] * 24;
+    st->dead_streams = x.dead_slots;
+    st->ctx_uploads = M->be->ctx_uploads.load();
+    st->ctx_hits = M->be->ctx_hits.load();
+    return MONT_OK;
+}
+
+mont_status_t mont_serve_cancel(mont_server_t *S, uint64_t id)
+{
+    if (!S)
+        return fail(MONT_E_INVAL, "null server");
+    std::unique_lock<std::mutex> lk(S->mu);
+    // not yet seen by the service thread: complete it here
+    for (auto it = S->inbox.begin(); it != S->inbox.end(); ++it)
+        if (it->id == id) {
+            const double t = now_s();
+            S->outbox.push_back({it->id, MONT_E_CANCELED, it->t_submit, 0.0, 0.0, t});
+            S->inbox.erase(it);
+            ++S->finished;
+            ++S->canceled_inbox;
+            lk.unlock();
+            S->cv_done.notify_all();
+            return MONT_OK;
+        }
+    CancelReq r{id, MONT_OK, true};
+    S->cancels.push_back(&r);
+    S->cv_work.notify_one();
+    S->cv_done.wait(lk, [&r] { return !r.pending; });
+    if (r.result == mont_sched::E_BUSY)
+        return fail(MONT_E_BUSY, "job %llu is in a launched batch", (unsigned long long)id);
+    if (r.result != MONT_OK)
+        return fail(MONT_E_INVAL, "no job %llu is waiting", (unsigned long long)id);
     return MONT_OK;
 }
 

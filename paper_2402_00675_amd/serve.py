@@ -6,12 +6,17 @@ log-uniform lengths, each job with its own odd 31- or 62-bit modulus),
 replays it against a Server with native-clock arrivals, and summarises the
 completions as latency percentiles and throughput.
 
-Host staging: jobs read their operands from pinned host pools (values below
-every modulus of their class: [0, 2^30) for 31-bit and [0, 2^61) for 62-bit
-moduli; exponents uniform over 64 bits) at a seeded offset per job, and write
-results into pinned result buffers.  With ``distinct_outputs=False`` all jobs
-of a class share one result buffer (a sink), which keeps host memory bounded
-for 10^5-job streams while still copying every result back.
+Host staging: jobs read their operands from pinned host pools at a seeded
+offset per job, and write results into pinned result buffers.  Each word-size
+class splits its modulus range into POOL_BUCKETS equal intervals (31-bit
+moduli: [2^30, 2^31) in steps of 2^24; 62-bit: [2^61, 2^62) in steps of 2^55),
+and bucket k has its own operand pools drawn uniform in [0, L_k), L_k the
+bucket's lower end: every operand of a job is below its modulus N, and the
+operands cover [0, N) except its top N - L_k < 2^24 (2^55) values, i.e. more
+than 98 % of the residue range, top half included.  Exponents are uniform
+over 64 bits.  With ``distinct_outputs=False`` all jobs of a class share one
+result buffer (a sink), which keeps host memory bounded for 10^5-job streams
+while still copying every result back.
 """
 from __future__ import annotations
 
@@ -23,6 +28,20 @@ from . import _lib
 from . import inputs as inp
 
 POOL_SLACK = 1 << 16
+POOL_BUCKETS = 64
+CLASS_BITS = {32: 31, 64: 62}
+
+
+def bucket_of(N: int, w: int) -> int:
+    """The operand-pool bucket of a modulus of the 31-bit (w = 32) or 62-bit (w = 64) class."""
+    b = CLASS_BITS[w]
+    return (N - (1 << (b - 1))) >> (b - 1 - 6)
+
+
+def bucket_floor(k: int, w: int) -> int:
+    """L_k: the lower end of bucket k's modulus interval, the bound of its operand pools."""
+    b = CLASS_BITS[w]
+    return (1 << (b - 1)) + (k << (b - 1 - 6))
 
 
 def _pinned(torch, n, dtype):
@@ -44,14 +63,17 @@ class JobStream:
         self.njobs = njobs
         g = inp.rng(inp.W_SERVE, 100 + seed_rep)
         P = int(wl.hi) + POOL_SLACK
-        self.pool = {
-            32: (_pinned(torch, P, torch.uint32), _pinned(torch, P, torch.uint32)),
-            64: (_pinned(torch, P, torch.uint64), _pinned(torch, P, torch.uint64)),
-        }
-        self.pool[32][0].numpy()[:] = g.integers(0, 1 << 30, size=P, dtype=np.uint64).astype(np.uint32)
-        self.pool[32][1].numpy()[:] = g.integers(0, 1 << 30, size=P, dtype=np.uint64).astype(np.uint32)
-        self.pool[64][0].numpy()[:] = g.integers(0, 1 << 61, size=P, dtype=np.uint64)
-        self.pool[64][1].numpy()[:] = g.integers(0, 1 << 61, size=P, dtype=np.uint64)
+        # pool[w][k] = (a, b): operands of the jobs whose modulus lies in bucket k, uniform below L_k
+        self.bucket = [bucket_of(int(N), 64 if wd else 32) for N, wd in zip(mods, wide)]
+        self.pool = {}
+        for w, tdt, ndt in ((32, torch.uint32, np.uint32), (64, torch.uint64, np.uint64)):
+            self.pool[w] = []
+            for k in range(POOL_BUCKETS):
+                L = bucket_floor(k, w)
+                pair = (_pinned(torch, P, tdt), _pinned(torch, P, tdt))
+                for t in pair:
+                    t.numpy()[:] = g.integers(0, L, size=P, dtype=np.uint64).astype(ndt)
+                self.pool[w].append(pair)
         self.exps = _pinned(torch, P, torch.uint64)
         self.exps.numpy()[:] = inp.u64_uniform(g, P)
         offs = (seeds % POOL_SLACK).astype(np.int64)
@@ -73,7 +95,7 @@ class JobStream:
             w = 64 if wide[i] else 32
             n = int(lens[i])
             o = int(offs[i])
-            x, b = self.pool[w]
+            x, b = self.pool[w][self.bucket[i]]
             in0 = x.data_ptr() + o * esz[w]
             if ops[i] == 0:
                 op, in1 = _lib.OP_MUL, b.data_ptr() + o * esz[w]
@@ -91,7 +113,7 @@ class JobStream:
 
     def pinned_buffers(self):
         """Every pinned host buffer the stream's jobs read or write."""
-        bufs = [t for pair in self.pool.values() for t in pair] + [self.exps]
+        bufs = [t for pairs in self.pool.values() for pair in pairs for t in pair] + [self.exps]
         bufs += list(getattr(self, "sink", {}).values()) + list(self.arena.values())
         return bufs
 
@@ -107,9 +129,10 @@ class JobStream:
         """Host copies of job i's operands (for checking)."""
         w = 64 if self.wide[i] else 32
         n, o = int(self.lens[i]), int(self.offs[i])
-        x = self.pool[w][0].numpy()[o:o + n].copy()
+        a, b = self.pool[w][self.bucket[i]]
+        x = a.numpy()[o:o + n].copy()
         if self.ops[i] == 0:
-            return x, self.pool[w][1].numpy()[o:o + n].copy()
+            return x, b.numpy()[o:o + n].copy()
         return x, self.exps.numpy()[o:o + n].copy()
 
 

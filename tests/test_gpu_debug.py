@@ -158,7 +158,8 @@ def test_ragged_and_serving():
         mg.debug_violations(reset=True)
         stream = serve.JobStream(torch, njobs=40, seed_rep=9, distinct_outputs=True, hi=1 << 10)
         for w in (32, 64):   # every job's window holds some of these
-            stream.pool[w][0].numpy()[::101] = np.iinfo(np.uint32 if w == 32 else np.uint64).max
+            for a, _ in stream.pool[w]:
+                a.numpy()[::101] = np.iinfo(np.uint32 if w == 32 else np.uint64).max
         srv = mg.Server(hbm_budget_bytes=64 << 20, streams=2)
         try:
             done = serve.replay(srv, stream, np.zeros(stream.njobs))

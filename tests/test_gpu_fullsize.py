@@ -119,9 +119,13 @@ def test_serving_stream_every_job():
         stream.declare(srv)
         try:
             done = serve.replay(srv, stream, np.zeros(njobs))
+            st = srv.stats()
         finally:
             srv.close()
         assert len(done) == njobs and all(d[1] == 0 for d in done)
+        # one resident-constant upload per modulus seen, more moduli than the table holds
+        # (entries are reused), a hit for every other job
+        assert st["ctx_uploads"] + st["ctx_hits"] == njobs and st["ctx_uploads"] >= len(set(stream.mods))
 
         def job_ok(i):
             got = stream.outs[i].numpy()

@@ -100,3 +100,107 @@ def test_host_region_checks():
         assert np.array_equal(o.numpy(), want)
     finally:
         srv.close()
+
+
+def test_resident_constants_are_reused():
+    """Jobs that share a modulus reuse its resident constants: one upload per distinct modulus."""
+    stream = serve.JobStream(torch, njobs=200, seed_rep=5, distinct_outputs=True, hi=1 << 12)
+    mods = [int(m) for m in stream.mods]
+    shared = 0
+    for i in range(0, 200, 2):
+        # job i + 1 takes job i's modulus where its operands (drawn below its own bucket's
+        # floor) stay below that modulus
+        w = 64 if stream.wide[i] else 32
+        if bool(stream.wide[i]) == bool(stream.wide[i + 1]) and serve.bucket_floor(stream.bucket[i + 1], w) <= mods[i]:
+            mods[i + 1] = mods[i]
+            stream.jobs[i + 1].N = mods[i]
+            shared += 1
+    assert shared >= 10
+    stream.mods = mods
+    srv = mg.Server(hbm_budget_bytes=64 << 20, streams=2, max_batch_jobs=16)
+    stream.declare(srv)
+    try:
+        done = serve.replay(srv, stream, np.zeros(stream.njobs))
+        assert all(d[1] == 0 for d in done)
+        st = srv.stats()
+        distinct = len({(m, bool(w)) for m, w in zip(mods, stream.wide)})
+        assert st["ctx_uploads"] == distinct and st["ctx_uploads"] + st["ctx_hits"] == stream.njobs
+        for i in range(stream.njobs):
+            assert np.array_equal(stream.outs[i].numpy(), oracle_of(stream, i)), i
+        # the same stream again: every modulus is resident already
+        for i in range(stream.njobs):
+            stream.outs[i].zero_()
+        done = serve.replay(srv, stream, np.zeros(stream.njobs))
+        assert all(d[1] == 0 for d in done)
+        st2 = srv.stats()
+        assert st2["ctx_uploads"] == distinct and st2["ctx_hits"] == st["ctx_hits"] + stream.njobs
+        for i in range(0, stream.njobs, 3):
+            assert np.array_equal(stream.outs[i].numpy(), oracle_of(stream, i)), i
+    finally:
+        srv.close()
+
+
+def test_cancel_waiting_jobs():
+    """Jobs cancelled before their launch complete with MONT_E_CANCELED and leave their out
+    buffers untouched; the others complete exactly; memory returns to zero."""
+    stream = serve.JobStream(torch, njobs=240, seed_rep=6, distinct_outputs=True, hi=1 << 16)
+    for i in range(stream.njobs):
+        stream.outs[i].fill_(0x5A)          # every element 90, never a result here
+    srv = mg.Server(hbm_budget_bytes=32 << 20, streams=1, max_batch_jobs=8)
+    stream.declare(srv)
+    try:
+        for i in range(stream.njobs):
+            srv.submit_struct(stream.jobs[i])
+        rcs = {i: srv.cancel(i) for i in range(stream.njobs - 1, 0, -3)}
+        assert all(rc in (0, mg.E_BUSY, mg.E_INVAL) for rc in rcs.values())
+        canceled = {i for i, rc in rcs.items() if rc == 0}
+        assert len(canceled) > 20                   # most late jobs were still waiting
+        srv.drain(120_000)
+        got = {}
+        while len(got) < stream.njobs:
+            for d in srv.poll(4096, 100):
+                assert d[0] not in got
+                got[d[0]] = d[1]
+        for i in range(stream.njobs):
+            if i in canceled:
+                assert got[i] == mg.E_CANCELED
+                assert np.all(stream.outs[i].numpy() == 0x5A), i
+            else:
+                assert got[i] == 0
+                assert np.array_equal(stream.outs[i].numpy(), oracle_of(stream, i)), i
+        st = srv.stats()
+        assert st["canceled"] == len(canceled) and st["bytes_in_use"] == 0
+        assert srv.cancel(0) == mg.E_INVAL           # finished long ago
+    finally:
+        srv.close()
+
+
+def test_batch_deadline_gives_up_and_recovers_memory():
+    """With a 1 microsecond deadline nearly every batch is given up at its first poll: its jobs
+    complete with MONT_E_DEVICE, the stream is replaced, and the batch's memory stays reserved
+    until the abandoned work (which runs to its normal end here) is seen to finish.  Jobs that
+    did complete are exact."""
+    import time
+    stream = serve.JobStream(torch, njobs=120, seed_rep=7, distinct_outputs=True, hi=1 << 16)
+    srv = mg.Server(hbm_budget_bytes=64 << 20, streams=2, max_batch_jobs=8, deadline_us=1)
+    stream.declare(srv)
+    try:
+        done = serve.replay(srv, stream, np.zeros(stream.njobs))
+        status = {d[0]: d[1] for d in done}
+        assert set(status.values()) <= {0, mg.E_DEVICE}
+        st = srv.stats()
+        assert st["timed_out"] > 0 and st["timed_out"] == sum(v == mg.E_DEVICE for v in status.values())
+        for i, v in status.items():
+            if v == 0:
+                assert np.array_equal(stream.outs[i].numpy(), oracle_of(stream, i)), i
+        t0 = time.time()
+        while srv.stats()["quarantined_bytes"] and time.time() - t0 < 30:
+            time.sleep(0.01)
+        st = srv.stats()
+        assert st["quarantined_bytes"] == 0 and st["bytes_in_use"] == 0 and st["dead_streams"] == 0
+        # the abandoned batches ran to their end: their outputs are exact too
+        for i, v in status.items():
+            if v != 0:
+                assert np.array_equal(stream.outs[i].numpy(), oracle_of(stream, i)), i
+    finally:
+        srv.close()

@@ -18,7 +18,7 @@ SRC = os.path.join(ROOT, "tests", "native", "sched_sim.cpp")
 HDR = os.path.join(ROOT, "paper_2402_00675_amd", "csrc", "mont_sched.hpp")
 LIB = os.path.join(ROOT, "_build", "libsched_sim_ubsan.so")
 
-OK, E_INVAL, E_DOMAIN, E_DEVICE = 0, -1, -2, -5
+OK, E_INVAL, E_DOMAIN, E_DEVICE, E_BUSY, E_CANCELED = 0, -1, -2, -5, -6, -7
 MUL, POW = 0, 2
 ALIGN = 64
 
@@ -35,7 +35,13 @@ def build(lib_path, sanitize):
 def bind(L):
     vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
     L.sim_create.restype = vp
-    L.sim_create.argtypes = [u64, u64, u32, u32, i32]
+    L.sim_create.argtypes = [u64, u64, u32, u32, i32, ctypes.c_double]
+    L.sim_advance.argtypes = [vp, ctypes.c_double]
+    L.sim_cancel.argtypes = [vp, u64]
+    L.sim_fail_next_retire.argtypes = [vp]
+    L.sim_finish_retired.argtypes = [vp, i32, i32]
+    L.sim_retire_count.argtypes = [vp, i32]
+    L.sim_idle.argtypes = [vp]
     L.sim_submit.argtypes = [vp, u64, u64, u32, u32, u64]
     L.sim_step.argtypes = [vp]
     L.sim_finish_slot.argtypes = [vp, i32, i32]
@@ -56,11 +62,12 @@ def lib():
 
 class Sim:
     KEYS = ["submitted", "completed", "rejected", "launches", "jobs_launched", "used32", "used64", "peak32",
-            "peak64", "queued", "staged", "in_flight"]
+            "peak64", "queued", "staged", "in_flight", "canceled", "timed_out", "quarantined32", "quarantined64",
+            "dead_slots"]
 
-    def __init__(self, L, cap32=4096, cap64=4096, max_in_flight=1000, max_batch=100, slots=2):
+    def __init__(self, L, cap32=4096, cap64=4096, max_in_flight=1000, max_batch=100, slots=2, deadline=0.0):
         self.L = L
-        self.h = L.sim_create(cap32, cap64, max_in_flight, max_batch, slots)
+        self.h = L.sim_create(cap32, cap64, max_in_flight, max_batch, slots, deadline)
 
     def submit(self, id_, n, w=32, op=MUL, N=8380417):
         return self.L.sim_submit(self.h, id_, N, w, op, n)
@@ -83,8 +90,14 @@ class Sim:
         k = self.L.sim_slot_jobs(self.h, s, ids.ctypes.data, offs.ctypes.data, 10000)
         return ids[:k].tolist(), offs[:k].tolist()
 
+    def advance(self, dt):
+        self.L.sim_advance(self.h, dt)
+
+    def cancel(self, id_):
+        return self.L.sim_cancel(self.h, id_)
+
     def stats(self):
-        v = np.zeros(12, np.uint64)
+        v = np.zeros(len(self.KEYS), np.uint64)
         self.L.sim_stats(self.h, v.ctypes.data)
         return dict(zip(self.KEYS, v.tolist()))
 
@@ -260,6 +273,148 @@ def test_random_workload_accounting(lib):
     s.close()
 
 
+def test_deadline_quarantines_memory_until_the_retired_batch_ends(lib):
+    """A batch past its deadline fails at once with E_DEVICE; its slot is renewed; its memory is
+    released only when the retired work is seen to end, so no new job is placed under it."""
+    s = Sim(lib, cap32=1024, slots=1, deadline=5.0)
+    s.submit(1, 512)
+    s.step()
+    assert s.slot(0)[0] == [1]
+    s.advance(3.0)
+    s.step()
+    assert s.take() == {}                     # within the deadline
+    s.advance(3.0)
+    s.step()
+    assert s.take() == {1: E_DEVICE}
+    st = s.stats()
+    assert st["timed_out"] == 1 and st["quarantined32"] == 512 and st["used32"] == 512 and st["in_flight"] == 0
+    assert lib.sim_retire_count(s.h, 0) == 1
+    # the renewed slot serves new work, placed beside the quarantined span
+    s.submit(2, 512)
+    s.step()
+    ids, offs = s.slot(0)
+    assert ids == [2] and offs == [512]
+    s.submit(3, 100)                          # no room until the retired batch ends
+    s.step()
+    assert s.stats()["queued"] == 1
+    assert lib.sim_finish_retired(s.h, 0, 1) == 0
+    s.step()                                  # releases the quarantined span, admits job 3
+    st = s.stats()
+    assert st["quarantined32"] == 0 and st["used32"] == 512 + 128 and st["staged"] == 1
+    s.finish(0)
+    s.step()
+    s.finish(0)
+    s.step()
+    assert s.take() == {2: OK, 3: OK}
+    assert s.stats()["used32"] == 0
+    s.close()
+
+
+def test_failed_retired_batch_also_releases_memory(lib):
+    s = Sim(lib, cap32=4096, slots=2, deadline=1.0)
+    s.submit(1, 100)
+    s.step()
+    s.advance(2.0)
+    s.step()
+    assert s.take() == {1: E_DEVICE}
+    lib.sim_finish_retired(s.h, 0, -1)
+    s.step()
+    st = s.stats()
+    assert st["used32"] == 0 and st["quarantined32"] == 0
+    s.close()
+
+
+def test_slot_that_cannot_be_renewed_leaves_service(lib):
+    s = Sim(lib, cap32=4096, slots=2, deadline=1.0)
+    s.submit(1, 100)
+    s.step()
+    lib.sim_fail_next_retire(s.h)
+    s.advance(2.0)
+    s.step()
+    assert s.take() == {1: E_DEVICE} and s.stats()["dead_slots"] == 1
+    s.submit(2, 100)                          # served by the other slot
+    s.step()
+    assert s.slot(1)[0] == [2] and s.slot(0)[0] == [1]
+    s.finish(1)
+    s.step()
+    assert s.take() == {2: OK}
+    s.submit(3, 100)
+    s.step()
+    lib.sim_fail_next_retire(s.h)
+    s.advance(2.0)
+    s.step()                                  # the last slot dies too
+    assert s.take() == {3: E_DEVICE} and s.stats()["dead_slots"] == 2
+    assert s.submit(4, 100) == OK
+    s.step()
+    assert s.take() == {4: E_DEVICE}          # nothing can run any more
+    assert s.stats()["used32"] == 256         # the dead slots' memory (two 128-slot spans) stays reserved
+    s.close()
+
+
+def test_cancel_queued_staged_and_launched(lib):
+    s = Sim(lib, cap32=1024, slots=1, max_batch=1)
+    s.submit(1, 512)
+    s.submit(2, 256)
+    s.submit(3, 512)                          # does not fit: stays queued
+    s.step()                                  # 1 launched, 2 admitted (staged), 3 queued
+    st = s.stats()
+    assert st["staged"] == 1 and st["queued"] == 1
+    assert s.cancel(1) == E_BUSY
+    assert s.cancel(3) == OK
+    assert s.cancel(2) == OK
+    assert s.cancel(2) == E_INVAL and s.cancel(99) == E_INVAL
+    assert s.take() == {3: E_CANCELED, 2: E_CANCELED}
+    st = s.stats()
+    assert st["canceled"] == 2 and st["used32"] == 512 and st["queued"] == 0 and st["staged"] == 0
+    s.finish(0)
+    s.step()
+    assert s.take() == {1: OK}
+    assert s.stats()["used32"] == 0 and s.stats()["completed"] == 3
+    s.close()
+
+
+def test_random_workload_with_deadlines_and_cancels(lib):
+    """Random arrivals, completions, expiries, retired-batch ends and cancels: every job
+    finishes exactly once, and memory (quarantined included) returns to zero."""
+    rng = np.random.default_rng(11)
+    s = Sim(lib, cap32=1 << 17, cap64=1 << 16, max_in_flight=64, max_batch=16, slots=3, deadline=4.0)
+    nxt, seen, tickets = 0, {}, 0
+    for _ in range(3000):
+        for _ in range(int(rng.poisson(2))):
+            w = 64 if rng.uniform() < 0.5 else 32
+            s.submit(nxt, int(rng.integers(1, 20000)), w=w, N=(1 << 61) - 1 if w == 64 else 8380417)
+            nxt += 1
+        if nxt and rng.uniform() < 0.2:
+            s.cancel(int(rng.integers(0, nxt)))
+        s.advance(1.0)
+        s.step()
+        for sl in range(3):
+            if rng.uniform() < 0.2:
+                s.finish(sl)
+        for t in range(tickets + 8):
+            if rng.uniform() < 0.3:
+                lib.sim_finish_retired(s.h, t, 1)
+        tickets = int(s.stats()["timed_out"]) + 8
+        for k, v in s.take().items():
+            assert k not in seen
+            seen[k] = v
+    for _ in range(10000):
+        for sl in range(3):
+            s.finish(sl)
+        for t in range(tickets + 3000):
+            lib.sim_finish_retired(s.h, t, 1)
+        s.advance(0.5)
+        s.step()
+        seen.update(s.take())
+        if len(seen) == nxt and s.stats()["quarantined32"] == 0 and s.stats()["quarantined64"] == 0:
+            break
+    st = s.stats()
+    assert len(seen) == nxt and set(seen.values()) <= {OK, E_DEVICE, E_CANCELED}
+    assert st["timed_out"] > 0 and st["canceled"] > 0
+    assert st["used32"] == 0 and st["used64"] == 0 and st["completed"] == nxt
+    s.close()
+
+
 ASAN_SCRIPT = """
 import ctypes, sys
 sys.path.insert(0, %r)
@@ -268,6 +423,9 @@ L = t.bind(ctypes.CDLL(%r))
 t.test_random_workload_accounting(L)
 t.test_fragmented_arena_coalesces(L)
 t.test_launch_and_device_failures_release_memory(L)
+t.test_random_workload_with_deadlines_and_cancels(L)
+t.test_deadline_quarantines_memory_until_the_retired_batch_ends(L)
+t.test_cancel_queued_staged_and_launched(L)
 print("asan-ok")
 """
 
