@@ -19,7 +19,7 @@ Operations (all in HIP kernels of libmont.so, called through its C ABI):
 """
 from ._lib import (  # noqa: F401
     BATCH_DYNAMIC, BATCH_GRAPH, BATCH_NONTEMPORAL, BATCH_TUNE, CLASSIC, E_BUSY, E_CANCELED, E_DEVICE, E_INVAL, OP_MUL, OP_POW, OP_REDC, PLANTARD, SIGNED,
-    SIGNED_PLANTARD, SIGNED_PLANTARD_ALPHA, VARIANTS, Batch, Ctx, MontError, elem_dtype, get_launch,
+    SIGNED_PLANTARD, SIGNED_PLANTARD_ALPHA, VARIANTS, Batch, Ctx, MontError, batch_run_noalloc, elem_dtype, get_launch,
     Server, crt, debug_violations, header_functions, library, load, mul, mul_const, mul_rns, ntt, pools, pow,
     redc, redc_range, set_launch, setup, stream_ref, tune_mul, valu_ref, version,
 )

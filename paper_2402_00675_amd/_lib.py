@@ -133,6 +133,7 @@ def _open(path: str):
         "mont_batch_info": (i32, [vp, P(BatchInfoStruct)]),
         "mont_batch_set_shape": (i32, [vp, P(BatchShapeStruct), vp]),
         "mont_batch_destroy": (None, [vp]),
+        "mont_batch_run_noalloc": (i32, [P(CtxStruct), u32, P(SegStruct), u32, P(PoolsStruct), u32, vp]),
         "mont_tune_mul": (i32, [P(CtxStruct), vp, vp, vp, sz, i32, P(LaunchStruct), vp]),
         "mont_set_launch": (i32, [u32, u32, i32, P(LaunchStruct)]),
         "mont_get_launch": (i32, [u32, u32, i32, P(LaunchStruct)]),
@@ -426,6 +427,23 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def _seg_array(segs):
+    sa = (SegStruct * max(len(segs), 1))()
+    for i, sg in enumerate(segs):
+        ci, op, var, n, off = sg[:5]
+        off1 = sg[5] if len(sg) > 5 else off
+        sa[i].ctx, sa[i].op, sa[i].variant, sa[i].n, sa[i].off, sa[i].off1 = ci, op, variant_id(var), n, off, off1
+    return sa
+
+
+def batch_run_noalloc(ctxs, segs, p: PoolsStruct, tile_elems=0, stream=None):
+    """mont_batch_run_noalloc: one ragged launch over segs (tuples as for Batch) with no device
+    allocation (the tables go to the library's fixed device array)."""
+    arr = (CtxStruct * max(len(ctxs), 1))(*[c.s for c in ctxs])
+    check(load().mont_batch_run_noalloc(arr, len(ctxs), _seg_array(segs), len(segs), ctypes.byref(p), tile_elems,
+                                        _stream(stream)))
 
 
 def as_numpy_u64(t) -> np.ndarray:

@@ -34,13 +34,14 @@ SOURCES = [
     "mont_setup.cpp",
     "mont_serve.cpp",
     "mont_tunecache.cpp",
+    "mont_noalloc.hip",
 ]
 
 # The MONT_DEBUG library: these sources again with -DMONT_DEBUG (precondition
 # counters ahead of every call), the rest shared with the release build.
 LIB_DEBUG = os.path.join(PKG, "libmont_debug.so")
 DEBUG_SOURCES = ["mont_capi.cpp", "mont_ragged.hip", "mont_crt.hip", "mont_ntt.hip", "mont_serve.cpp",
-                 "mont_debug.hip"]
+                 "mont_noalloc.hip", "mont_debug.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = [

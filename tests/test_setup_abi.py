@@ -125,3 +125,18 @@ def test_batch_validation_errors():
     with pytest.raises(mg.MontError) as e:
         mg.Batch([c32], [(0, mg.OP_POW, "signed", 10, 0)])     # pow is classic only
     assert e.value.code == -3
+
+
+def test_noalloc_rejects_oversized_tables_before_device_use():
+    """mont_batch_run_noalloc refuses tables larger than its fixed device array with
+    MONT_E_INVAL before any device call (the pool addresses are never touched)."""
+    c = mg.setup(8380417, 32)
+    p = _lib.PoolsStruct()
+    for i in range(3):
+        p.in0[i] = p.in1[i] = p.out[i] = 0x10000 * (i + 1)
+    with pytest.raises(mg.MontError) as e:
+        mg.batch_run_noalloc([c], [(0, mg.OP_MUL, "classic", 1 << 30, 0)], p, tile_elems=256)
+    assert e.value.code == -1 and "scratch" in str(e.value)
+    with pytest.raises(mg.MontError) as e:
+        mg.batch_run_noalloc([c], [(0, mg.OP_MUL, "classic", 10, 0)], p, tile_elems=1000)
+    assert e.value.code == -1
