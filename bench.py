@@ -169,7 +169,8 @@ def main():
     ms_median = float(np.median([x.elapsed_time(y) for x, y in per[1:]]))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(units),
-                "kernel": "k_map<64,classic,mul> (mont_mul_rns)", "bytes_per_unit": 24,
+                "kernel": "k_map<64,classic,mul> (mont_mul_rns)", "launch": mg.get_launch(mg.OP_MUL, 64, "classic"),
+                "bytes_per_unit": 24,
                 "units_per_launch": units, "ms_per_launch": round(ms_launch, 4),
                 "ms_per_launch_median": round(ms_median, 4)}
 

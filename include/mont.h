@@ -362,6 +362,8 @@ typedef struct mont_launch {
     uint32_t unroll;     /* 16-byte chunks per thread per iteration: 1, 2 or 4 */
     uint32_t nontemporal;/* 1: non-temporal loads/stores */
     uint32_t blocks_per_cu; /* 0: one pass over the data; else grid = CUs * this */
+    uint32_t block;      /* lanes per workgroup of mont_mul / mont_redc's 16-byte path: 64
+                            or 256 (default 64); exponentiation ignores it */
 } mont_launch_t;
 
 /*

@@ -66,7 +66,8 @@ class BatchShapeStruct(ctypes.Structure):
 
 
 class LaunchStruct(ctypes.Structure):
-    _fields_ = [("unroll", ctypes.c_uint32), ("nontemporal", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32)]
+    _fields_ = [("unroll", ctypes.c_uint32), ("nontemporal", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
+                ("block", ctypes.c_uint32)]
 
 
 _lib = None
@@ -347,15 +348,15 @@ def valu_ref(kind: int, iters: int, blocks: int, out, stream=None):
     check(load().mont_valu_ref(kind, iters, blocks, _dev(out, "out", 8, blocks * 256), _stream(stream)))
 
 
-def set_launch(op: int, w: int, variant, unroll=1, nontemporal=1, blocks_per_cu=0):
-    L = LaunchStruct(unroll, nontemporal, blocks_per_cu)
+def set_launch(op: int, w: int, variant, unroll=1, nontemporal=1, blocks_per_cu=0, block=64):
+    L = LaunchStruct(unroll, nontemporal, blocks_per_cu, block)
     check(load().mont_set_launch(op, w, variant_id(variant), ctypes.byref(L)))
 
 
 def get_launch(op: int, w: int, variant="classic"):
     L = LaunchStruct()
     check(load().mont_get_launch(op, w, variant_id(variant), ctypes.byref(L)))
-    return {"unroll": L.unroll, "nontemporal": L.nontemporal, "blocks_per_cu": L.blocks_per_cu}
+    return {"unroll": L.unroll, "nontemporal": L.nontemporal, "blocks_per_cu": L.blocks_per_cu, "block": L.block}
 
 
 def tune_mul(ctx: Ctx, a, b, out, variant="classic", stream=None):
@@ -364,7 +365,7 @@ def tune_mul(ctx: Ctx, a, b, out, variant="classic", stream=None):
     L = LaunchStruct()
     check(load().mont_tune_mul(ctypes.byref(ctx.s), _dev(a, "a", eb, n), _dev(b, "b", eb, n),
                                _dev(out, "out", eb, n), n, variant_id(variant), ctypes.byref(L), _stream(stream)))
-    return {"unroll": L.unroll, "nontemporal": L.nontemporal, "blocks_per_cu": L.blocks_per_cu}
+    return {"unroll": L.unroll, "nontemporal": L.nontemporal, "blocks_per_cu": L.blocks_per_cu, "block": L.block}
 
 
 # ------------------------------------------------------------------- batches

@@ -347,10 +347,13 @@ mont_status_t mont_set_launch(uint32_t op, uint32_t w, mont_variant_t variant, c
         return fail(MONT_E_INVAL, "bad launch key");
     if (l->unroll != 1 && l->unroll != 2 && l->unroll != 4)
         return fail(MONT_E_INVAL, "unroll must be 1, 2 or 4");
+    if (l->block != 64 && l->block != 256)
+        return fail(MONT_E_INVAL, "block must be 64 or 256");
     Launch L;
     L.unroll = (int)l->unroll;
     L.nontemporal = l->nontemporal ? 1 : 0;
     L.blocks_per_cu = (int)l->blocks_per_cu;
+    L.block = (int)l->block;
     set_launch((int)op, wc, (int)variant, L);
     return MONT_OK;
 }
@@ -364,6 +367,7 @@ mont_status_t mont_get_launch(uint32_t op, uint32_t w, mont_variant_t variant, m
     l->unroll = (uint32_t)L.unroll;
     l->nontemporal = (uint32_t)L.nontemporal;
     l->blocks_per_cu = (uint32_t)L.blocks_per_cu;
+    l->block = (uint32_t)L.block;
     return MONT_OK;
 }
 
@@ -407,7 +411,8 @@ extern "C" mont_status_t mont_tune_mul(const mont_ctx_t *ctx, const void *a, con
         bestL.unroll = (int)rec["unroll"];
         bestL.nontemporal = (int)rec["nontemporal"];
         bestL.blocks_per_cu = (int)rec["blocks_per_cu"];
-        if (bestL.unroll != 1 && bestL.unroll != 2 && bestL.unroll != 4)
+        bestL.block = rec.count("block") ? (int)rec["block"] : BLOCK;
+        if ((bestL.unroll != 1 && bestL.unroll != 2 && bestL.unroll != 4) || (bestL.block != 64 && bestL.block != 256))
             bestL = saved;
         set_launch(0, wc, variant, bestL);
     } else {
@@ -426,6 +431,7 @@ extern "C" mont_status_t mont_tune_mul(const mont_ctx_t *ctx, const void *a, con
         float best_ms = 1e30f;
         const int unrolls[] = {1, 2, 4};
         const int bpcs[] = {0, 4, 8, 16};
+        const int blocks[] = {64, 256};
         // clocks to their loaded state first (about 25 ms of the current shape)
         {
             const auto t0 = std::chrono::steady_clock::now();
@@ -436,10 +442,12 @@ extern "C" mont_status_t mont_tune_mul(const mont_ctx_t *ctx, const void *a, con
                     rc = fail(MONT_E_DEVICE, "tuning warm-up failed");
             } while (!rc && std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(25));
         }
-        // every candidate shape: unroll x non-temporal x workgroups per CU; the first failure ends the sweep
-        for (int c = 0; c < 3 * 2 * 4 && !rc; ++c) {
+        // every candidate shape: workgroup size x unroll x non-temporal x workgroups per CU; the first
+        // failure ends the sweep
+        for (int c = 0; c < 2 * 3 * 2 * 4 && !rc; ++c) {
             Launch L;
-            L.unroll = unrolls[c / 8];
+            L.block = blocks[c / 24];
+            L.unroll = unrolls[(c / 8) % 3];
             L.nontemporal = (c / 4) % 2;
             L.blocks_per_cu = bpcs[c % 4];
             set_launch(0, wc, variant, L);
@@ -470,12 +478,14 @@ extern "C" mont_status_t mont_tune_mul(const mont_ctx_t *ctx, const void *a, con
         tune_store(key, {{"unroll", (double)bestL.unroll},
                          {"nontemporal", (double)bestL.nontemporal},
                          {"blocks_per_cu", (double)bestL.blocks_per_cu},
+                         {"block", (double)bestL.block},
                          {"ms", best_ms / 5}});
     }
     if (best) {
         best->unroll = (uint32_t)bestL.unroll;
         best->nontemporal = (uint32_t)bestL.nontemporal;
         best->blocks_per_cu = (uint32_t)bestL.blocks_per_cu;
+        best->block = (uint32_t)bestL.block;
     }
     // the caller's out receives one product with the chosen shape
     return mont_mul(ctx, a, b, out, n, variant, stream);

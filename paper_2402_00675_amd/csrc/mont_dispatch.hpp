@@ -12,19 +12,19 @@ namespace mont {
 
 inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
-template <int W, int V, int OP, int E, int U, bool NT>
+template <int W, int V, int OP, int E, int U, bool NT, int BS = BLOCK>
 hipError_t go_map(const MapArgs &a, dim3 grid, hipStream_t s)
 {
     if (a.rows == 1) {
         KTab<1> t;
         t.c[0] = a.ctx[0];
-        hipLaunchKernelGGL((k_map<W, V, OP, E, U, NT, 1>), grid, dim3(BLOCK), 0, s, t, a.in0, a.in1, a.out, a.n,
+        hipLaunchKernelGGL((k_map<W, V, OP, E, U, NT, 1, BS>), grid, dim3(BS), 0, s, t, a.in0, a.in1, a.out, a.n,
                            a.ld, a.kc);
     } else if constexpr (OP == 0) {
         KTab<MAX_ROWS> t{};
         for (int r = 0; r < a.rows; ++r)
             t.c[r] = a.ctx[r];
-        hipLaunchKernelGGL((k_map<W, V, OP, E, U, NT, MAX_ROWS>), grid, dim3(BLOCK), 0, s, t, a.in0, a.in1,
+        hipLaunchKernelGGL((k_map<W, V, OP, E, U, NT, MAX_ROWS, BS>), grid, dim3(BS), 0, s, t, a.in0, a.in1,
                            a.out, a.n, a.ld, a.kc);
     } else {
         return hipErrorInvalidValue;
@@ -32,9 +32,9 @@ hipError_t go_map(const MapArgs &a, dim3 grid, hipStream_t s)
     return hipGetLastError();
 }
 
-inline uint64_t grid_x(uint64_t nchunk, int per_thread, int rows, const Launch &L)
+inline uint64_t grid_x(uint64_t nchunk, int per_thread, int rows, const Launch &L, int bs = BLOCK)
 {
-    const uint64_t per_block = (uint64_t)BLOCK * per_thread;
+    const uint64_t per_block = (uint64_t)bs * per_thread;
     uint64_t gx = (nchunk + per_block - 1) / per_block;
     if (L.blocks_per_cu > 0) {
         const uint64_t cap = std::max<uint64_t>(1, (uint64_t)device_cus() * L.blocks_per_cu / rows);
@@ -56,19 +56,24 @@ hipError_t launch_map_v(const MapArgs &a, const Launch &L, hipStream_t s)
         return go_map<W, V, OP, 1, 1, false>(a, grid, s);
     }
     const int U = (L.unroll == 4 || L.unroll == 1) ? L.unroll : 2;
-    dim3 grid((unsigned)grid_x(a.n / E, U, a.rows, L), (unsigned)a.rows);
-    if (L.nontemporal) {
+    const int bs = L.block == 64 ? 64 : BLOCK;
+    dim3 grid((unsigned)grid_x(a.n / E, U, a.rows, L, bs), (unsigned)a.rows);
+    auto go = [&](auto bs_c) {
+        constexpr int B = decltype(bs_c)::value;
+        if (L.nontemporal) {
+            if (U == 1)
+                return go_map<W, V, OP, E, 1, true, B>(a, grid, s);
+            if (U == 2)
+                return go_map<W, V, OP, E, 2, true, B>(a, grid, s);
+            return go_map<W, V, OP, E, 4, true, B>(a, grid, s);
+        }
         if (U == 1)
-            return go_map<W, V, OP, E, 1, true>(a, grid, s);
+            return go_map<W, V, OP, E, 1, false, B>(a, grid, s);
         if (U == 2)
-            return go_map<W, V, OP, E, 2, true>(a, grid, s);
-        return go_map<W, V, OP, E, 4, true>(a, grid, s);
-    }
-    if (U == 1)
-        return go_map<W, V, OP, E, 1, false>(a, grid, s);
-    if (U == 2)
-        return go_map<W, V, OP, E, 2, false>(a, grid, s);
-    return go_map<W, V, OP, E, 4, false>(a, grid, s);
+            return go_map<W, V, OP, E, 2, false, B>(a, grid, s);
+        return go_map<W, V, OP, E, 4, false, B>(a, grid, s);
+    };
+    return bs == 64 ? go(std::integral_constant<int, 64>{}) : go(std::integral_constant<int, BLOCK>{});
 }
 
 template <int W, int OP>

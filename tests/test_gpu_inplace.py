@@ -216,13 +216,13 @@ def test_tune_cache_is_read_back(tmp_path, monkeypatch):
         arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
         assert key.startswith("%s:v%d:mul:w32:v2:log2n21" % (arch, mg.version()))
         # plant a distinctive shape for the same key, and one for another library version
-        planted = {"unroll": 4, "nontemporal": 0, "blocks_per_cu": 8}
+        planted = {"unroll": 4, "nontemporal": 0, "blocks_per_cu": 8, "block": 256}
         if {k: recs[0][k] for k in planted} == planted:
-            planted = {"unroll": 2, "nontemporal": 0, "blocks_per_cu": 16}
+            planted = {"unroll": 2, "nontemporal": 0, "blocks_per_cu": 16, "block": 64}
         other = key.replace(":v%d:" % mg.version(), ":v%d:" % (mg.version() + 1))
         with open(cache, "a") as f:
             f.write(json.dumps(dict(key=key, ms=0.001, **planted)) + "\n")
-            f.write(json.dumps(dict(key=other, ms=0.001, unroll=1, nontemporal=1, blocks_per_cu=4)) + "\n")
+            f.write(json.dumps(dict(key=other, ms=0.001, unroll=1, nontemporal=1, blocks_per_cu=4, block=64)) + "\n")
         out.zero_()
         best = mg.tune_mul(c, da, db, out, variant="plantard")
         assert best == planted

@@ -271,11 +271,11 @@ def test_small_and_misaligned(w, n):
         assert np.array_equal(got, want)
 
 
-LAUNCHES = [(u, nt, bpc) for u in (1, 2, 4) for nt in (0, 1) for bpc in (0, 4)]
+LAUNCHES = [(u, nt, bpc, bs) for u in (1, 2, 4) for nt in (0, 1) for bpc in (0, 4) for bs in (64, 256)]
 
 
-@pytest.mark.parametrize("u,nt,bpc", LAUNCHES)
-def test_launch_shapes(u, nt, bpc):
+@pytest.mark.parametrize("u,nt,bpc,bs", LAUNCHES)
+def test_launch_shapes(u, nt, bpc, bs):
     """Every unroll / non-temporal / grid shape gives the same results."""
     saved = {(op, w, v): mg.get_launch(op, w, v) for op in (mg.OP_MUL, mg.OP_REDC) for w in (16, 32, 64)
              for v in ["classic", "signed_plantard"]}
@@ -283,8 +283,8 @@ def test_launch_shapes(u, nt, bpc):
         for w, N in [(16, 3329), (32, 8380417), (64, (1 << 60) - 93)]:
             c = mg.setup(N, w)
             for variant in ["classic", "signed_plantard"]:
-                mg.set_launch(mg.OP_MUL, w, variant, u, nt, bpc)
-                mg.set_launch(mg.OP_REDC, w, variant, u, nt, bpc)
+                mg.set_launch(mg.OP_MUL, w, variant, u, nt, bpc, bs)
+                mg.set_launch(mg.OP_REDC, w, variant, u, nt, bpc, bs)
                 a, b = operands(variant, w, N, 300_007, inp.rng(97, u * 10 + nt + bpc))
                 got = host(mg.mul(c, dev(a), dev(b), variant=variant))
                 assert np.array_equal(got, orc.mul(variant, w, N, a, b))
@@ -689,6 +689,7 @@ def test_tune_mul_and_cache(tmp_path, monkeypatch):
         out = torch.empty_like(da)
         best = mg.tune_mul(c, da, db, out, variant="plantard")
         assert best["unroll"] in (1, 2, 4) and best["nontemporal"] in (0, 1) and best["blocks_per_cu"] in (0, 4, 8, 16)
+        assert best["block"] in (64, 256)
         assert mg.get_launch(mg.OP_MUL, w, "plantard") == best
         got = host(mg.mul(c, da, db, variant="plantard"))
         assert np.array_equal(got, orc.mul("plantard", w, N, a, b))
