@@ -334,23 +334,23 @@ void mont_batch_destroy(mont_batch_t *batch);
  * (code under stream capture that must not call hipMalloc, tight serving
  * loops, harnesses that forbid allocation): the work of mont_batch_create
  * followed by one mont_batch_run, with the same results, that allocates
- * nothing.  The batch's constant, segment and tile tables go to a fixed
- * device array of MONT_NOALLOC_SCRATCH_BYTES that the library holds on each
- * device it runs on until the process ends; the launch is the one-pass shape (one
+ * nothing.  The batch's constant and tile tables go to a fixed device array
+ * of MONT_NOALLOC_SCRATCH_BYTES that the library holds on each device it
+ * runs on until the process ends; the launch is the one-pass shape (one
  * workgroup per tile of tile_elems 32-bit elements, 0 = 4096; a power of two
  * in [256, 2^20]), non-temporal.  ctxs, segs and pools are HOST structures
  * with the meaning of mont_batch_create and mont_batch_run; segments are
  * validated the same way, with the same errors.  Tables larger than the
- * array (64 bytes per context, 32 per segment, 16 per tile, 64 more) return
- * MONT_E_INVAL before any device use; a larger tile_elems or
- * mont_batch_create serves such batches.  The tables are copied to the device on `stream` and the
- * call waits for that copy (and so for the stream's earlier work) before it
- * returns; the kernel itself runs asynchronously.  Every call on one device
- * shares that device's array: calls that overlap on one device (on other
- * streams or from other threads) race and must not be issued; calls in
- * order on one stream are safe.
+ * array (64 bytes per context, 32 per segment and 32 per tile, 64 more)
+ * return MONT_E_INVAL before any device use; a larger tile_elems or
+ * mont_batch_create serves such batches.  The tables are copied to the
+ * device on `stream` and the call waits for that copy (and so for the
+ * stream's earlier work) before it returns; the kernel itself runs
+ * asynchronously.  Every call on one device shares that device's array:
+ * calls that overlap on one device (on other streams or from other threads)
+ * race and must not be issued; calls in order on one stream are safe.
  */
-#define MONT_NOALLOC_SCRATCH_BYTES (8u << 20)
+#define MONT_NOALLOC_SCRATCH_BYTES (16u << 20)
 mont_status_t mont_batch_run_noalloc(const mont_ctx_t *ctxs, uint32_t nctx, const mont_seg_t *segs, uint32_t nseg,
                                      const mont_pools_t *pools, uint32_t tile_elems, void *stream);
 

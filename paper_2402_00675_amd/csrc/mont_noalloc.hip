@@ -1,6 +1,6 @@
 // mont_batch_run_noalloc: a ragged batch (mont_batch_create + mont_batch_run
-// in one call) that allocates no device memory.  The batch's constant,
-// segment and tile tables live in a fixed file-scope device array instead of
+// in one call) that allocates no device memory.  The batch's constant and
+// tile tables live in a fixed file-scope device array instead of
 // library-owned allocations; the kernel is the ragged batch kernel, one pass
 // over the tiles (one workgroup per tile, static order), the default shape of
 // a batch.
@@ -28,9 +28,10 @@
 namespace mont {
 
 // [0, 64): zero words (the ragged kernel's counter argument; unused by the
-// static schedule); then nctx per-modulus constant records (64 bytes each),
-// nseg segment descriptors (32 bytes each) and the tile table (16 bytes per
-// tile), each starting on a 16-byte boundary.
+// static schedule); then nctx per-modulus constant records (64 bytes each)
+// and the tile table (32 bytes per tile) from the next 16-byte boundary.  The
+// host array of the same size holds these and, after them, the validated
+// segments (32 bytes each), which the kernel does not read.
 static __device__ __align__(256) unsigned char scratch[MONT_NOALLOC_SCRATCH_BYTES];
 
 constexpr size_t NA_HEAD = 64;
@@ -91,15 +92,18 @@ extern "C" mont_status_t mont_batch_run_noalloc(const mont_ctx_t *ctxs, uint32_t
             return fail(MONT_E_INVAL, "segment %u: size too large", i);
         ntiles += (sg.n + te - 1) / te;
     }
+    // device tables [0, need): head, constants, tiles; the validated segments
+    // follow them in the host array only
     const size_t o_ctx = NA_HEAD;
-    const size_t o_seg = align16(o_ctx + (size_t)nctx * sizeof(KCtx));
-    const size_t o_tile = align16(o_seg + (size_t)nseg * sizeof(DSeg));
+    const size_t o_tile = align16(o_ctx + (size_t)nctx * sizeof(KCtx));
     const uint64_t need = o_tile + ntiles * sizeof(DTile);
-    if (need > MONT_NOALLOC_SCRATCH_BYTES)
+    const uint64_t o_seg = align16(need);
+    if (o_seg + (uint64_t)nseg * sizeof(DSeg) > MONT_NOALLOC_SCRATCH_BYTES)
         return fail(MONT_E_INVAL,
                     "batch tables need %llu bytes (%u contexts, %u segments, %llu tiles of %u elements): more than "
                     "the %u-byte scratch array; use a larger tile_elems or mont_batch_create",
-                    (unsigned long long)need, nctx, nseg, (unsigned long long)ntiles, tb,
+                    (unsigned long long)(o_seg + (uint64_t)nseg * sizeof(DSeg)), nctx, nseg,
+                    (unsigned long long)ntiles, tb,
                     (unsigned)MONT_NOALLOC_SCRATCH_BYTES);
     if (ntiles == 0)
         return MONT_OK;
@@ -135,9 +139,7 @@ extern "C" mont_status_t mont_batch_run_noalloc(const mont_ctx_t *ctxs, uint32_t
     uint64_t L = 0;
     auto put = [&](uint32_t seg, uint64_t start, uint32_t cnt) {
         const uint64_t pos = perm ? (L % 8) * c8 + L / 8 : L;
-        ht[pos].seg = seg;
-        ht[pos].cnt = cnt;
-        ht[pos].start = start;
+        ht[pos] = make_tile(hs[seg], start, cnt);
         ++L;
     };
     auto cut = [&](uint32_t i) {
@@ -190,8 +192,7 @@ extern "C" mont_status_t mont_batch_run_noalloc(const mont_ctx_t *ctxs, uint32_t
         P.out[i] = pools->out[i];
     }
     unsigned char *d = static_cast<unsigned char *>(base);
-    e = launch_ragged(reinterpret_cast<const KCtx *>(d + o_ctx), reinterpret_cast<const DSeg *>(d + o_seg),
-                      reinterpret_cast<const DTile *>(d + o_tile), (uint32_t)ntiles, P, reinterpret_cast<uint32_t *>(d),
-                      0u, (uint32_t)ntiles, true, s);
+    e = launch_ragged(reinterpret_cast<const KCtx *>(d + o_ctx), reinterpret_cast<const DTile *>(d + o_tile),
+                      (uint32_t)ntiles, P, reinterpret_cast<uint32_t *>(d), 0u, (uint32_t)ntiles, true, s);
     return e == hipSuccess ? MONT_OK : hip_fail(e, "ragged launch");
 }

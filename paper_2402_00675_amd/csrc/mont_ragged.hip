@@ -2,14 +2,16 @@
 // modulus, word size, length and operation, in ONE persistent launch.
 //
 // Host side: every segment is cut into tiles (equal output bytes for the
-// streaming ops, a fixed element count for exponentiation) and a tile table
-// {segment, start, count} plus a segment table {constants, pool offset, op,
-// variant} are uploaded once.  Device side: a persistent grid (a multiple of
-// the CU count) walks the tile table either round-robin (static) or through
-// an atomic tile counter (dynamic; the last workgroup to finish resets the
-// counter, so a replay needs no memset).  The tile's descriptor is
-// wave-uniform, so it is fetched with scalar loads and its constants stay in
-// SGPRs; the op / word size / variant switch is a uniform branch.
+// streaming ops, a fixed element count for exponentiation); a table of
+// per-modulus constants and a tile table {pool offsets, count, constants
+// index, op, variant, width} are uploaded once.  Device side: one workgroup
+// per tile (one pass), or a persistent grid (a multiple of the CU count) that
+// walks the tile table round-robin (static) or through an atomic tile counter
+// (dynamic; the last workgroup to finish resets the counter, so a replay
+// needs no memset), fetching the next tile's record (or claiming it) while
+// the current one runs.  The tile's record is wave-uniform, so it is fetched
+// with scalar loads and its constants stay in SGPRs; the op / word size /
+// variant switch is a uniform branch.
 //
 // Launches can be replayed from a hipGraph whose kernel node is updated in
 // place when the caller's pool pointers change.
@@ -177,8 +179,8 @@ __device__ __forceinline__ void tile_width(uint32_t op, uint32_t variant, const 
 
 template <bool NT>
 __global__ void __launch_bounds__(BLOCK)
-    k_ragged(const KCtx *__restrict__ ctab, const DSeg *__restrict__ segs, const DTile *__restrict__ tiles,
-             uint32_t ntiles, DPools P, uint32_t *__restrict__ ctr, uint32_t dynamic)
+    k_ragged(const KCtx *__restrict__ ctab, const DTile *__restrict__ tiles, uint32_t ntiles, DPools P,
+             uint32_t *__restrict__ ctr, uint32_t dynamic)
 {
     __shared__ uint32_t s_next[2];
     uint32_t t;
@@ -191,28 +193,40 @@ __global__ void __launch_bounds__(BLOCK)
     } else {
         t = xcd_block(blockIdx.x, gridDim.x);
     }
+    t = __builtin_amdgcn_readfirstlane(t);
+    DTile td{};
+    if (t < ntiles)
+        td = tiles[t];
     while (t < ntiles) {
-        t = __builtin_amdgcn_readfirstlane(t);
+        // The next tile is fetched while this one runs: its index from the counter
+        // (the claim's result is first needed after the tile), or, statically, its
+        // record.
+        uint32_t claim = 0;
         if (dynamic && threadIdx.x == 0)
-            s_next[buf ^ 1] = atomicAdd(&ctr[0], 1u);  // fetch the next tile while this one runs
-        const DTile td = tiles[t];
-        const DSeg &sd = segs[td.seg];
-        const KCtx &kc = ctab[sd.ctx];
-        const uint64_t g0 = sd.off + td.start;
-        const uint64_t g1 = sd.off1 + td.start;
-        const uint32_t wc = sd.wc;
+            claim = atomicAdd(&ctr[0], 1u);
+        const uint32_t tn = t + gridDim.x;
+        DTile nd{};
+        if (!dynamic && tn < ntiles)
+            nd = tiles[tn];
+        const KCtx &kc = ctab[td.ctx];
+        const uint32_t wc = td.vw >> 8, variant = td.vw & 0xffu;
         if (wc == 0)
-            tile_width<16, NT>(sd.op, sd.variant, kc, P, g0, g1, td.cnt);
+            tile_width<16, NT>(td.op, variant, kc, P, td.g0, td.g1, td.cnt);
         else if (wc == 1)
-            tile_width<32, NT>(sd.op, sd.variant, kc, P, g0, g1, td.cnt);
+            tile_width<32, NT>(td.op, variant, kc, P, td.g0, td.g1, td.cnt);
         else
-            tile_width<64, NT>(sd.op, sd.variant, kc, P, g0, g1, td.cnt);
+            tile_width<64, NT>(td.op, variant, kc, P, td.g0, td.g1, td.cnt);
         if (dynamic) {
+            if (threadIdx.x == 0)
+                s_next[buf ^ 1] = claim;
             __syncthreads();  // s_next[buf^1] written; everyone done with s_next[buf]
             buf ^= 1;
-            t = s_next[buf];
+            t = __builtin_amdgcn_readfirstlane(s_next[buf]);
+            if (t < ntiles)
+                td = tiles[t];
         } else {
-            t += gridDim.x;
+            t = tn;
+            td = nd;
         }
     }
     if (dynamic) {
@@ -240,9 +254,8 @@ struct mont_batch {
     int dev = 0;
     std::vector<mont_ctx_t> ctxs;
     std::vector<mont_seg_t> segs;
-    std::vector<DSeg> hsegs;
-    DSeg *dsegs = nullptr;
-    KCtx *dctx = nullptr;        // the batch's per-modulus constants, indexed by the segments
+    std::vector<DSeg> hsegs;     // validated segments (host only: tiles carry what the kernel needs)
+    KCtx *dctx = nullptr;        // the batch's per-modulus constants, indexed by the tiles
     DTile *dtiles = nullptr;
     uint32_t *dctr = nullptr;
     size_t tiles_cap = 0;
@@ -317,23 +330,16 @@ static mont_status_t build_tiles(mont_batch &b, hipStream_t s)
         const mont_seg_t &sg = b.segs[i];
         const uint32_t wc = b.hsegs[i].wc;
         const uint64_t te = tile_elems(b, wc, sg.op);
-        for (uint64_t st = 0; st < sg.n; st += te) {
-            DTile t;
-            t.seg = i;
-            t.start = st;
-            t.cnt = (uint32_t)std::min<uint64_t>(te, sg.n - st);
-            (sg.op == MONT_OP_POW ? pow_tiles : map_tiles).push_back(t);
-        }
+        for (uint64_t st = 0; st < sg.n; st += te)
+            (sg.op == MONT_OP_POW ? pow_tiles : map_tiles)
+                .push_back(make_tile(b.hsegs[i], st, (uint32_t)std::min<uint64_t>(te, sg.n - st)));
     }
     // Streaming tiles grouped by (width class, operation, variant), segment
     // order kept inside a group: at any moment the workgroups then run one code
     // path over one set of pools (on MI355X, 31- and 62-bit segments
     // interleaved in segment order ran 9 % slower than the two classes one
     // after the other).
-    auto key = [&](const DTile &t) {
-        const mont_seg_t &sg = b.segs[t.seg];
-        return (b.hsegs[t.seg].wc << 16) | (sg.op << 8) | sg.variant;
-    };
+    auto key = [](const DTile &t) { return ((t.vw >> 8) << 16) | (t.op << 8) | (t.vw & 0xffu); };
     std::stable_sort(map_tiles.begin(), map_tiles.end(),
                      [&](const DTile &x, const DTile &y) { return key(x) < key(y); });
     // the heaviest tiles (exponentiation) first, so a dynamic schedule ends level
@@ -411,19 +417,19 @@ static mont_status_t check_pools(const mont_batch &b, const mont_pools_t *p)
 
 void *ragged_kernel_ptr(bool nt) { return nt ? (void *)k_ragged<true> : (void *)k_ragged<false>; }
 
-hipError_t launch_ragged(const KCtx *ctab, const DSeg *segs, const DTile *tiles, uint32_t ntiles, const DPools &P,
-                         uint32_t *ctr, uint32_t dyn, uint32_t grid, bool nt, hipStream_t s)
+hipError_t launch_ragged(const KCtx *ctab, const DTile *tiles, uint32_t ntiles, const DPools &P, uint32_t *ctr,
+                         uint32_t dyn, uint32_t grid, bool nt, hipStream_t s)
 {
     if (nt)
-        hipLaunchKernelGGL(k_ragged<true>, dim3(grid), dim3(BLOCK), 0, s, ctab, segs, tiles, ntiles, P, ctr, dyn);
+        hipLaunchKernelGGL(k_ragged<true>, dim3(grid), dim3(BLOCK), 0, s, ctab, tiles, ntiles, P, ctr, dyn);
     else
-        hipLaunchKernelGGL(k_ragged<false>, dim3(grid), dim3(BLOCK), 0, s, ctab, segs, tiles, ntiles, P, ctr, dyn);
+        hipLaunchKernelGGL(k_ragged<false>, dim3(grid), dim3(BLOCK), 0, s, ctab, tiles, ntiles, P, ctr, dyn);
     return hipGetLastError();
 }
 
 static mont_status_t launch_direct(mont_batch &b, const DPools &P, hipStream_t s, uint32_t dyn)
 {
-    const hipError_t e = launch_ragged(b.dctx, b.dsegs, b.dtiles, b.ntiles, P, b.dctr, dyn, b.grid, b.nt, s);
+    const hipError_t e = launch_ragged(b.dctx, b.dtiles, b.ntiles, P, b.dctr, dyn, b.grid, b.nt, s);
     return e == hipSuccess ? MONT_OK : hip_fail(e, "ragged launch");
 }
 
@@ -431,11 +437,10 @@ static mont_status_t launch_graph(mont_batch &b, const DPools &P, hipStream_t s,
 {
     DPools Pc = P;
     KCtx *ctab = b.dctx;
-    DSeg *segs = b.dsegs;
     DTile *tiles = b.dtiles;
     uint32_t nt = b.ntiles;
     uint32_t *ctr = b.dctr;
-    void *args[] = {&ctab, &segs, &tiles, &nt, &Pc, &ctr, &dyn};
+    void *args[] = {&ctab, &tiles, &nt, &Pc, &ctr, &dyn};
     hipKernelNodeParams kp{};
     kp.func = ragged_kernel_ptr(b.nt);
     kp.gridDim = dim3(b.grid);
@@ -670,9 +675,7 @@ mont_status_t mont_batch_create(const mont_ctx_t *ctxs, uint32_t nctx, const mon
     }
     (void)hipGetDevice(&b->dev);
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipMalloc(&b->dsegs, std::max<size_t>(nseg, 1) * sizeof(DSeg));
-    if (e == hipSuccess)
-        e = hipMalloc(&b->dctx, std::max<size_t>(nctx, 1) * sizeof(KCtx));
+    hipError_t e = hipMalloc(&b->dctx, std::max<size_t>(nctx, 1) * sizeof(KCtx));
     if (e == hipSuccess)
         e = hipMalloc(&b->dctr, 64);
     if (e != hipSuccess) {
@@ -682,8 +685,6 @@ mont_status_t mont_batch_create(const mont_ctx_t *ctxs, uint32_t nctx, const mon
     std::vector<KCtx> kctx(nctx);
     for (uint32_t i = 0; i < nctx; ++i)
         kctx[i] = to_kctx(ctxs[i]);
-    if (nseg)
-        e = hipMemcpyAsync(b->dsegs, b->hsegs.data(), nseg * sizeof(DSeg), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && nctx)
         e = hipMemcpyAsync(b->dctx, kctx.data(), nctx * sizeof(KCtx), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
@@ -825,8 +826,6 @@ void mont_batch_destroy(mont_batch_t *b)
         (void)hipGraphExecDestroy(b->exec);
     if (b->graph)
         (void)hipGraphDestroy(b->graph);
-    if (b->dsegs)
-        (void)hipFree(b->dsegs);
     if (b->dctx)
         (void)hipFree(b->dctx);
     if (b->dtiles)

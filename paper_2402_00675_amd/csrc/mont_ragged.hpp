@@ -1,5 +1,5 @@
-// Descriptors of the persistent ragged-batch kernel, shared by the batch API
-// and the serving loop.
+// Descriptors of the persistent ragged-batch kernel, shared by the batch API,
+// the allocation-free batch and the serving loop.
 #pragma once
 
 #include "../../include/mont.h"
@@ -7,6 +7,7 @@
 
 namespace mont {
 
+// One segment as the host validates it (make_dseg); the kernel never reads it.
 struct DSeg {
     uint64_t off;    // element offset of in0 / out in the pools of its width
     uint64_t off1;   // element offset of in1 (b as w-bit elements; exponents as uint64)
@@ -15,13 +16,31 @@ struct DSeg {
     uint32_t wc;     // width class 0/1/2 = 16/32/64 bits
     uint32_t ctx;    // index of the segment's constants in the launch's KCtx table
 };
-static_assert(sizeof(DSeg) == 32, "segment descriptor layout");
 
+// One tile of work as the kernel reads it (32 bytes, one scalar load): its
+// element range in the pools and everything needed to process it, so the only
+// other load before the data is the tile's constants, ctab[ctx].
 struct DTile {
-    uint32_t seg;
-    uint32_t cnt;
-    uint64_t start;  // element index inside the segment
+    uint64_t g0;   // first element in in0 and out (a 2w-bit T index for MONT_OP_REDC)
+    uint64_t g1;   // the same element's index in in1 (w-bit b, or uint64 exponent)
+    uint32_t cnt;  // elements
+    uint32_t ctx;  // constants: ctab[ctx]
+    uint32_t op;   // MONT_OP_*
+    uint32_t vw;   // variant | width class << 8
 };
+static_assert(sizeof(DTile) == 32, "tile record layout");
+
+inline DTile make_tile(const DSeg &d, uint64_t start, uint32_t cnt)
+{
+    DTile t;
+    t.g0 = d.off + start;
+    t.g1 = d.off1 + start;
+    t.cnt = cnt;
+    t.ctx = d.ctx;
+    t.op = d.op;
+    t.vw = d.variant | (d.wc << 8);
+    return t;
+}
 
 struct DPools {
     const void *in0[3];
@@ -29,15 +48,17 @@ struct DPools {
     void *out[3];
 };
 
-// One persistent launch over `ntiles` tiles; segment i reduces with the
-// constants ctab[segs[i].ctx] (ctr: two zeroed uint32 that the kernel leaves
-// zeroed again when dyn = 1).  nt selects non-temporal loads and stores.
-hipError_t launch_ragged(const KCtx *ctab, const DSeg *segs, const DTile *tiles, uint32_t ntiles, const DPools &P,
-                         uint32_t *ctr, uint32_t dyn, uint32_t grid, bool nt, hipStream_t s);
+// One launch over `ntiles` tiles, tile i reducing with the constants
+// ctab[tiles[i].ctx]: grid = ntiles for one pass, fewer for a persistent grid
+// (static round-robin, or tiles claimed from the counter ctr[0] when dyn = 1;
+// ctr: two zeroed uint32 that the kernel leaves zeroed again).  nt selects
+// non-temporal loads and stores.
+hipError_t launch_ragged(const KCtx *ctab, const DTile *tiles, uint32_t ntiles, const DPools &P, uint32_t *ctr,
+                         uint32_t dyn, uint32_t grid, bool nt, hipStream_t s);
 void *ragged_kernel_ptr(bool nt);
 
 // Validates segment i of a batch (context index, op, variant, sizes, operand
-// alignment) and fills its device descriptor; the error text names the segment.
+// alignment) and fills its host descriptor; the error text names the segment.
 mont_status_t make_dseg(const mont_ctx_t *ctxs, uint32_t nctx, const mont_seg_t &sg, uint32_t i, DSeg &d);
 // Elements per tile of a segment of width class wc and operation op.
 uint32_t seg_tile_elems(uint32_t tile_base, uint32_t pow_tile, uint32_t wc, uint32_t op);

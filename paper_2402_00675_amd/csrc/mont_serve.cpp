@@ -227,8 +227,9 @@ class GpuBackend : public mont_sched::Backend {
             tile_base = c.tile_elems;
         grid_max = (uint32_t)device_cus() * 8;
         // every in-flight job pins at most one entry; batches abandoned at their
-        // deadline keep theirs until they end, hence the margin
-        const uint32_t ncent = 2 * c.max_jobs_in_flight + 65536;
+        // deadline keep theirs until they end, hence the margin; 2^18 more entries
+        // (16 MiB) keep that many moduli cached
+        const uint32_t ncent = 2 * c.max_jobs_in_flight + (1u << 18);
         if (hipMalloc(&dctab, (size_t)ncent * sizeof(KCtx)) != hipSuccess)
             return fail(MONT_E_NOMEM, "resident constant table");
         cent.resize(ncent);
@@ -240,7 +241,7 @@ class GpuBackend : public mont_sched::Backend {
         slot.resize(nslots);
         const size_t max_jobs = c.max_batch_jobs;
         for (ServeSlot &s : slot)
-            if (mont_status_t rc = make_slot(s, max_jobs * (sizeof(KCtx) + 4 + sizeof(DSeg) + 64 * sizeof(DTile) +
+            if (mont_status_t rc = make_slot(s, max_jobs * (sizeof(KCtx) + 4 + 64 * sizeof(DTile) +
                                                             96 * sizeof(XDesc))))
                 return rc;
         return MONT_OK;
@@ -453,9 +454,17 @@ class GpuBackend : public mont_sched::Backend {
         const size_t es[2] = {4, 8};
         for (uint32_t i = 0; i < jobs.size(); ++i) {
             const mont_sched::Job &j = *jobs[i];
+            DSeg d;
+            d.ctx = s.pinned[i];
+            d.off = j.off;
+            // in1 slot = 8 bytes: exponents index uint64 at off, products index w-bit b at off * 8 / es
+            d.off1 = j.op == mont_sched::OP_POW ? j.off : j.off * (8 / es[j.cls]);
+            d.op = j.op == mont_sched::OP_POW ? MONT_OP_POW : MONT_OP_MUL;
+            d.variant = CLASSIC;
+            d.wc = j.cls == 0 ? 1 : 2;
             const uint64_t te = j.op == mont_sched::OP_POW ? pow_tile : (j.cls == 0 ? tile_base : tile_base / 2);
             for (uint64_t st = 0; st < j.n; st += te)
-                tiles.push_back({i, (uint32_t)std::min<uint64_t>(te, j.n - st), st});
+                tiles.push_back(make_tile(d, st, (uint32_t)std::min<uint64_t>(te, j.n - st)));
         }
         {
             std::lock_guard<std::mutex> g(reg_mu);
@@ -488,8 +497,7 @@ class GpuBackend : public mont_sched::Backend {
         // one packed table upload per batch
         const size_t o_newc = 0;
         const size_t o_newi = up16(o_newc + newc.size() * sizeof(KCtx));
-        const size_t o_seg = up16(o_newi + newi.size() * sizeof(uint32_t));
-        const size_t o_tile = up16(o_seg + jobs.size() * sizeof(DSeg));
+        const size_t o_tile = up16(o_newi + newi.size() * sizeof(uint32_t));
         const size_t o_xin = up16(o_tile + tiles.size() * sizeof(DTile));
         const size_t o_xtin = up16(o_xin + xin.size() * sizeof(XDesc));
         const size_t o_xout = up16(o_xtin + xtin.size() * sizeof(XTile));
@@ -499,19 +507,6 @@ class GpuBackend : public mont_sched::Backend {
             return -1;
         std::memcpy(s.hstage + o_newc, newc.data(), newc.size() * sizeof(KCtx));
         std::memcpy(s.hstage + o_newi, newi.data(), newi.size() * sizeof(uint32_t));
-        DSeg *hsegs = (DSeg *)(s.hstage + o_seg);
-        for (uint32_t i = 0; i < jobs.size(); ++i) {
-            const mont_sched::Job &j = *jobs[i];
-            DSeg &d = hsegs[i];
-            std::memset(&d, 0, sizeof d);
-            d.ctx = s.pinned[i];
-            d.off = j.off;
-            // in1 slot = 8 bytes: exponents index uint64 at off, products index w-bit b at off * 8 / es
-            d.off1 = j.op == mont_sched::OP_POW ? j.off : j.off * (8 / es[j.cls]);
-            d.op = j.op == mont_sched::OP_POW ? MONT_OP_POW : MONT_OP_MUL;
-            d.variant = CLASSIC;
-            d.wc = j.cls == 0 ? 1 : 2;
-        }
         std::memcpy(s.hstage + o_tile, tiles.data(), tiles.size() * sizeof(DTile));
         std::memcpy(s.hstage + o_xin, xin.data(), xin.size() * sizeof(XDesc));
         std::memcpy(s.hstage + o_xtin, xtin.data(), xtin.size() * sizeof(XTile));
@@ -551,8 +546,8 @@ class GpuBackend : public mont_sched::Backend {
             P.in1[2] = in1[1];
             P.out[2] = out[1];
             const uint32_t grid = (uint32_t)std::max<size_t>(1, std::min<size_t>(tiles.size(), grid_max));
-            e = launch_ragged(dctab, (const DSeg *)(s.dstage + o_seg), (const DTile *)(s.dstage + o_tile),
-                              (uint32_t)tiles.size(), P, s.dctr, 1u, grid, true, s.stream);
+            e = launch_ragged(dctab, (const DTile *)(s.dstage + o_tile), (uint32_t)tiles.size(), P, s.dctr, 1u, grid,
+                              true, s.stream);
         }
         if (e == hipSuccess && !xtout.empty()) {
             hipLaunchKernelGGL(k_xfer, dim3((unsigned)xtout.size()), dim3(BLOCK), 0, s.stream,

@@ -32,16 +32,16 @@ POOL_BUCKETS = 64
 CLASS_BITS = {32: 31, 64: 62}
 
 
-def bucket_of(N: int, w: int) -> int:
+def bucket_of(N: int, w: int, buckets: int = POOL_BUCKETS) -> int:
     """The operand-pool bucket of a modulus of the 31-bit (w = 32) or 62-bit (w = 64) class."""
     b = CLASS_BITS[w]
-    return (N - (1 << (b - 1))) >> (b - 1 - 6)
+    return (N - (1 << (b - 1))) >> (b - 1 - (buckets.bit_length() - 1))
 
 
-def bucket_floor(k: int, w: int) -> int:
+def bucket_floor(k: int, w: int, buckets: int = POOL_BUCKETS) -> int:
     """L_k: the lower end of bucket k's modulus interval, the bound of its operand pools."""
     b = CLASS_BITS[w]
-    return (1 << (b - 1)) + (k << (b - 1 - 6))
+    return (1 << (b - 1)) + (k << (b - 1 - (buckets.bit_length() - 1)))
 
 
 def _pinned(torch, n, dtype):
@@ -51,9 +51,11 @@ def _pinned(torch, n, dtype):
 class JobStream:
     """Jobs of one stream with their host buffers (kept alive here)."""
 
-    def __init__(self, torch, njobs, seed_rep=0, distinct_outputs=False, hi=None):
+    def __init__(self, torch, njobs, seed_rep=0, distinct_outputs=False, hi=None, buckets=POOL_BUCKETS):
         """distinct_outputs: True (every job), False (all jobs write one sink buffer per
-        word size) or a collection of job indices that get their own output buffers."""
+        word size) or a collection of job indices that get their own output buffers.
+        buckets: operand pools per class (a power of two; 1 = one pool below the class's
+        smallest modulus)."""
         wl = inp.ServeWorkload()
         if hi is not None:
             wl.hi = hi
@@ -64,12 +66,13 @@ class JobStream:
         g = inp.rng(inp.W_SERVE, 100 + seed_rep)
         P = int(wl.hi) + POOL_SLACK
         # pool[w][k] = (a, b): operands of the jobs whose modulus lies in bucket k, uniform below L_k
-        self.bucket = [bucket_of(int(N), 64 if wd else 32) for N, wd in zip(mods, wide)]
+        self.buckets = buckets
+        self.bucket = [bucket_of(int(N), 64 if wd else 32, buckets) for N, wd in zip(mods, wide)]
         self.pool = {}
         for w, tdt, ndt in ((32, torch.uint32, np.uint32), (64, torch.uint64, np.uint64)):
             self.pool[w] = []
-            for k in range(POOL_BUCKETS):
-                L = bucket_floor(k, w)
+            for k in range(buckets):
+                L = bucket_floor(k, w, buckets)
                 pair = (_pinned(torch, P, tdt), _pinned(torch, P, tdt))
                 for t in pair:
                     t.numpy()[:] = g.integers(0, L, size=P, dtype=np.uint64).astype(ndt)
