@@ -611,7 +611,7 @@ def ragged(torch, mg, inp, nseg):
         info = b2.info()
         b2.close()
         kind = "one_pass" if not info["blocks_per_cu"] else "persistent_%s" % (
-            "dynamic" if info["flags"] & mg.BATCH_DYNAMIC else "static")
+            "dynamic%d" % info["counters"] if info["flags"] & mg.BATCH_DYNAMIC else "static")
         r = {"ms": round(ms, 3), "GB_s": round(nbytes / (ms * 1e-3) / 1e9, 1), "grid_kind": kind,
              "speedup_vs_per_vector": round(ms_pv / ms, 2), "info": info}
         log("ragged %s: %s" % (name, r))
@@ -620,12 +620,13 @@ def ragged(torch, mg, inp, nseg):
     # the tuned launch (the tuner picks tile size x grid kind x schedule), then each grid kind
     # at a fixed shape, all replayed from a hipGraph
     res["tuned_graph"] = shape_run("tuned_graph", mg.BATCH_GRAPH | mg.BATCH_TUNE, None)
-    res["one_pass_graph"] = shape_run("one_pass_graph", mg.BATCH_GRAPH,
-                                      dict(tile_elems=4096, blocks_per_cu=0, dynamic=False))
-    for bpc in (2, 4, 8):
-        for dyn in (False, True):
-            nm = "persistent_%s_bpc%d_graph" % ("dynamic" if dyn else "static", bpc)
-            res[nm] = shape_run(nm, mg.BATCH_GRAPH, dict(tile_elems=4096, blocks_per_cu=bpc, dynamic=dyn))
+    for tile, bs in ((2048, 256), (2048, 64), (4096, 256)):
+        nm = "one_pass_tile%d_block%d_graph" % (tile, bs)
+        res[nm] = shape_run(nm, mg.BATCH_GRAPH, dict(tile_elems=tile, blocks_per_cu=0, dynamic=False, block=bs))
+    # persistent grids: static round-robin, and dynamic with one tile counter or one per XCD
+    for bpc, tile, dyn in ((2, 8192, 0), (2, 4096, 1), (2, 4096, 8), (2, 8192, 1), (2, 8192, 8), (4, 2048, 8)):
+        nm = "persistent_%s_bpc%d_tile%d_block256_graph" % ("dynamic%d" % dyn if dyn else "static", bpc, tile)
+        res[nm] = shape_run(nm, mg.BATCH_GRAPH, dict(tile_elems=tile, blocks_per_cu=bpc, dynamic=dyn, block=256))
     res["speedup_vs_per_vector"] = res["tuned_graph"]["speedup_vs_per_vector"]
 
     # the same per-vector launches replayed from one captured graph (no host launch cost)

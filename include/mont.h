@@ -299,6 +299,7 @@ typedef struct mont_batch_info {
     uint32_t flags;      /* the batch's flags, plus MONT_BATCH_NONTEMPORAL when it applies */
     uint32_t blocks_per_cu; /* 0: one workgroup per tile; else the persistent grid is CUs x this */
     uint32_t pow_tile;   /* elements per exponentiation tile */
+    uint32_t counters;   /* tile counters of a dynamic schedule (1 or 8), 0 when static */
 } mont_batch_info_t;
 mont_status_t mont_batch_info(const mont_batch_t *batch, mont_batch_info_t *info);
 
@@ -312,10 +313,14 @@ mont_status_t mont_batch_info(const mont_batch_t *batch, mont_batch_info_t *info
  *   blocks_per_cu  0: one pass, one workgroup per tile; 1..64: a persistent
  *                  grid of (compute units x blocks_per_cu) workgroups, capped
  *                  at the tile count, each looping over tiles;
- *   dynamic        1: each workgroup takes its next tile from an atomic
- *                  counter (the kernel leaves the counter zeroed for the next
- *                  run); 0: static round-robin over the tile table;
- *   nontemporal    1: non-temporal loads and stores.
+ *   dynamic        0: static round-robin over the tile table; 1: each
+ *                  workgroup takes its next tile from one atomic counter; 8:
+ *                  from one counter per XCD (tiles x, x+8, ... for XCD x),
+ *                  moving on to the next XCD's counter once its own is used up
+ *                  (one counter when the grid is not a multiple of 8).  The
+ *                  kernel leaves the counters zeroed for the next run;
+ *   nontemporal    1: non-temporal loads and stores;
+ *   block          lanes per workgroup: 64 or 256 (0 = 256).
  * Results do not depend on the shape.  MONT_E_INVAL for values outside these
  * ranges; the batch must not be running (its earlier runs completed).
  */
@@ -324,6 +329,7 @@ typedef struct mont_batch_shape {
     uint32_t blocks_per_cu;
     uint32_t dynamic;
     uint32_t nontemporal;
+    uint32_t block;
 } mont_batch_shape_t;
 mont_status_t mont_batch_set_shape(mont_batch_t *batch, const mont_batch_shape_t *shape, void *stream);
 

@@ -57,12 +57,12 @@ class PoolsStruct(ctypes.Structure):
 class BatchInfoStruct(ctypes.Structure):
     _fields_ = [("ntiles", ctypes.c_uint64), ("elements", ctypes.c_uint64), ("tile_elems", ctypes.c_uint32),
                 ("grid", ctypes.c_uint32), ("block", ctypes.c_uint32), ("flags", ctypes.c_uint32),
-                ("blocks_per_cu", ctypes.c_uint32), ("pow_tile", ctypes.c_uint32)]
+                ("blocks_per_cu", ctypes.c_uint32), ("pow_tile", ctypes.c_uint32), ("counters", ctypes.c_uint32)]
 
 
 class BatchShapeStruct(ctypes.Structure):
     _fields_ = [("tile_elems", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32), ("dynamic", ctypes.c_uint32),
-                ("nontemporal", ctypes.c_uint32)]
+                ("nontemporal", ctypes.c_uint32), ("block", ctypes.c_uint32)]
 
 
 class LaunchStruct(ctypes.Structure):
@@ -408,9 +408,11 @@ class Batch:
         f = {OP_MUL: load().mont_mul_ragged, OP_REDC: load().mont_redc_ragged, OP_POW: load().mont_pow_ragged}[op]
         check(f(self.h, ctypes.byref(p), _stream(stream)))
 
-    def set_shape(self, tile_elems=4096, blocks_per_cu=0, dynamic=False, nontemporal=True, stream=None):
-        """Fixes the launch shape (mont_batch_set_shape): one pass (blocks_per_cu = 0) or a persistent grid."""
-        sh = BatchShapeStruct(tile_elems, blocks_per_cu, 1 if dynamic else 0, 1 if nontemporal else 0)
+    def set_shape(self, tile_elems=4096, blocks_per_cu=0, dynamic=False, nontemporal=True, block=256, stream=None):
+        """Fixes the launch shape (mont_batch_set_shape): one pass (blocks_per_cu = 0) or a persistent grid.
+        dynamic: False (static), True or 8 (a tile counter per XCD), 1 (one tile counter)."""
+        dyn = 8 if dynamic is True else int(dynamic)
+        sh = BatchShapeStruct(tile_elems, blocks_per_cu, dyn, 1 if nontemporal else 0, block)
         check(load().mont_batch_set_shape(self.h, ctypes.byref(sh), _stream(stream)))
 
     def info(self):

@@ -143,7 +143,7 @@ extern "C" {
 
 const char *mont_last_error(void) { return g_err.c_str(); }
 
-uint32_t mont_version(void) { return (1u << 16) | 2u; }
+uint32_t mont_version(void) { return (1u << 16) | 3u; }
 
 mont_status_t mont_setup(uint64_t N, uint32_t log2R, mont_ctx_t *ctx) { return setup_ctx(N, log2R, ctx); }
 

@@ -6,9 +6,9 @@
 // per-modulus constants and a tile table {pool offsets, count, constants
 // index, op, variant, width} are uploaded once.  Device side: one workgroup
 // per tile (one pass), or a persistent grid (a multiple of the CU count) that
-// walks the tile table round-robin (static) or through an atomic tile counter
-// (dynamic; the last workgroup to finish resets the counter, so a replay
-// needs no memset), fetching the next tile's record (or claiming it) while
+// walks the tile table round-robin (static) or through atomic tile counters
+// (dynamic: one counter, or one per XCD; the last workgroup to finish resets
+// them, so a replay needs no memset), fetching the next tile's record (or claiming it) while
 // the current one runs.  The tile's record is wave-uniform, so it is fetched
 // with scalar loads and its constants stay in SGPRs; the op / word size /
 // variant switch is a uniform branch.
@@ -42,7 +42,7 @@ struct WC {
     static constexpr int v = W == 16 ? 0 : W == 32 ? 1 : 2;
 };
 
-template <int W, int V, int OP, bool NT>
+template <int W, int V, int OP, bool NT, int BS>
 __device__ __forceinline__ void tile_map(const KCtx &c, const DPools &P, uint64_t g0, uint64_t g1, uint32_t cnt)
 {
     using R = Red<W, V>;
@@ -68,12 +68,12 @@ __device__ __forceinline__ void tile_map(const KCtx &c, const DPools &P, uint64_
     const uint64_t gv = g0 + head;  // multiple of E: 16-byte aligned for aligned pools
     const uint32_t rest = cnt - head;
     const uint32_t nv = rest / E;
-    for (uint32_t c0 = threadIdx.x; c0 < nv; c0 += BLOCK * RAGGED_U) {
+    for (uint32_t c0 = threadIdx.x; c0 < nv; c0 += BS * RAGGED_U) {
         El a[RAGGED_U][E], b[RAGGED_U][E];
         TT t[RAGGED_U][E];
 #pragma unroll
         for (int u = 0; u < RAGGED_U; ++u) {
-            const uint32_t ci = c0 + u * BLOCK;
+            const uint32_t ci = c0 + u * BS;
             if (ci < nv) {
                 const uint64_t g = gv + (uint64_t)ci * E;
                 if constexpr (OP == 0) {
@@ -86,7 +86,7 @@ __device__ __forceinline__ void tile_map(const KCtx &c, const DPools &P, uint64_
         }
 #pragma unroll
         for (int u = 0; u < RAGGED_U; ++u) {
-            const uint32_t ci = c0 + u * BLOCK;
+            const uint32_t ci = c0 + u * BS;
             if (ci < nv) {
                 El o[E];
 #pragma unroll
@@ -110,7 +110,7 @@ __device__ __forceinline__ void tile_map(const KCtx &c, const DPools &P, uint64_
     }
 }
 
-template <int W>
+template <int W, int BS>
 __device__ __forceinline__ void tile_pow(const KCtx &c, const DPools &P, uint64_t g0, uint64_t g1, uint32_t cnt)
 {
     using R = Red<W, CLASSIC>;
@@ -121,73 +121,98 @@ __device__ __forceinline__ void tile_pow(const KCtx &c, const DPools &P, uint64_
     const El *px = (const El *)P.in0[wc];
     const uint64_t *pe = (const uint64_t *)P.in1[wc] + (int64_t)(g1 - g0);
     El *po = (El *)P.out[wc];
-    __shared__ El tab[4 * BLOCK];
+    __shared__ El tab[4 * BS];
     El *const mine = tab + threadIdx.x;
     const int mode = ladder_mode<W>(c.N);  // wave-uniform
-    for (uint32_t i = threadIdx.x; i < cnt; i += BLOCK) {
+    for (uint32_t i = threadIdx.x; i < cnt; i += BS) {
         const uint64_t g = g0 + i;
         const El x[1] = {px[g]};
         const uint64_t k[1] = {pe[g]};
         El y[1];
         if (W == 32 && mode == 3) {
-            pow_lanes<R, W == 32 ? 3 : 0, 1>(red, x, k, r2, one, mine, BLOCK, y);
+            pow_lanes<R, W == 32 ? 3 : 0, 1>(red, x, k, r2, one, mine, BS, y);
             po[g] = Ladder<R, W == 32 ? 3 : 0>::out(red, y[0]);
         } else if (W == 64 && mode == 1) {
-            pow_lanes<R, W == 64 ? 1 : 0, 1>(red, x, k, r2, one, mine, BLOCK, y);
+            pow_lanes<R, W == 64 ? 1 : 0, 1>(red, x, k, r2, one, mine, BS, y);
             po[g] = Ladder<R, W == 64 ? 1 : 0>::out(red, y[0]);
         } else {
-            pow_lanes<R, 0, 1>(red, x, k, r2, one, mine, BLOCK, y);
+            pow_lanes<R, 0, 1>(red, x, k, r2, one, mine, BS, y);
             po[g] = Ladder<R, 0>::out(red, y[0]);
         }
     }
 }
 
-template <int W, int OP, bool NT>
+template <int W, int OP, bool NT, int BS>
 __device__ __forceinline__ void tile_variant(uint32_t variant, const KCtx &c, const DPools &P, uint64_t g0,
                                              uint64_t g1, uint32_t cnt)
 {
     switch (variant) {
     case CLASSIC:
-        tile_map<W, CLASSIC, OP, NT>(c, P, g0, g1, cnt);
+        tile_map<W, CLASSIC, OP, NT, BS>(c, P, g0, g1, cnt);
         break;
     case SIGNED:
-        tile_map<W, SIGNED, OP, NT>(c, P, g0, g1, cnt);
+        tile_map<W, SIGNED, OP, NT, BS>(c, P, g0, g1, cnt);
         break;
     case PLANTARD:
-        tile_map<W, PLANTARD, OP, NT>(c, P, g0, g1, cnt);
+        tile_map<W, PLANTARD, OP, NT, BS>(c, P, g0, g1, cnt);
         break;
     case SIGNED_PLANTARD:
-        tile_map<W, SIGNED_PLANTARD, OP, NT>(c, P, g0, g1, cnt);
+        tile_map<W, SIGNED_PLANTARD, OP, NT, BS>(c, P, g0, g1, cnt);
         break;
     default:
-        tile_map<W, SIGNED_PLANTARD_ALPHA, OP, NT>(c, P, g0, g1, cnt);
+        tile_map<W, SIGNED_PLANTARD_ALPHA, OP, NT, BS>(c, P, g0, g1, cnt);
         break;
     }
 }
 
-template <int W, bool NT>
+template <int W, bool NT, int BS>
 __device__ __forceinline__ void tile_width(uint32_t op, uint32_t variant, const KCtx &c, const DPools &P,
                                            uint64_t g0, uint64_t g1, uint32_t cnt)
 {
     if (op == MONT_OP_MUL)
-        tile_variant<W, 0, NT>(variant, c, P, g0, g1, cnt);
+        tile_variant<W, 0, NT, BS>(variant, c, P, g0, g1, cnt);
     else if (op == MONT_OP_REDC)
-        tile_variant<W, 1, NT>(variant, c, P, g0, g1, cnt);
+        tile_variant<W, 1, NT, BS>(variant, c, P, g0, g1, cnt);
     else
-        tile_pow<W>(c, P, g0, g1, cnt);
+        tile_pow<W, BS>(c, P, g0, g1, cnt);
 }
 
-template <bool NT>
-__global__ void __launch_bounds__(BLOCK)
+template <bool NT, int BS>
+__global__ void __launch_bounds__(BS)
     k_ragged(const KCtx *__restrict__ ctab, const DTile *__restrict__ tiles, uint32_t ntiles, DPools P,
              uint32_t *__restrict__ ctr, uint32_t dynamic)
 {
+    // dynamic: 0 static, 1 one tile counter, 8 one counter per XCD.
+    // Eight counters: with a grid that is a multiple of 8 (else one counter is
+    // used), workgroup b (dispatched to XCD b mod 8) claims from counter
+    // x = b mod 8 the tiles of the x-th eighth of the table in order (one
+    // counter on one address serializes its atomics: one claim every ~11 ns
+    // measured, so 1.5 x 10^6 tiles of 512 elements took 17 ms); each counter
+    // has its own 128-byte line.  A workgroup whose eighth is used up moves on
+    // to the next one, so XCDs that run faster than others take over their
+    // remaining tiles.
+    const uint32_t nx = dynamic == 8 && gridDim.x % 8u == 0 ? 8u : 1u;
+    uint32_t sh = blockIdx.x % nx;  // lane 0's current shard
+    uint32_t left = nx;             // shards lane 0 has not yet found used up
+    auto shard_lo = [&](uint32_t x) { return (uint32_t)((uint64_t)ntiles * x / nx); };
+    // lane 0: the tile for `claim` of shard sh, or the next tile of a later
+    // shard that still has one (ntiles once every shard is used up)
+    auto next_tile = [&](uint32_t claim) {
+        uint32_t t = shard_lo(sh) + claim;
+        while (t >= shard_lo(sh + 1)) {
+            if (!--left)
+                return ntiles;
+            sh = sh + 1 == nx ? 0 : sh + 1;
+            t = shard_lo(sh) + atomicAdd(&ctr[CTR_STRIDE * sh], 1u);
+        }
+        return t;
+    };
     __shared__ uint32_t s_next[2];
     uint32_t t;
     int buf = 0;
     if (dynamic) {
         if (threadIdx.x == 0)
-            s_next[0] = atomicAdd(&ctr[0], 1u);
+            s_next[0] = next_tile(atomicAdd(&ctr[CTR_STRIDE * sh], 1u));
         __syncthreads();
         t = s_next[0];
     } else {
@@ -203,7 +228,7 @@ __global__ void __launch_bounds__(BLOCK)
         // record.
         uint32_t claim = 0;
         if (dynamic && threadIdx.x == 0)
-            claim = atomicAdd(&ctr[0], 1u);
+            claim = atomicAdd(&ctr[CTR_STRIDE * sh], 1u);
         const uint32_t tn = t + gridDim.x;
         DTile nd{};
         if (!dynamic && tn < ntiles)
@@ -211,14 +236,14 @@ __global__ void __launch_bounds__(BLOCK)
         const KCtx &kc = ctab[td.ctx];
         const uint32_t wc = td.vw >> 8, variant = td.vw & 0xffu;
         if (wc == 0)
-            tile_width<16, NT>(td.op, variant, kc, P, td.g0, td.g1, td.cnt);
+            tile_width<16, NT, BS>(td.op, variant, kc, P, td.g0, td.g1, td.cnt);
         else if (wc == 1)
-            tile_width<32, NT>(td.op, variant, kc, P, td.g0, td.g1, td.cnt);
+            tile_width<32, NT, BS>(td.op, variant, kc, P, td.g0, td.g1, td.cnt);
         else
-            tile_width<64, NT>(td.op, variant, kc, P, td.g0, td.g1, td.cnt);
+            tile_width<64, NT, BS>(td.op, variant, kc, P, td.g0, td.g1, td.cnt);
         if (dynamic) {
             if (threadIdx.x == 0)
-                s_next[buf ^ 1] = claim;
+                s_next[buf ^ 1] = next_tile(claim);
             __syncthreads();  // s_next[buf^1] written; everyone done with s_next[buf]
             buf ^= 1;
             t = __builtin_amdgcn_readfirstlane(s_next[buf]);
@@ -231,14 +256,15 @@ __global__ void __launch_bounds__(BLOCK)
     }
     if (dynamic) {
         // Every workgroup has made its last counter increment before it gets
-        // here; the last one to arrive resets both counters for the next run.
+        // here; the last one to arrive resets every counter for the next run.
         __syncthreads();
         if (threadIdx.x == 0) {
             __threadfence();
-            const uint32_t d = atomicAdd(&ctr[1], 1u);
+            const uint32_t d = atomicAdd(&ctr[CTR_STRIDE * 8], 1u);
             if (d == gridDim.x - 1) {
-                atomicExch(&ctr[0], 0u);
-                atomicExch(&ctr[1], 0u);
+                for (uint32_t x = 0; x < nx; ++x)
+                    atomicExch(&ctr[CTR_STRIDE * x], 0u);
+                atomicExch(&ctr[CTR_STRIDE * 8], 0u);
             }
         }
     }
@@ -276,6 +302,9 @@ struct mont_batch {
     uint32_t last_grid = 0, last_dyn = 0, last_ntiles = 0;
     bool last_nt = true;
     DTile *last_tiles = nullptr;
+    uint32_t block = BLOCK;      // lanes per workgroup: 64 or 256
+    uint32_t counters = 8;       // tile counters of the dynamic schedule: 1, or 8 (one per XCD)
+    uint32_t last_block = BLOCK;
 };
 
 namespace mont {
@@ -415,21 +444,24 @@ static mont_status_t check_pools(const mont_batch &b, const mont_pools_t *p)
     return MONT_OK;
 }
 
-void *ragged_kernel_ptr(bool nt) { return nt ? (void *)k_ragged<true> : (void *)k_ragged<false>; }
+void *ragged_kernel_ptr(bool nt, uint32_t block)
+{
+    if (block == 64)
+        return nt ? (void *)k_ragged<true, 64> : (void *)k_ragged<false, 64>;
+    return nt ? (void *)k_ragged<true, BLOCK> : (void *)k_ragged<false, BLOCK>;
+}
 
 hipError_t launch_ragged(const KCtx *ctab, const DTile *tiles, uint32_t ntiles, const DPools &P, uint32_t *ctr,
-                         uint32_t dyn, uint32_t grid, bool nt, hipStream_t s)
+                         uint32_t dyn, uint32_t grid, bool nt, hipStream_t s, uint32_t block)
 {
-    if (nt)
-        hipLaunchKernelGGL(k_ragged<true>, dim3(grid), dim3(BLOCK), 0, s, ctab, tiles, ntiles, P, ctr, dyn);
-    else
-        hipLaunchKernelGGL(k_ragged<false>, dim3(grid), dim3(BLOCK), 0, s, ctab, tiles, ntiles, P, ctr, dyn);
-    return hipGetLastError();
+    const uint32_t bs = block == 64 ? 64 : BLOCK;
+    void *args[] = {&ctab, &tiles, &ntiles, const_cast<DPools *>(&P), &ctr, &dyn};
+    return hipLaunchKernel(ragged_kernel_ptr(nt, bs), dim3(grid), dim3(bs), args, 0, s);
 }
 
 static mont_status_t launch_direct(mont_batch &b, const DPools &P, hipStream_t s, uint32_t dyn)
 {
-    const hipError_t e = launch_ragged(b.dctx, b.dtiles, b.ntiles, P, b.dctr, dyn, b.grid, b.nt, s);
+    const hipError_t e = launch_ragged(b.dctx, b.dtiles, b.ntiles, P, b.dctr, dyn, b.grid, b.nt, s, b.block);
     return e == hipSuccess ? MONT_OK : hip_fail(e, "ragged launch");
 }
 
@@ -442,13 +474,25 @@ static mont_status_t launch_graph(mont_batch &b, const DPools &P, hipStream_t s,
     uint32_t *ctr = b.dctr;
     void *args[] = {&ctab, &tiles, &nt, &Pc, &ctr, &dyn};
     hipKernelNodeParams kp{};
-    kp.func = ragged_kernel_ptr(b.nt);
+    kp.func = ragged_kernel_ptr(b.nt, b.block);
     kp.gridDim = dim3(b.grid);
-    kp.blockDim = dim3(BLOCK);
+    kp.blockDim = dim3(b.block);
     kp.sharedMemBytes = 0;
     kp.kernelParams = args;
     kp.extra = nullptr;
     hipError_t e;
+    if (b.exec && (b.last_nt != b.nt || b.last_block != b.block)) {
+        // another kernel (non-temporal hint or workgroup size): an executable graph's
+        // kernel node cannot change its function, so the graph is built again (after
+        // the batch's earlier runs, on this stream)
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess)
+            return hip_fail(e, "ragged graph rebuild");
+        (void)hipGraphExecDestroy(b.exec);
+        (void)hipGraphDestroy(b.graph);
+        b.exec = nullptr;
+        b.graph = nullptr;
+    }
     if (!b.exec) {
         e = hipGraphCreate(&b.graph, 0);
         if (e == hipSuccess)
@@ -458,7 +502,7 @@ static mont_status_t launch_graph(mont_batch &b, const DPools &P, hipStream_t s,
         if (e != hipSuccess)
             return hip_fail(e, "ragged graph build");
     } else if (std::memcmp(&b.last, &P, sizeof P) != 0 || b.last_grid != b.grid || b.last_dyn != dyn ||
-               b.last_nt != b.nt || b.last_ntiles != b.ntiles || b.last_tiles != b.dtiles) {
+               b.last_ntiles != b.ntiles || b.last_tiles != b.dtiles) {
         e = hipGraphExecKernelNodeSetParams(b.exec, b.node, &kp);
         if (e != hipSuccess)
             return hip_fail(e, "ragged graph update");
@@ -469,6 +513,7 @@ static mont_status_t launch_graph(mont_batch &b, const DPools &P, hipStream_t s,
     b.last_nt = b.nt;
     b.last_ntiles = b.ntiles;
     b.last_tiles = b.dtiles;
+    b.last_block = b.block;
     e = hipGraphLaunch(b.exec, s);
     return e == hipSuccess ? MONT_OK : hip_fail(e, "ragged graph launch");
 }
@@ -477,13 +522,13 @@ static mont_status_t run_once(mont_batch &b, const DPools &P, hipStream_t s)
 {
     if (b.ntiles == 0)
         return MONT_OK;
-    const uint32_t dyn = (b.flags & MONT_BATCH_DYNAMIC) ? 1u : 0u;
+    const uint32_t dyn = (b.flags & MONT_BATCH_DYNAMIC) ? b.counters : 0u;
     return (b.flags & MONT_BATCH_GRAPH) ? launch_graph(b, P, s, dyn) : launch_direct(b, P, s, dyn);
 }
 
 // Tuning: tile size x workgroups per CU x schedule, timed with HIP events.
 struct RaggedTune {
-    uint32_t tile_base, blocks_per_cu, dynamic, nt;
+    uint32_t tile_base, blocks_per_cu, dynamic, nt, block;
 };
 
 static std::string tune_key(const mont_batch &b)
@@ -543,11 +588,17 @@ static mont_status_t tune(mont_batch &b, const DPools &Pcaller, hipStream_t s)
         if (tune_lookup(key, r) && r.count("tile_elems") && r.count("blocks_per_cu") && r.count("dynamic") &&
             r.count("nontemporal")) {
             const uint32_t t = (uint32_t)r["tile_elems"], bpc = (uint32_t)r["blocks_per_cu"];
-            if (t >= 256 && t <= (1u << 20) && !(t & (t - 1)) && bpc <= 64) {
+            const uint32_t bs = r.count("block") ? (uint32_t)r["block"] : BLOCK;
+            const uint32_t dyn = (uint32_t)r["dynamic"];
+            if (t >= 256 && t <= (1u << 20) && !(t & (t - 1)) && bpc <= 64 && (bs == 64 || bs == 256) &&
+                (dyn == 0 || dyn == 1 || dyn == 8)) {
                 b.tile_base = t;
                 b.blocks_per_cu = bpc;
+                b.block = bs;
                 b.nt = r["nontemporal"] != 0;
-                b.flags = (b.flags & ~MONT_BATCH_DYNAMIC) | (r["dynamic"] != 0 ? MONT_BATCH_DYNAMIC : 0u);
+                b.flags = (b.flags & ~MONT_BATCH_DYNAMIC) | (dyn ? MONT_BATCH_DYNAMIC : 0u);
+                if (dyn)
+                    b.counters = dyn;
                 return build_tiles(b, s);
             }
         }
@@ -563,9 +614,14 @@ static mont_status_t tune(mont_batch &b, const DPools &Pcaller, hipStream_t s)
         return fail(MONT_E_DEVICE, "event create");
     }
     const uint32_t tiles[] = {1024, 2048, 4096, 8192, 16384};
-    const uint32_t bpcs[] = {0, 4, 8, 16};
+    const uint32_t bpcs[] = {0, 2, 4, 8};
+    const uint32_t kinds[] = {0, 1, 8};
+    // 64-lane workgroups stay available through mont_batch_set_shape but are not
+    // swept: on the ragged kernel they never won (the per-tile descriptor and
+    // constant loads are amortized over 4x fewer lanes).
     float best = 1e30f;
-    RaggedTune bt{b.tile_base, b.blocks_per_cu, (b.flags & MONT_BATCH_DYNAMIC) ? 1u : 0u, b.nt ? 1u : 0u};
+    RaggedTune bt{b.tile_base, b.blocks_per_cu, (b.flags & MONT_BATCH_DYNAMIC) ? b.counters : 0u, b.nt ? 1u : 0u,
+                  b.block};
     const uint32_t saved_flags = b.flags;
     b.flags &= ~MONT_BATCH_GRAPH;  // time direct launches
     mont_status_t rc = MONT_OK;
@@ -591,12 +647,16 @@ static mont_status_t tune(mont_batch &b, const DPools &Pcaller, hipStream_t s)
             b.blocks_per_cu = bpc;
             if ((rc = build_tiles(b, s)))
                 goto done;
-            for (uint32_t v = 0; v < 4; ++v) {
-                const uint32_t dyn = v & 1u, nt = v >> 1;
+            // schedules: static, one tile counter, eight (one per XCD); either access
+            for (uint32_t v = 0; v < 6; ++v) {
+                const uint32_t dyn = kinds[v % 3], nt = v / 3, bs = BLOCK;
                 if (dyn && !bpc)
                     continue;  // one workgroup per tile: nothing to balance
                 b.flags = (b.flags & ~MONT_BATCH_DYNAMIC) | (dyn ? MONT_BATCH_DYNAMIC : 0u);
+                if (dyn)
+                    b.counters = dyn;
                 b.nt = nt != 0;
+                b.block = bs;
                 if ((rc = run_once(b, P, s)))  // warm
                     goto done;
                 (void)hipEventRecord(e0, s);
@@ -612,7 +672,7 @@ static mont_status_t tune(mont_batch &b, const DPools &Pcaller, hipStream_t s)
                 (void)hipEventElapsedTime(&ms, e0, e1);
                 if (ms < best) {
                     best = ms;
-                    bt = {tb, bpc, dyn, nt};
+                    bt = {tb, bpc, dyn, nt, bs};
                 }
             }
         }
@@ -625,9 +685,12 @@ done:
     (void)hipEventDestroy(e1);
     // the best shape so far (the starting one if none was timed), also after a failure
     b.flags = (saved_flags & ~MONT_BATCH_DYNAMIC) | (bt.dynamic ? MONT_BATCH_DYNAMIC : 0u);
+    if (bt.dynamic)
+        b.counters = bt.dynamic;
     b.tile_base = bt.tile_base;
     b.blocks_per_cu = bt.blocks_per_cu;
     b.nt = bt.nt != 0;
+    b.block = bt.block;
     if (rc) {
         (void)build_tiles(b, s);
         return rc;
@@ -636,6 +699,7 @@ done:
                      {"blocks_per_cu", (double)bt.blocks_per_cu},
                      {"dynamic", (double)bt.dynamic},
                      {"nontemporal", (double)bt.nt},
+                     {"block", (double)bt.block},
                      {"ms", best / 5}});
     return build_tiles(b, s);
 }
@@ -677,7 +741,7 @@ mont_status_t mont_batch_create(const mont_ctx_t *ctxs, uint32_t nctx, const mon
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMalloc(&b->dctx, std::max<size_t>(nctx, 1) * sizeof(KCtx));
     if (e == hipSuccess)
-        e = hipMalloc(&b->dctr, 64);
+        e = hipMalloc(&b->dctr, CTR_BYTES);
     if (e != hipSuccess) {
         mont_batch_destroy(b);
         return fail(MONT_E_NOMEM, "batch tables");
@@ -690,7 +754,7 @@ mont_status_t mont_batch_create(const mont_ctx_t *ctxs, uint32_t nctx, const mon
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);  // the host tables die here
     if (e == hipSuccess)
-        e = hipMemsetAsync(b->dctr, 0, 64, s);
+        e = hipMemsetAsync(b->dctr, 0, CTR_BYTES, s);
     if (e != hipSuccess) {
         mont_batch_destroy(b);
         return hip_fail(e, "batch upload");
@@ -792,10 +856,11 @@ mont_status_t mont_batch_info(const mont_batch_t *b, mont_batch_info_t *info)
     info->elements = b->elements;
     info->tile_elems = b->tile_base;
     info->grid = b->grid;
-    info->block = BLOCK;
+    info->block = b->block;
     info->flags = b->flags | (b->nt ? MONT_BATCH_NONTEMPORAL : 0u);
     info->blocks_per_cu = b->blocks_per_cu;
     info->pow_tile = b->pow_tile;
+    info->counters = (b->flags & MONT_BATCH_DYNAMIC) ? b->counters : 0u;
     return MONT_OK;
 }
 
@@ -808,12 +873,17 @@ mont_status_t mont_batch_set_shape(mont_batch_t *b, const mont_batch_shape_t *sh
         return fail(MONT_E_INVAL, "tile_elems must be a power of two in [256, 2^20]");
     if (sh->blocks_per_cu > 64)
         return fail(MONT_E_INVAL, "blocks_per_cu must be at most 64");
-    if (sh->dynamic > 1 || sh->nontemporal > 1)
-        return fail(MONT_E_INVAL, "dynamic and nontemporal are 0 or 1");
+    if ((sh->dynamic != 0 && sh->dynamic != 1 && sh->dynamic != 8) || sh->nontemporal > 1)
+        return fail(MONT_E_INVAL, "dynamic is 0, 1 or 8 and nontemporal 0 or 1");
+    if (sh->block != 0 && sh->block != 64 && sh->block != 256)
+        return fail(MONT_E_INVAL, "block must be 0 (256), 64 or 256");
+    b->block = sh->block == 64 ? 64 : BLOCK;
     b->tile_base = t;
     b->blocks_per_cu = sh->blocks_per_cu;
     b->nt = sh->nontemporal != 0;
     b->flags = (b->flags & ~MONT_BATCH_DYNAMIC) | (sh->dynamic ? MONT_BATCH_DYNAMIC : 0u);
+    if (sh->dynamic)
+        b->counters = sh->dynamic;
     b->tuned = true;  // an explicit shape replaces tuning
     return build_tiles(*b, (hipStream_t)stream);
 }

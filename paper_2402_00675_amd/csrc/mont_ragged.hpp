@@ -48,14 +48,19 @@ struct DPools {
     void *out[3];
 };
 
+// Counters of the dynamic schedule: 8 claim counters (one per XCD) and a done
+// counter, each uint32 on its own 128-byte line.
+constexpr uint32_t CTR_STRIDE = 32;                      // uint32 between counters
+constexpr size_t CTR_BYTES = 9 * CTR_STRIDE * sizeof(uint32_t);
+
 // One launch over `ntiles` tiles, tile i reducing with the constants
 // ctab[tiles[i].ctx]: grid = ntiles for one pass, fewer for a persistent grid
-// (static round-robin, or tiles claimed from the counter ctr[0] when dyn = 1;
-// ctr: two zeroed uint32 that the kernel leaves zeroed again).  nt selects
-// non-temporal loads and stores.
+// (static round-robin, or tiles claimed from the counters in ctr when dyn = 1;
+// ctr: CTR_BYTES of zeroes that the kernel leaves zeroed again).  nt selects
+// non-temporal loads and stores; block is the workgroup size (64 or 256).
 hipError_t launch_ragged(const KCtx *ctab, const DTile *tiles, uint32_t ntiles, const DPools &P, uint32_t *ctr,
-                         uint32_t dyn, uint32_t grid, bool nt, hipStream_t s);
-void *ragged_kernel_ptr(bool nt);
+                         uint32_t dyn, uint32_t grid, bool nt, hipStream_t s, uint32_t block = BLOCK);
+void *ragged_kernel_ptr(bool nt, uint32_t block);
 
 // Validates segment i of a batch (context index, op, variant, sizes, operand
 // alignment) and fills its host descriptor; the error text names the segment.

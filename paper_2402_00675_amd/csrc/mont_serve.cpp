@@ -254,9 +254,9 @@ class GpuBackend : public mont_sched::Backend {
         if (e == hipSuccess)
             e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
         if (e == hipSuccess)
-            e = hipMalloc(&s.dctr, 64);
+            e = hipMalloc(&s.dctr, CTR_BYTES);
         if (e == hipSuccess)
-            e = hipMemsetAsync(s.dctr, 0, 64, s.stream);
+            e = hipMemsetAsync(s.dctr, 0, CTR_BYTES, s.stream);
         if (e != hipSuccess)
             return hip_fail(e, "serving slot");
         return reserve(s, stage_bytes);
@@ -546,7 +546,7 @@ class GpuBackend : public mont_sched::Backend {
             P.in1[2] = in1[1];
             P.out[2] = out[1];
             const uint32_t grid = (uint32_t)std::max<size_t>(1, std::min<size_t>(tiles.size(), grid_max));
-            e = launch_ragged(dctab, (const DTile *)(s.dstage + o_tile), (uint32_t)tiles.size(), P, s.dctr, 1u, grid,
+            e = launch_ragged(dctab, (const DTile *)(s.dstage + o_tile), (uint32_t)tiles.size(), P, s.dctr, 8u, grid,
                               true, s.stream);
         }
         if (e == hipSuccess && !xtout.empty()) {

@@ -135,12 +135,13 @@ def test_ragged_in_place_persistent():
 
 # ------------------------------------------------------ ragged launch shapes
 
-SHAPES = [(bpc, dyn, tile) for bpc in (0, 4, 16) for dyn in (False, True) for tile in (1024, 8192)]
+SHAPES = [(bpc, dyn, tile, bs) for bpc in (0, 4, 16) for dyn in (False, True) for tile in (1024, 8192)
+          for bs in (64, 256)]
 
 
 @pytest.mark.parametrize("graph", [False, True])
-@pytest.mark.parametrize("bpc,dyn,tile", SHAPES)
-def test_ragged_shapes(bpc, dyn, tile, graph):
+@pytest.mark.parametrize("bpc,dyn,tile,bs", SHAPES)
+def test_ragged_shapes(bpc, dyn, tile, bs, graph):
     """One-pass and persistent grids, static and dynamic schedules, against the oracle on every
     replay (the dynamic schedule's counter must reset itself between runs)."""
     ctxs, segs, meta, cur0, cur1 = ragged_case(41, 300, 20_000, [mg.OP_MUL, mg.OP_MUL, mg.OP_POW])
@@ -150,9 +151,9 @@ def test_ragged_shapes(bpc, dyn, tile, graph):
     do = {w: torch.zeros(cur0[w] + 16, dtype=d0[w].dtype, device="cuda") for w in (16, 32, 64)}
     P = mg.pools([d0[16], d0[32], d0[64]], [d1[16], d1[32], d1[64]], [do[16], do[32], do[64]])
     bt = mg.Batch(ctxs, segs, flags=mg.BATCH_GRAPH if graph else 0)
-    bt.set_shape(tile_elems=tile, blocks_per_cu=bpc, dynamic=dyn)
+    bt.set_shape(tile_elems=tile, blocks_per_cu=bpc, dynamic=dyn, block=bs)
     info = bt.info()
-    assert info["blocks_per_cu"] == bpc and info["tile_elems"] == tile
+    assert info["blocks_per_cu"] == bpc and info["tile_elems"] == tile and info["block"] == bs
     assert bool(info["flags"] & mg.BATCH_DYNAMIC) == dyn
     if bpc:
         assert info["grid"] <= info["ntiles"] and info["grid"] <= bpc * torch.cuda.get_device_properties(0).multi_processor_count
@@ -175,7 +176,7 @@ def test_ragged_redc_shapes(bpc, dyn):
     do = {w: torch.zeros(cur0[w] + 16, dtype=d0[w].dtype, device="cuda") for w in (16, 32, 64)}
     P = mg.pools([d0[16], d0[32], d0[64]], [None, None, None], [do[16], do[32], do[64]])
     bt = mg.Batch(ctxs, segs, flags=mg.BATCH_GRAPH)
-    bt.set_shape(tile_elems=2048, blocks_per_cu=bpc, dynamic=dyn)
+    bt.set_shape(tile_elems=2048, blocks_per_cu=bpc, dynamic=dyn, block=64 if dyn else 256)
     for _ in range(2):
         bt.run(P)
         sync()
@@ -183,10 +184,71 @@ def test_ragged_redc_shapes(bpc, dyn):
     bt.close()
 
 
+def _ragged_out_case(seed):
+    ctxs, segs, meta, cur0, cur1 = ragged_case(seed, 300, 20_000, [mg.OP_MUL, mg.OP_MUL, mg.OP_POW])
+    in0, in1, inputs = ragged_buffers(meta, cur0, cur1, seed)
+    d0 = {w: dev(in0[w]) for w in (16, 32, 64)}
+    d1 = {w: dev(in1[w]) for w in (16, 32, 64)}
+    do = {w: torch.zeros(cur0[w] + 16, dtype=d0[w].dtype, device="cuda") for w in (16, 32, 64)}
+    P = mg.pools([d0[16], d0[32], d0[64]], [d1[16], d1[32], d1[64]], [do[16], do[32], do[64]])
+    return ctxs, segs, meta, inputs, do, P
+
+
+def _run_check(bt, P, do, meta, inputs):
+    for w in do:
+        do[w].zero_()
+    bt.run(P)
+    sync()
+    check_ragged(meta, inputs, {w: host(do[w]) for w in do})
+
+
+def test_ragged_graph_follows_shape_changes():
+    """A captured batch whose kernel changes (workgroup size, non-temporal
+    access) or whose grid changes between runs: every run matches the oracle."""
+    ctxs, segs, meta, inputs, do, P = _ragged_out_case(43)
+    bt = mg.Batch(ctxs, segs, flags=mg.BATCH_GRAPH)
+    steps = [dict(tile_elems=4096, block=256), dict(tile_elems=4096, block=64),
+             dict(tile_elems=4096, block=64, nontemporal=False), dict(tile_elems=2048, block=256),
+             dict(tile_elems=2048, blocks_per_cu=2, dynamic=True, block=256),
+             dict(tile_elems=2048, blocks_per_cu=2, dynamic=True, block=64),
+             dict(tile_elems=2048, blocks_per_cu=2, dynamic=False, block=64, nontemporal=False)]
+    for shape in steps:
+        bt.set_shape(**shape)
+        info = bt.info()
+        assert info["block"] == shape["block"] and info["tile_elems"] == shape["tile_elems"]
+        for _ in range(2):
+            _run_check(bt, P, do, meta, inputs)
+    bt.close()
+
+
+@pytest.mark.parametrize("counters", [1, 8])
+def test_ragged_dynamic_counter_shards(counters):
+    """Dynamic schedules with one tile counter, and with one per XCD on grids
+    whose size is a multiple of 8 (including workgroups that move on to other
+    XCDs' counters) and on grids that are not; each replayed so the counters'
+    self-reset is exercised."""
+    ctxs, segs, meta, inputs, do, P = _ragged_out_case(44)
+    bt = mg.Batch(ctxs, segs, flags=mg.BATCH_GRAPH)
+    sharded = set()
+    for tile in (256, 1024, 2048, 4096, 8192):
+        for bpc in (1, 64):
+            bt.set_shape(tile_elems=tile, blocks_per_cu=bpc, dynamic=counters)
+            info = bt.info()
+            assert info["counters"] == counters and info["flags"] & mg.BATCH_DYNAMIC
+            sharded.add(info["grid"] % 8 == 0)
+            for _ in range(3):
+                _run_check(bt, P, do, meta, inputs)
+    bt.set_shape(tile_elems=4096)
+    assert bt.info()["counters"] == 0
+    bt.close()
+    assert sharded == {True, False}
+
+
 def test_ragged_shape_rejects_bad_values():
     c = mg.setup(8380417, 32)
     bt = mg.Batch([c], [(0, mg.OP_MUL, "classic", 100, 0)])
-    for kw in (dict(tile_elems=1000), dict(tile_elems=128), dict(blocks_per_cu=65), dict(tile_elems=1 << 21)):
+    for kw in (dict(tile_elems=1000), dict(tile_elems=128), dict(blocks_per_cu=65), dict(tile_elems=1 << 21),
+               dict(blocks_per_cu=2, dynamic=2), dict(blocks_per_cu=2, dynamic=4)):
         with pytest.raises(mg.MontError) as e:
             bt.set_shape(**kw)
         assert e.value.code == -1
@@ -250,7 +312,7 @@ def test_ragged_tune_cache_is_read_back(tmp_path, monkeypatch):
     bt.close()
     recs = [json.loads(l) for l in cache.read_text().splitlines()]
     assert len(recs) == 1 and ":ragged:" in recs[0]["key"]
-    planted = {"tile_elems": 2048, "blocks_per_cu": 8, "dynamic": 1, "nontemporal": 0}
+    planted = {"tile_elems": 2048, "blocks_per_cu": 8, "dynamic": 1, "nontemporal": 0, "block": 64}
     if all(recs[0][k] == v for k, v in planted.items()):
         planted["tile_elems"] = 4096
     with open(cache, "a") as f:
@@ -262,7 +324,8 @@ def test_ragged_tune_cache_is_read_back(tmp_path, monkeypatch):
     sync()
     info = bt.info()
     bt.close()
-    assert info["tile_elems"] == planted["tile_elems"] and info["blocks_per_cu"] == 8
+    assert info["tile_elems"] == planted["tile_elems"] and info["blocks_per_cu"] == 8 and info["block"] == 64
     assert info["flags"] & mg.BATCH_DYNAMIC and not info["flags"] & mg.BATCH_NONTEMPORAL
+    assert info["counters"] == 1
     assert len(cache.read_text().splitlines()) == 2
     check_ragged(meta, inputs, {w: host(do[w]) for w in do})
