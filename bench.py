@@ -43,9 +43,11 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--sections", default=None,
                    help="comma list of secondary measurements to run (default: all unless --quick): "
-                        "copy,ceiling,r32,const,crt,ntt,r16,valu,pow,ragged,serving; opt-in: ntt_lengths "
-                        "(every transform length at each width)")
+                        "copy,ceiling,r32,const,offsets,crt,ntt,r16,valu,pow,ragged,serving; opt-in: ntt_lengths "
+                        "(every transform length at each width), ragged_fixed (the ragged batch at --ragged-shape)")
     p.add_argument("--ragged-segments", type=int, default=4096)
+    p.add_argument("--ragged-shape", default="4096,2,8",
+                   help="tile_elems,blocks_per_cu,dynamic of the opt-in ragged_fixed section")
     p.add_argument("--serve-jobs", type=int, default=100_000)
     return p.parse_args()
 
@@ -260,7 +262,7 @@ def copy_ceiling(torch):
     return {"torch_copy_GBs": copy, "ref_2r1w_GBs": ref}
 
 
-SECTIONS = ("copy", "ceiling", "r32", "const", "crt", "ntt", "r16", "valu", "pow", "ragged", "serving")
+SECTIONS = ("copy", "ceiling", "r32", "const", "offsets", "crt", "ntt", "r16", "valu", "pow", "ragged", "serving")
 
 
 def ceiling(torch, mg, inp):
@@ -344,6 +346,36 @@ def secondary(torch, mg, inp, args, sections):
                 log("r32 const %s: %.1f Gmodmul/s" % (v, gms))
             del a, o
         ex["r32_mul_const"] = cst
+
+    if "offsets" in sections:
+        # the 32-bit product on slices at element offsets: all aligned, all at one offset
+        # (element-wise head, then the 16-byte body), and at different offsets (element-wise)
+        w2 = inp.R32Workload()
+        c32 = mg.setup(w2.N, 32)
+        ah, bh = w2.operands(False)
+        n = w2.n - 8
+        A = torch.from_numpy(ah[:n]).to(dev)
+        B = torch.from_numpy(bh[:n]).to(dev)
+        bufs = [torch.zeros(w2.n + 8, dtype=torch.uint32, device=dev) for _ in range(3)]
+        want = None
+        offs = {}
+        for name, (ka, kb, ko) in (("aligned", (0, 0, 0)), ("equal_offset_1", (1, 1, 1)),
+                                   ("equal_offset_3", (3, 3, 3)), ("offsets_1_2_3", (1, 2, 3))):
+            a, b, o = bufs[0][ka:ka + n], bufs[1][kb:kb + n], bufs[2][ko:ko + n]
+            a.copy_(A)
+            b.copy_(B)
+            _, ms = timed_sec(lambda: mg.mul(c32, a, b, out=o), torch)
+            got = o.cpu()
+            if want is None:
+                want = got
+            elif not torch.equal(got, want):
+                raise SystemExit("bench: offsets %s results differ from the aligned call" % name)
+            gms = n / (ms * 1e-3) / 1e9
+            offs[name] = {"Gmodmul_s": round(gms, 1), "GB_s": round(12 * gms, 1),
+                          "frac_hbm": round(12 * gms / HBM_PEAK_GBS, 4)}
+            log("r32 classic %s: %.1f Gmodmul/s" % (name, gms))
+        del bufs, A, B
+        ex["r32_mul_offsets"] = offs
 
     if "crt" in sections:
         # integers from the 64-bit RNS rows: 2^25 elements of 8 residues -> 8-word integers
@@ -515,6 +547,9 @@ def secondary(torch, mg, inp, args, sections):
         log("pow w32, N = 8380417: %.3f Gpow/s" % rate)
         ex["pow"] = pw
 
+    if "ragged_fixed" in sections:
+        ex["ragged_fixed"] = ragged_fixed(torch, mg, inp, args.ragged_segments,
+                                          tuple(int(x) for x in args.ragged_shape.split(",")))
     if "ragged" in sections:
         ex["ragged"] = ragged(torch, mg, inp, args.ragged_segments)
     if "serving" in sections and args.serve_jobs:
@@ -565,6 +600,43 @@ def _mismatch(o32, e32, o64, e64):
         r["count"] += int(d.size)
         if d.size:
             r[name] = {"count": int(d.size), "first": int(d[0]), "last": int(d[-1])}
+    return r
+
+
+def ragged_fixed(torch, mg, inp, nseg, shape):
+    """The ragged product batch at one explicit launch shape (tile_elems, blocks_per_cu,
+    dynamic), checked once against one launch per vector, then 20 graph-replayed runs: the
+    run the ragged kernel's rocprofv3 summaries are taken from."""
+    dev = torch.device("cuda:0")
+    wl = inp.RaggedWorkload(nseg=nseg)
+    lens, wide, mods = wl.segments()
+    offs, (a32, b32), (a64, b64) = wl.operands(lens, wide, mods)
+    ctxs = [mg.setup(N, 64 if wd else 32) for N, wd in zip(mods, wide)]
+    segs = [(i, mg.OP_MUL, "classic", int(n), int(o), int(o)) for i, (n, o) in enumerate(zip(lens, offs))]
+    d = {k: torch.from_numpy(v).to(dev) for k, v in (("a32", a32), ("b32", b32), ("a64", a64), ("b64", b64))}
+    o32 = torch.zeros_like(d["a32"])
+    o64 = torch.zeros_like(d["a64"])
+    P = mg.pools([None, d["a32"], d["a64"]], [None, d["b32"], d["b64"]], [None, o32, o64])
+    nbytes = 12 * int(sum(n for n, wd in zip(lens, wide) if not wd)) + 24 * int(sum(n for n, wd in zip(lens, wide) if wd))
+    bt = mg.Batch(ctxs, segs, flags=mg.BATCH_GRAPH)
+    bt.run_pervector(P)
+    torch.cuda.synchronize()
+    o32h, o64h = o32.cpu().numpy(), o64.cpu().numpy()
+    o32.zero_()
+    o64.zero_()
+    tile, bpc, dyn = shape
+    bt.set_shape(tile_elems=tile, blocks_per_cu=bpc, dynamic=dyn)
+    bt.run(P)
+    torch.cuda.synchronize()
+    bad = _mismatch(o32, o32h, o64, o64h)
+    if bad["count"]:
+        raise SystemExit("bench: ragged shape %s results differ from the per-vector launches: %s" % (shape, bad))
+    _, ms = timed(lambda: bt.run(P), torch, 20, 5)
+    info = bt.info()
+    bt.close()
+    r = {"shape": {"tile_elems": tile, "blocks_per_cu": bpc, "dynamic": dyn}, "grid": info["grid"],
+         "ntiles": info["ntiles"], "bytes": nbytes, "ms": round(ms, 4), "GB_s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+    log("ragged fixed shape: %s" % r)
     return r
 
 

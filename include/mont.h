@@ -42,6 +42,12 @@
  * without waiting; results are ready once the stream is synchronised.
  * In-place operation (out == an input of the same width) is allowed; other
  * overlaps are not.  n == 0 returns MONT_OK and launches nothing.
+ * Alignment: elements must be naturally aligned.  mont_mul, mont_mul_const,
+ * mont_redc and mont_mul_rns stream 16-byte chunks when every pointer is
+ * 16-byte aligned, or when all of them become so after the same first h
+ * elements (slices of aligned arrays at one offset): those h elements are
+ * then computed by a separate small launch before the 16-byte body.  Other
+ * pointers take an element-wise path with the same results.
  *
  * Errors.  Argument and domain errors are found on the host before any
  * launch and returned synchronously; nothing is enqueued then.  A HIP

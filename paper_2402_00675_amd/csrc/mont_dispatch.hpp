@@ -19,13 +19,13 @@ hipError_t go_map(const MapArgs &a, dim3 grid, hipStream_t s)
         KTab<1> t;
         t.c[0] = a.ctx[0];
         hipLaunchKernelGGL((k_map<W, V, OP, E, U, NT, 1, BS>), grid, dim3(BS), 0, s, t, a.in0, a.in1, a.out, a.n,
-                           a.ld, a.kc);
+                           a.ld, a.kc, a.head);
     } else if constexpr (OP == 0) {
         KTab<MAX_ROWS> t{};
         for (int r = 0; r < a.rows; ++r)
             t.c[r] = a.ctx[r];
         hipLaunchKernelGGL((k_map<W, V, OP, E, U, NT, MAX_ROWS, BS>), grid, dim3(BS), 0, s, t, a.in0, a.in1,
-                           a.out, a.n, a.ld, a.kc);
+                           a.out, a.n, a.ld, a.kc, a.head);
     } else {
         return hipErrorInvalidValue;
     }
@@ -49,8 +49,35 @@ hipError_t launch_map_v(const MapArgs &a, const Launch &L, hipStream_t s)
     using R = Red<W, V>;
     using El = typename R::E;
     constexpr int E = 16 / (int)sizeof(El);
-    const bool vec = aligned16(a.in0) && (OP != 0 || aligned16(a.in1)) && aligned16(a.out) &&
-                     (a.rows == 1 || (a.ld * sizeof(El)) % 16 == 0);
+    const bool rows_ok = a.rows == 1 || (a.ld * sizeof(El)) % 16 == 0;
+    const bool vec = aligned16(a.in0) && (OP != 0 || aligned16(a.in1)) && aligned16(a.out) && rows_ok;
+    // Operands that all become aligned after the same first h elements (equal
+    // offsets, the usual case for slices of aligned arrays): the 16-byte body
+    // starts at element h, and the kernel's first workgroup computes the h
+    // elements before it along with the tail.  h aligns the body to 128 bytes
+    // (a cache line) when every operand allows it, else to 16 bytes.
+    const size_t s0 = OP == 1 ? 2 * sizeof(El) : sizeof(El);  // REDC reads 2w-bit T
+    auto head_for = [&](uintptr_t al) -> uint64_t {
+        const uint64_t h = ((al - ((uintptr_t)a.out & (al - 1))) & (al - 1)) / sizeof(El);
+        const bool ok = ((uintptr_t)a.in0 + h * s0) % al == 0 &&
+                        (OP != 0 || ((uintptr_t)a.in1 + h * sizeof(El)) % al == 0) &&
+                        (a.rows == 1 || (a.ld * sizeof(El)) % al == 0);
+        return ok ? h : ~0ull;
+    };
+    uint64_t h = head_for(128);
+    if (h == ~0ull)
+        h = head_for(16);
+    if (!vec && rows_ok && E > 1 && a.head == 0 && (uintptr_t)a.out % sizeof(El) == 0 && h != ~0ull && h > 0 &&
+        h < a.n) {
+        MapArgs bd = a;
+        bd.n = a.n - h;
+        bd.in0 = (const char *)a.in0 + h * s0;
+        if (OP == 0)
+            bd.in1 = (const char *)a.in1 + h * sizeof(El);
+        bd.out = (char *)a.out + h * sizeof(El);
+        bd.head = (uint32_t)h;
+        return launch_map_v<W, V, OP>(bd, L, s);
+    }
     if (!vec) {
         dim3 grid((unsigned)grid_x(a.n, 1, a.rows, L), (unsigned)a.rows);
         return go_map<W, V, OP, 1, 1, false>(a, grid, s);

@@ -43,6 +43,7 @@ struct MapArgs {
     void *out;
     uint64_t n, ld;   // per row: n elements, row stride ld elements
     KConst kc{};      // op 2 only
+    uint32_t head = 0;  // elements before in0 / in1 / out (below 128 / element size), computed element-wise
 };
 
 // ------------------------------------------------------------ memory helpers
@@ -132,10 +133,13 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t g)
 // out[i] = red.mul(a[i], b[i]) (OP 0), red.redc(T[i]) (OP 1) or
 // red.mul_const(a[i], kc) (OP 2), per row, in workgroups of BS lanes.  out
 // may be in0 or in1 (in-place calls): every element is read and written by
-// the same lane, reads first, so the pointers carry no __restrict__.
+// the same lane, reads first, so the pointers carry no __restrict__.  The
+// `head` elements just before the (16-byte aligned) pointers, at indices
+// -head .. -1, are computed element-wise by workgroup 0, like the tail.
 template <int W, int V, int OP, int E, int U, bool NT, int NR, int BS>
 __global__ void __launch_bounds__(BS)
-    k_map(KTab<NR> tab, const void *in0, const void *in1, void *out, uint64_t n, uint64_t ld, KConst kc)
+    k_map(KTab<NR> tab, const void *in0, const void *in1, void *out, uint64_t n, uint64_t ld, KConst kc,
+          uint32_t head)
 {
     using R = Red<W, V>;
     using El = typename R::E;
@@ -191,17 +195,20 @@ __global__ void __launch_bounds__(BS)
         base += step;
     } while (base < nchunk);
     if constexpr (E > 1) {
-        // the last n mod E elements of the row
-        if (bx == 0 && threadIdx.x < (unsigned)E) {
-            const uint64_t i = nchunk * E + threadIdx.x;
-            if (i < n) {
+        // the last n mod E elements of the row, and the head before it
+        if (bx == 0) {
+            auto one = [&](int64_t i) {
                 if constexpr (OP == 0)
                     po[i] = red.mul(pa[i], pb[i]);
                 else if constexpr (OP == 2)
                     po[i] = red.mul_const(pa[i], kc);
                 else
                     po[i] = red.redc(pt[i]);
-            }
+            };
+            if (threadIdx.x < (unsigned)E && nchunk * E + threadIdx.x < n)
+                one((int64_t)(nchunk * E + threadIdx.x));
+            for (uint32_t j = threadIdx.x; j < head; j += BS)
+                one((int64_t)j - (int64_t)head);
         }
     }
 }

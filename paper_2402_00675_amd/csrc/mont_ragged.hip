@@ -57,7 +57,22 @@ __device__ __forceinline__ void tile_map(const KCtx &c, const DPools &P, uint64_
     const TT *pt = (const TT *)P.in0[wc];
     El *po = (El *)P.out[wc];
 
-    const uint32_t head = (uint32_t)std::min<uint64_t>(cnt, (E - g0 % E) % E);
+    // Element-wise head: up to the next 128-byte line of out when every
+    // operand reaches a line boundary at the same element (pools at one
+    // phase), so no 16-byte chunk of the body straddles two lines; else up to
+    // the next 16-byte chunk.  Wave-uniform scalar arithmetic.
+    uint32_t h = (E - g0 % E) % E;
+    {
+        constexpr uint32_t s0 = OP == 0 ? sizeof(El) : sizeof(TT);
+        const uintptr_t ao = (uintptr_t)(po + g0);
+        const uint32_t hl = (uint32_t)(((128 - (ao & 127)) & 127) / sizeof(El));
+        const bool in_line = OP == 0 ? ((uintptr_t)(pa + g0) + hl * s0) % 128 == 0 &&
+                                           ((uintptr_t)(pb + g0) + hl * sizeof(El)) % 128 == 0
+                                     : ((uintptr_t)(pt + g0) + hl * s0) % 128 == 0;
+        if (in_line)
+            h = hl;
+    }
+    const uint32_t head = std::min(cnt, h);
     if (threadIdx.x < head) {
         const uint64_t g = g0 + threadIdx.x;
         if constexpr (OP == 0)

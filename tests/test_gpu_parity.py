@@ -265,10 +265,78 @@ def test_small_and_misaligned(w, n):
         da, db = dev(a), dev(b)
         want = orc.mul(variant, w, N, a[1:], b[1:])
         out = torch.empty(n + 1, dtype=da.dtype, device="cuda")
-        mg.mul(c, da[1:], db[1:], out=out[1:], variant=variant)       # scalar path
+        mg.mul(c, da[1:], db[1:], out=out[1:], variant=variant)       # head + 16-byte body
         assert np.array_equal(host(out)[1:], want)
         got = host(mg.mul(c, da[1:].clone(), db[1:].clone(), variant=variant))  # aligned path
         assert np.array_equal(got, want)
+        out2 = torch.zeros(n + 2, dtype=da.dtype, device="cuda")
+        mg.mul(c, da[1:], db[1:], out=out2[2:], variant=variant)      # offsets differ: element-wise path
+        assert np.array_equal(host(out2)[2:], want)
+
+
+def _offset_views(x, k, n):
+    """n elements of a fresh device copy of x, starting k elements past a 16-byte aligned address."""
+    buf = torch.zeros(n + k + 8, dtype=x.dtype, device="cuda")
+    assert buf.data_ptr() % 16 == 0
+    buf[k:k + n] = x[:n]
+    return buf, buf[k:k + n]
+
+
+@pytest.mark.parametrize("w", [16, 32, 64])
+def test_equal_offset_heads(w):
+    """Pointers at one offset k within a 16-byte chunk (a head of 16/size - k elements, then the
+    16-byte body), for every k, products, fixed-operand products, reductions, RNS rows and
+    in-place calls; lengths shorter than the head, equal to it and spanning many chunks."""
+    N = {16: 3329, 32: 8380417, 64: (1 << 62) - 57}[w]
+    c = mg.setup(N, w)
+    E = 128 // w
+    g = inp.rng(99, w)
+    for variant in ["classic", "signed_plantard"]:
+        for k in range(E):
+            for n in sorted({1, E - k, E - k + 1, 3 * E + 1, 100_003}):
+                a, b = operands(variant, w, N, n, g)
+                want = orc.mul(variant, w, N, a, b)
+                ba, va = _offset_views(dev(a), k, n)
+                bb, vb = _offset_views(dev(b), k, n)
+                bo, vo = _offset_views(torch.zeros(n, dtype=va.dtype, device="cuda"), k, n)
+                mg.mul(c, va, vb, out=vo, variant=variant)
+                assert np.array_equal(host(vo), want), (variant, k, n)
+                assert not host(bo)[:k].any() and not host(bo)[k + n:].any()   # nothing outside
+                # b one 16-byte chunk further: the body can reach 16-byte but not 128-byte alignment
+                _, vb16 = _offset_views(dev(b), k + E, n)
+                vo.zero_()
+                mg.mul(c, va, vb16, out=vo, variant=variant)
+                assert np.array_equal(host(vo), want), ("16-byte head", variant, k, n)
+                kb = int(b[0])
+                mg.mul_const(c, va, kb, out=vo, variant=variant)
+                assert np.array_equal(host(vo), orc.mul(variant, w, N, a, np.full(n, kb, dtype=a.dtype))), (k, n)
+                mg.mul(c, va, vb, out=va, variant=variant)                      # in place
+                assert np.array_equal(host(va), want), ("in place", variant, k, n)
+                vals = t_values(variant, w, N, n, seed=k + n)
+                T = pack_T(vals, variant, w)
+                T2 = T.reshape(n, -1)        # one row per T (two words at w = 64)
+                tbuf = torch.zeros((n + k + 8) * T2.shape[1], dtype=dev(T2).dtype, device="cuda").view(n + k + 8, -1)
+                tbuf[k:k + n] = dev(T2)
+                mg.redc(c, tbuf[k:k + n], n=n, out=vo, variant=variant)
+                assert np.array_equal(host(vo), orc.redc(variant, w, N, T)), ("redc", variant, k, n)
+
+
+def test_rns_rows_at_an_offset():
+    """RNS rows whose first element sits one word past a 16-byte boundary (row stride a multiple of 16 bytes)."""
+    wl = inp.RNS64Workload(n=20_000)
+    a, b = wl.operands(n=wl.n)
+    k, ld = a.shape
+    ctxs = [mg.setup(N, 64) for N in wl.moduli]
+    flat = {}
+    for name, x in (("a", a), ("b", b), ("o", np.zeros_like(a))):
+        buf = torch.zeros(k * ld + 2, dtype=torch.uint64, device="cuda")
+        buf[1:1 + k * ld] = dev(x.reshape(-1))
+        flat[name] = buf[1:1 + k * ld].view(k, ld)
+    mg.mul_rns(ctxs, flat["a"], flat["b"], out=flat["o"], n=ld - 3)
+    got = host(flat["o"])
+    for i, N in enumerate(wl.moduli):
+        assert np.array_equal(got[i, :ld - 3], orc.mul("classic", 64, N, a[i, :ld - 3], b[i, :ld - 3])), i
+        assert not got[i, ld - 3:].any()
 
 
 LAUNCHES = [(u, nt, bpc, bs) for u in (1, 2, 4) for nt in (0, 1) for bpc in (0, 4) for bs in (64, 256)]
