@@ -45,9 +45,10 @@
  * Alignment: elements must be naturally aligned.  mont_mul, mont_mul_const,
  * mont_redc and mont_mul_rns stream 16-byte chunks when every pointer is
  * 16-byte aligned, or when all of them become so after the same first h
- * elements (slices of aligned arrays at one offset): those h elements are
- * then computed by a separate small launch before the 16-byte body.  Other
- * pointers take an element-wise path with the same results.
+ * elements (slices of aligned arrays at one offset): the 16-byte body then
+ * starts at element h (on a 128-byte line when every pointer allows it) and
+ * the same launch computes the h elements before it.  Other pointers take
+ * an element-wise path with the same results.
  *
  * Errors.  Argument and domain errors are found on the host before any
  * launch and returned synchronously; nothing is enqueued then.  A HIP
@@ -59,6 +60,20 @@
  *
  * Contexts are plain values: immutable after mont_setup, safe to share
  * across threads and streams, and copied by value into kernel arguments.
+ *
+ * Environment (read at each use):
+ *   MONT_LOG         diagnostics on stderr: unset or 0 silent; 1 or "error":
+ *                    the message of every error a call returns; 2 or "info":
+ *                    also tuning decisions, hipGraph rebuilds and serving
+ *                    events (deadline expiries, retired slots, cancellation
+ *                    requests); 3 or "debug": also one line per batch run.
+ *   MONT_TUNE        unset: MONT_BATCH_TUNE and mont_tune_mul behave as
+ *                    documented; 0: never tune (the flag is ignored and
+ *                    mont_tune_mul keeps the current shape); 1: every batch
+ *                    whose shape was not fixed by mont_batch_set_shape is
+ *                    tuned on its first run, flag or not.
+ *   MONT_TUNE_CACHE  JSON-lines file of tuned shapes (see mont_tune_mul).
+ *   MONT_LIBRARY     (Python binding only) path of the library to load.
  */
 #ifndef MONT_H
 #define MONT_H

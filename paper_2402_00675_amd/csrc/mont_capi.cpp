@@ -32,7 +32,42 @@ mont_status_t fail(mont_status_t code, const char *fmt, ...)
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     g_err = buf;
+    log_msg(1, "error %d: %s", (int)code, buf);
     return code;
+}
+
+int log_level()
+{
+    const char *v = std::getenv("MONT_LOG");
+    if (!v || !*v)
+        return 0;
+    if (!std::strcmp(v, "error"))
+        return 1;
+    if (!std::strcmp(v, "info"))
+        return 2;
+    if (!std::strcmp(v, "debug"))
+        return 3;
+    return std::atoi(v);
+}
+
+void log_msg(int level, const char *fmt, ...)
+{
+    if (log_level() < level)
+        return;
+    char buf[640];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    std::fprintf(stderr, "[mont %s] %s\n", level <= 1 ? "error" : level == 2 ? "info" : "debug", buf);
+}
+
+int tune_override()
+{
+    const char *v = std::getenv("MONT_TUNE");
+    if (!v || !*v)
+        return -1;
+    return std::atoi(v) != 0 ? 1 : 0;
 }
 
 mont_status_t hip_fail(hipError_t e, const char *what)
@@ -406,7 +441,10 @@ extern "C" mont_status_t mont_tune_mul(const mont_ctx_t *ctx, const void *a, con
     const Launch saved = get_launch(0, wc, variant);
     Launch bestL = saved;
     TuneRecord rec;
-    if (tune_lookup(key, rec) && rec.count("unroll") && rec.count("nontemporal") && rec.count("blocks_per_cu")) {
+    if (tune_override() == 0) {
+        // tuning switched off: the current shape computes the product
+        log_msg(2, "mul tune: %s: MONT_TUNE=0, current shape kept", key.c_str());
+    } else if (tune_lookup(key, rec) && rec.count("unroll") && rec.count("nontemporal") && rec.count("blocks_per_cu")) {
         // a shape tuned earlier for this device, library version, width, variant and size class
         bestL.unroll = (int)rec["unroll"];
         bestL.nontemporal = (int)rec["nontemporal"];
@@ -415,6 +453,8 @@ extern "C" mont_status_t mont_tune_mul(const mont_ctx_t *ctx, const void *a, con
         if ((bestL.unroll != 1 && bestL.unroll != 2 && bestL.unroll != 4) || (bestL.block != 64 && bestL.block != 256))
             bestL = saved;
         set_launch(0, wc, variant, bestL);
+        log_msg(2, "mul tune: %s: cached shape unroll %d, nt %d, %d workgroups/CU, block %d", key.c_str(),
+                bestL.unroll, bestL.nontemporal, bestL.blocks_per_cu, bestL.block);
     } else {
         // Candidates write a library-owned buffer: a and b are only read, so an
         // in-place call (out == a or out == b) is exact.
@@ -475,6 +515,8 @@ extern "C" mont_status_t mont_tune_mul(const mont_ctx_t *ctx, const void *a, con
         set_launch(0, wc, variant, rc ? saved : bestL);
         if (rc)
             return rc;
+        log_msg(2, "mul tune: %s: unroll %d, nt %d, %d workgroups/CU, block %d (%.4f ms per call)", key.c_str(),
+                bestL.unroll, bestL.nontemporal, bestL.blocks_per_cu, bestL.block, best_ms / 5);
         tune_store(key, {{"unroll", (double)bestL.unroll},
                          {"nontemporal", (double)bestL.nontemporal},
                          {"blocks_per_cu", (double)bestL.blocks_per_cu},

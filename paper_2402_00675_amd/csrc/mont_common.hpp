@@ -12,6 +12,17 @@
 namespace mont {
 
 mont_status_t fail(mont_status_t code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
+// Diagnostics on stderr, by the level in $MONT_LOG (read at each use): unset
+// or 0 silent; 1 every error a call returns, with its message; 2 also tuning
+// decisions, graph rebuilds and serving events (deadline expiries, retired
+// slots, cancellations); 3 also one line per batch launch.
+int log_level();
+void log_msg(int level, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+// $MONT_TUNE: -1 unset (the MONT_BATCH_TUNE flag decides), 0 never tune (the
+// flag and mont_tune_mul's sweep are ignored), 1 tune every batch whose shape
+// was not set explicitly.
+int tune_override();
 mont_status_t hip_fail(hipError_t e, const char *what);
 KCtx to_kctx(const mont_ctx_t &c);
 int width_class(uint32_t w);

@@ -500,6 +500,7 @@ static mont_status_t launch_graph(mont_batch &b, const DPools &P, hipStream_t s,
         // another kernel (non-temporal hint or workgroup size): an executable graph's
         // kernel node cannot change its function, so the graph is built again (after
         // the batch's earlier runs, on this stream)
+        log_msg(2, "ragged graph rebuilt: kernel changed (workgroup %u, nt %d)", b.block, (int)b.nt);
         e = hipStreamSynchronize(s);
         if (e != hipSuccess)
             return hip_fail(e, "ragged graph rebuild");
@@ -614,6 +615,8 @@ static mont_status_t tune(mont_batch &b, const DPools &Pcaller, hipStream_t s)
                 b.flags = (b.flags & ~MONT_BATCH_DYNAMIC) | (dyn ? MONT_BATCH_DYNAMIC : 0u);
                 if (dyn)
                     b.counters = dyn;
+                log_msg(2, "ragged tune: %s: cached shape tile %u, %u workgroups/CU, counters %u, nt %d", key.c_str(),
+                        t, bpc, dyn, (int)b.nt);
                 return build_tiles(b, s);
             }
         }
@@ -710,6 +713,8 @@ done:
         (void)build_tiles(b, s);
         return rc;
     }
+    log_msg(2, "ragged tune: %s: tile %u, %u workgroups/CU, counters %u, nt %u (%.4f ms per run)", key.c_str(),
+            bt.tile_base, bt.blocks_per_cu, bt.dynamic, bt.nt, best / 5);
     tune_store(key, {{"tile_elems", (double)bt.tile_base},
                      {"blocks_per_cu", (double)bt.blocks_per_cu},
                      {"dynamic", (double)bt.dynamic},
@@ -810,12 +815,17 @@ mont_status_t mont_batch_run(mont_batch_t *b, const mont_pools_t *pools, void *s
             return hip_fail(de, "precondition check");
     }
 #endif
-    if ((b->flags & MONT_BATCH_TUNE) && !b->tuned) {
+    const int tov = tune_override();
+    if ((tov == 1 || (tov != 0 && (b->flags & MONT_BATCH_TUNE))) && !b->tuned) {
         rc = tune(*b, P, s);
         if (rc)
             return rc;
         b->tuned = true;
     }
+    if (log_level() >= 3)
+        log_msg(3, "ragged run: %llu tiles, grid %u x %u lanes, tile %u, counters %u, nt %d, graph %d",
+                (unsigned long long)b->ntiles, b->grid, b->block, b->tile_base,
+                (b->flags & MONT_BATCH_DYNAMIC) ? b->counters : 0u, (int)b->nt, (b->flags & MONT_BATCH_GRAPH) ? 1 : 0);
     return run_once(*b, P, s);
 }
 

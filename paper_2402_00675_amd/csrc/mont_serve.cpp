@@ -289,11 +289,13 @@ class GpuBackend : public mont_sched::Backend {
         ServeSlot fresh;
         if (make_slot(fresh, slot[si].stage_cap) != MONT_OK) {
             free_slot(fresh);
+            log_msg(2, "serve: slot %d missed its deadline and could not be renewed; it stays out of use", si);
             return -1;
         }
         const int t = next_ticket++;
         retired[t] = slot[si];
         slot[si] = fresh;
+        log_msg(2, "serve: slot %d missed its deadline; its batch is retired as ticket %d, the slot renewed", si, t);
         return t;
     }
 
@@ -308,6 +310,7 @@ class GpuBackend : public mont_sched::Backend {
         unpin(it->second.pinned);
         free_slot(it->second);
         retired.erase(it);
+        log_msg(2, "serve: retired batch %d ended (%s)", t, e == hipSuccess ? "ok" : hipGetErrorString(e));
         return e == hipSuccess ? 1 : -1;
     }
 
@@ -876,6 +879,7 @@ mont_status_t mont_serve_cancel(mont_server_t *S, uint64_t id)
             S->cv_done.notify_all();
             return MONT_OK;
         }
+    log_msg(2, "serve: cancel request for job %llu", (unsigned long long)id);
     CancelReq r{id, MONT_OK, true};
     S->cancels.push_back(&r);
     S->cv_work.notify_one();

@@ -329,3 +329,54 @@ def test_ragged_tune_cache_is_read_back(tmp_path, monkeypatch):
     assert info["counters"] == 1
     assert len(cache.read_text().splitlines()) == 2
     check_ragged(meta, inputs, {w: host(do[w]) for w in do})
+
+
+# ------------------------------------------------------------- environment
+
+
+def _small_ragged(seed):
+    ctxs, segs, meta, cur0, cur1 = ragged_case(seed, 64, 30_000, [mg.OP_MUL])
+    in0, in1, inputs = ragged_buffers(meta, cur0, cur1, seed)
+    d0 = {w: dev(in0[w]) for w in (16, 32, 64)}
+    d1 = {w: dev(in1[w]) for w in (16, 32, 64)}
+    do = {w: torch.zeros(cur0[w] + 16, dtype=d0[w].dtype, device="cuda") for w in (16, 32, 64)}
+    P = mg.pools([d0[16], d0[32], d0[64]], [d1[16], d1[32], d1[64]], [do[16], do[32], do[64]])
+    return ctxs, segs, meta, inputs, do, P
+
+
+def test_tune_env_off_and_on(tmp_path, monkeypatch, capfd):
+    """MONT_TUNE=0 ignores MONT_BATCH_TUNE and mont_tune_mul's sweep; MONT_TUNE=1 tunes a batch
+    without the flag; MONT_LOG=info reports the decisions.  Results match the oracle throughout."""
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("MONT_TUNE_CACHE", str(cache))
+    monkeypatch.setenv("MONT_LOG", "info")
+    ctxs, segs, meta, inputs, do, P = _small_ragged(61)
+    monkeypatch.setenv("MONT_TUNE", "0")
+    bt = mg.Batch(ctxs, segs, flags=mg.BATCH_TUNE)
+    before = bt.info()
+    _run_check(bt, P, do, meta, inputs)
+    assert bt.info() == before
+    bt.close()
+    assert not cache.exists() or cache.read_text() == ""
+    # mont_tune_mul keeps the current shape
+    N, w = 8380417, 32
+    c = mg.setup(N, w)
+    saved = mg.get_launch(mg.OP_MUL, w, "classic")
+    try:
+        a, b = operands("classic", w, N, 1 << 20, inp.rng(62, 1))
+        da, db = dev(a), dev(b)
+        out = torch.zeros_like(da)
+        got = mg.tune_mul(c, da, db, out, variant="classic")
+        assert got == saved and mg.get_launch(mg.OP_MUL, w, "classic") == saved
+        assert np.array_equal(host(out), orc.mul("classic", w, N, a, b))
+        assert not cache.exists() or cache.read_text() == ""
+        assert "MONT_TUNE=0" in capfd.readouterr().err
+        # switched on: a batch without the flag is tuned, and the decision logged and cached
+        monkeypatch.setenv("MONT_TUNE", "1")
+        bt = mg.Batch(ctxs, segs, flags=0)
+        _run_check(bt, P, do, meta, inputs)
+        bt.close()
+        assert len(cache.read_text().splitlines()) == 1
+        assert "[mont info] ragged tune:" in capfd.readouterr().err
+    finally:
+        mg.set_launch(mg.OP_MUL, w, "classic", **saved)

@@ -140,3 +140,20 @@ def test_noalloc_rejects_oversized_tables_before_device_use():
     with pytest.raises(mg.MontError) as e:
         mg.batch_run_noalloc([c], [(0, mg.OP_MUL, "classic", 10, 0)], p, tile_elems=1000)
     assert e.value.code == -1
+
+
+def test_log_env_reports_errors(monkeypatch, capfd):
+    """$MONT_LOG: silent when unset; from level 1 ("error") every returned error's message on stderr."""
+    lib = mg.load()
+    c = mg.setup(3329, 16)
+    monkeypatch.delenv("MONT_LOG", raising=False)
+    assert lib.mont_mul(ctypes.byref(c.s), None, None, None, 5, 0, None) == -1
+    assert "[mont" not in capfd.readouterr().err
+    for level in ("1", "error", "info", "3"):
+        monkeypatch.setenv("MONT_LOG", level)
+        assert lib.mont_mul(ctypes.byref(c.s), None, None, None, 5, 0, None) == -1
+        err = capfd.readouterr().err
+        assert "[mont error] error -1:" in err and "null" in err, (level, err)
+    monkeypatch.setenv("MONT_LOG", "0")
+    assert lib.mont_setup(4, 16, ctypes.byref(_lib.CtxStruct())) == -1
+    assert "[mont" not in capfd.readouterr().err
