@@ -677,11 +677,13 @@ def words_to_ints(w):
 
 
 @pytest.mark.parametrize("k", [1, 2, 3, 8, 11, 16])
-@pytest.mark.parametrize("kind", ["primes60", "primes64", "mixed"])
+@pytest.mark.parametrize("kind", ["primes60", "primes62", "primes64", "mixed"])
 def test_crt_parity(k, kind):
     g = inp.rng(94, k)
     if kind == "primes60":
-        mods = inp.random_primes(g, 60, k)          # within a factor 2 and below 2^62: lazy products
+        mods = inp.random_primes(g, 60, k)          # within a factor 2 and below 2^62: Shoup steps
+    elif kind == "primes62":
+        mods = inp.random_primes(g, 62, k)          # Shoup steps with moduli just below their 2^62 bound
     elif kind == "primes64":
         mods = inp.random_primes(g, 64, k)          # within a factor 2, above 2^63: one-subtraction path
     else:
@@ -710,10 +712,10 @@ def test_crt_parity(k, kind):
 def test_crt_small_and_edge_counts(k):
     """Element counts around one workgroup (the output leaves through LDS in
     16-byte chunks of the workgroup's words; an odd word count ends with one
-    8-byte store), for each form: 60-bit primes (Shoup steps), 64-bit primes,
+    8-byte store), for each form: 60- and 62-bit primes (Shoup steps), 64-bit primes,
     moduli of mixed sizes."""
     g = inp.rng(94, 200 + k)
-    for mods in (inp.random_primes(g, 60, k), inp.random_primes(g, 64, k),
+    for mods in (inp.random_primes(g, 60, k), inp.random_primes(g, 62, k), inp.random_primes(g, 64, k),
                  [3, 65537, (1 << 61) - 1, 1000000007, 127, 8191, 131071, (1 << 64) - 59][:k]):
         ctxs = [mg.setup(m, 64) for m in mods]
         for n in (1, 2, 255, 256, 257):
