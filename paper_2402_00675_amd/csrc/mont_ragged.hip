@@ -209,7 +209,8 @@ __global__ void __launch_bounds__(BS)
     const uint32_t nx = dynamic == 8 && gridDim.x % 8u == 0 ? 8u : 1u;
     uint32_t sh = blockIdx.x % nx;  // lane 0's current shard
     uint32_t left = nx;             // shards lane 0 has not yet found used up
-    auto shard_lo = [&](uint32_t x) { return (uint32_t)((uint64_t)ntiles * x / nx); };
+    const uint32_t lg = nx == 8 ? 3 : 0;
+    auto shard_lo = [&](uint32_t x) { return (uint32_t)(((uint64_t)ntiles * x) >> lg); };  // ntiles x / nx
     // lane 0: the tile for `claim` of shard sh, or the next tile of a later
     // shard that still has one (ntiles once every shard is used up)
     auto next_tile = [&](uint32_t claim) {
