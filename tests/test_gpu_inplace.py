@@ -244,6 +244,33 @@ def test_ragged_dynamic_counter_shards(counters):
     assert sharded == {True, False}
 
 
+@pytest.mark.parametrize("tiles", [8, 9, 16, 24])
+def test_ragged_dynamic_few_tiles(tiles):
+    """A dynamic grid of one workgroup per tile (grid = tile count): eight counters of one tile
+    each (8), of two or three (16, 24), and one counter (9, not a multiple of 8); replayed."""
+    N = 8380417
+    c = mg.setup(N, 32)
+    n = tiles * 256 - 5
+    g = inp.rng(71, tiles)
+    a = g.integers(0, N, size=n + 3, dtype=np.uint64).astype(np.uint32)
+    b = g.integers(0, N, size=n + 3, dtype=np.uint64).astype(np.uint32)
+    da, db = dev(a), dev(b)
+    do = torch.zeros(n + 8, dtype=torch.uint32, device="cuda")
+    bt = mg.Batch([c], [(0, mg.OP_MUL, "classic", n, 0)], flags=mg.BATCH_GRAPH)
+    bt.set_shape(tile_elems=256, blocks_per_cu=64, dynamic=8)
+    info = bt.info()
+    assert info["ntiles"] == tiles and info["grid"] == tiles and info["counters"] == 8
+    want = orc.mul("classic", 32, N, a[:n], b[:n])
+    P = mg.pools([None, da, None], [None, db, None], [None, do, None])
+    for _ in range(3):
+        do.zero_()
+        bt.run(P)
+        sync()
+        assert np.array_equal(host(do)[:n], want)
+        assert not host(do)[n:].any()
+    bt.close()
+
+
 def test_ragged_shape_rejects_bad_values():
     c = mg.setup(8380417, 32)
     bt = mg.Batch([c], [(0, mg.OP_MUL, "classic", 100, 0)])

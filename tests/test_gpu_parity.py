@@ -321,22 +321,31 @@ def test_equal_offset_heads(w):
                 assert np.array_equal(host(vo), orc.redc(variant, w, N, T)), ("redc", variant, k, n)
 
 
-def test_rns_rows_at_an_offset():
-    """RNS rows whose first element sits one word past a 16-byte boundary (row stride a multiple of 16 bytes)."""
+@pytest.mark.parametrize("pad", [0, 2])
+def test_rns_rows_at_an_offset(pad):
+    """RNS rows whose first element sits one word past a 16-byte boundary: a row stride that is a
+    multiple of 128 bytes (every row's body starts on a line) and one that is a multiple of 16
+    bytes only (bodies start on 16-byte chunks)."""
     wl = inp.RNS64Workload(n=20_000)
-    a, b = wl.operands(n=wl.n)
-    k, ld = a.shape
+    a0, b0 = wl.operands(n=wl.n)
+    k = a0.shape[0]
+    ld = wl.n + pad
+    a = np.zeros((k, ld), np.uint64)
+    b = np.zeros((k, ld), np.uint64)
+    a[:, :wl.n] = a0
+    b[:, :wl.n] = b0
     ctxs = [mg.setup(N, 64) for N in wl.moduli]
     flat = {}
     for name, x in (("a", a), ("b", b), ("o", np.zeros_like(a))):
         buf = torch.zeros(k * ld + 2, dtype=torch.uint64, device="cuda")
         buf[1:1 + k * ld] = dev(x.reshape(-1))
         flat[name] = buf[1:1 + k * ld].view(k, ld)
-    mg.mul_rns(ctxs, flat["a"], flat["b"], out=flat["o"], n=ld - 3)
+    n = wl.n - 3
+    mg.mul_rns(ctxs, flat["a"], flat["b"], out=flat["o"], n=n)
     got = host(flat["o"])
     for i, N in enumerate(wl.moduli):
-        assert np.array_equal(got[i, :ld - 3], orc.mul("classic", 64, N, a[i, :ld - 3], b[i, :ld - 3])), i
-        assert not got[i, ld - 3:].any()
+        assert np.array_equal(got[i, :n], orc.mul("classic", 64, N, a[i, :n], b[i, :n])), i
+        assert not got[i, n:].any()
 
 
 LAUNCHES = [(u, nt, bpc, bs) for u in (1, 2, 4) for nt in (0, 1) for bpc in (0, 4) for bs in (64, 256)]
