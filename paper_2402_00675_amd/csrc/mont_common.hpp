@@ -8,6 +8,7 @@
 
 #include "../../include/mont.h"
 #include "mont_kernels.hpp"
+#include "mont_tuneline.hpp"
 
 namespace mont {
 
@@ -32,8 +33,8 @@ mont_status_t check_variant(const mont_ctx_t *ctx, int variant);
 Launch get_launch(int op, int wc, int variant);
 void set_launch(int op, int wc, int variant, const Launch &l);
 
-// Tuned shapes, persisted as JSON lines in $MONT_TUNE_CACHE (mont_tunecache.cpp).
-using TuneRecord = std::map<std::string, double>;
+// Tuned shapes, persisted as JSON lines in $MONT_TUNE_CACHE (mont_tunecache.cpp;
+// line format in mont_tuneline.hpp).
 std::string tune_key_prefix();  // "<gfx arch>:v<mont_version()>:"
 bool tune_lookup(const std::string &key, TuneRecord &out);
 void tune_store(const std::string &key, const TuneRecord &r);

@@ -16,6 +16,7 @@
 #include <string>
 
 #include "mont_common.hpp"
+#include "mont_tuneline.hpp"
 
 namespace mont {
 
@@ -38,38 +39,6 @@ std::string tune_key_prefix()
     return arch + v;
 }
 
-// Parses one line written by tune_store: the key string, then "name": integer pairs.
-static bool parse_line(const char *s, std::string &key, TuneRecord &r)
-{
-    const char *k = std::strstr(s, "\"key\"");
-    if (!k)
-        return false;
-    k = std::strchr(k + 5, '"');
-    if (!k)
-        return false;
-    const char *e = std::strchr(k + 1, '"');
-    if (!e)
-        return false;
-    key.assign(k + 1, e);
-    r.clear();
-    const char *p = e + 1;
-    while ((p = std::strchr(p, '"')) != nullptr) {
-        const char *q = std::strchr(p + 1, '"');
-        if (!q)
-            break;
-        std::string name(p + 1, q);
-        const char *c = q + 1;
-        while (*c == ' ' || *c == ':')
-            ++c;
-        char *end = nullptr;
-        const double v = std::strtod(c, &end);
-        if (end != c)
-            r[name] = v;
-        p = end && end != c ? end : q + 1;
-    }
-    return true;
-}
-
 bool tune_lookup(const std::string &key, TuneRecord &out)
 {
     std::lock_guard<std::mutex> g(g_tc_mu);
@@ -81,7 +50,7 @@ bool tune_lookup(const std::string &key, TuneRecord &out)
             std::string k;
             TuneRecord r;
             while (std::fgets(line, sizeof line, f))
-                if (parse_line(line, k, r) && k == key) {
+                if (tune_parse_line(line, k, r) && k == key) {
                     out = r;
                     found = true;
                 }
@@ -107,14 +76,7 @@ void tune_store(const std::string &key, const TuneRecord &r)
     FILE *f = std::fopen(path, "a");
     if (!f)
         return;
-    std::string line = "{\"key\": \"" + key + "\"";
-    char buf[96];
-    for (const auto &kv : r) {
-        snprintf(buf, sizeof buf, ", \"%s\": %.6g", kv.first.c_str(), kv.second);
-        line += buf;
-    }
-    line += "}\n";
-    std::fputs(line.c_str(), f);
+    std::fputs(tune_format_line(key, r).c_str(), f);
     std::fclose(f);
 }
 
