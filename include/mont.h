@@ -398,9 +398,10 @@ typedef struct mont_launch {
  * non-temporal x grid) for this (w, variant) on n elements of the given
  * device buffers with HIP events, keeps the fastest for later calls in this
  * process, and appends it to the JSON-lines file named by $MONT_TUNE_CACHE
- * (if set).  A shape already recorded there (or earlier in this process) for
- * the same device architecture, library version, w, variant and size class
- * (floor(log2 n)) is applied without timing.  The candidates write a
+ * (if set).  A shape already recorded there (or, with no file named,
+ * earlier in this process) for the same device architecture, library
+ * version, w, variant and size class (floor(log2 n)) is applied without
+ * timing; ragged batches under MONT_BATCH_TUNE use the same cache.  The candidates write a
  * library-owned buffer (MONT_E_NOMEM if it cannot be allocated): a and b are
  * only read, and out receives one mont_mul of the chosen shape, so
  * out == a or out == b is allowed.  *best (may be NULL) gets the shape.

@@ -4,8 +4,8 @@
 // Keys start with the device's architecture and the library version, so a
 // cache written by another GPU or another build of the library is never
 // applied.  A lookup reads the file again (tunings are rare and the file is
-// small) and takes the last record with the key; records this process
-// writes are also kept in memory for when no file is named.
+// small) and takes the last record with the key.  With no file named, the
+// records this process stored are kept in memory instead.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -56,8 +56,7 @@ bool tune_lookup(const std::string &key, TuneRecord &out)
                 }
             std::fclose(f);
         }
-        if (found)
-            return true;
+        return found;  // a named file is the whole cache: its records, nothing remembered from other files
     }
     auto it = g_tc_mem.find(key);
     if (it == g_tc_mem.end())
