@@ -60,8 +60,12 @@ def test_rns64_workload():
         assert chunked_equal(got[i], lambda s, e, i=i, N=N: orc.mul("classic", 64, N, a[i, s:e], b[i, s:e]), wl.n), i
 
 
-@pytest.mark.parametrize("flags", [mg.BATCH_GRAPH, mg.BATCH_GRAPH | mg.BATCH_TUNE])
-def test_ragged_workload(flags):
+@pytest.mark.parametrize("flags,shape", [(mg.BATCH_GRAPH, None), (mg.BATCH_GRAPH | mg.BATCH_TUNE, None),
+                                         (mg.BATCH_GRAPH, (8192, 2, 1)), (mg.BATCH_GRAPH, (4096, 2, 8))],
+                         ids=["default", "tuned", "dynamic-1-counter", "dynamic-8-counters"])
+def test_ragged_workload(flags, shape):
+    """The 4096-vector batch of the benchmark, every element against the oracle: the default
+    shape, the tuned one, and the persistent dynamic grids with one and with eight tile counters."""
     wl = inp.RaggedWorkload()
     lens, wide, mods = wl.segments()
     offs, (a32, b32), (a64, b64) = wl.operands(lens, wide, mods)
@@ -72,6 +76,8 @@ def test_ragged_workload(flags):
     o64 = torch.zeros_like(d[2])
     P = mg.pools([None, d[0], d[2]], [None, d[1], d[3]], [None, o32, o64])
     bt = mg.Batch(ctxs, segs, flags=flags)
+    if shape is not None:
+        bt.set_shape(tile_elems=shape[0], blocks_per_cu=shape[1], dynamic=shape[2])
     bt.run(P)
     bt.run(P)           # a replay
     torch.cuda.synchronize()
