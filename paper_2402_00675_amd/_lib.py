@@ -425,6 +425,13 @@ class Batch:
             load().mont_batch_destroy(self.h)
             self.h = ctypes.c_void_p()
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
     def __del__(self):
         try:
             self.close()
@@ -594,6 +601,13 @@ class Server:
         if self.h:
             _serve_lib().mont_serve_destroy(self.h)
             self.h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
     def __del__(self):
         try:

@@ -244,6 +244,16 @@ def test_ragged_dynamic_counter_shards(counters):
     assert sharded == {True, False}
 
 
+def test_batch_is_a_context_manager():
+    c = mg.setup(8380417, 32)
+    x = torch.zeros(4096, dtype=torch.uint32, device="cuda")
+    with mg.Batch([c], [(0, mg.OP_MUL, "classic", 4000, 0)]) as bt:
+        bt.run(mg.pools([None, x, None], [None, x, None], [None, x, None]))
+        sync()
+        assert bt.info()["ntiles"] >= 1
+    assert not bt.h
+
+
 @pytest.mark.parametrize("tiles", [8, 9, 16, 24])
 def test_ragged_dynamic_few_tiles(tiles):
     """A dynamic grid of one workgroup per tile (grid = tile count): eight counters of one tile

@@ -102,6 +102,18 @@ def test_host_region_checks():
         srv.close()
 
 
+def test_server_is_a_context_manager():
+    x = torch.from_numpy(np.arange(512, dtype=np.uint32))
+    y = torch.from_numpy(np.full(512, 5, dtype=np.uint32))
+    o = torch.from_numpy(np.zeros(512, dtype=np.uint32))
+    with mg.Server(hbm_budget_bytes=16 << 20, streams=1) as srv:
+        srv.submit(3, 8380417, 32, mg.OP_MUL, x, y, o)
+        srv.drain(60_000)
+        assert srv.poll(4)[0][1] == 0
+    assert not srv.h
+    assert np.array_equal(o.numpy(), orc.mul("classic", 32, 8380417, x.numpy(), y.numpy()))
+
+
 def test_resident_constants_are_reused():
     """Jobs that share a modulus reuse its resident constants: one upload per distinct modulus."""
     stream = serve.JobStream(torch, njobs=200, seed_rep=5, distinct_outputs=True, hi=1 << 12)
