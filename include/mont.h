@@ -188,7 +188,8 @@ mont_status_t mont_mul_rns(const mont_ctx_t *ctxs, uint32_t k, const void *a, co
  * modulus case from Theorem 2.1), computed by Garner's mixed-radix
  * conversion: products by the constants N_j^{-1} mod N_i are Montgomery
  * products, or Shoup's precomputed-quotient products when every modulus is
- * below 2^62 and below twice every other one (results are identical).
+ * below 2^62 and below twice every other one (below 2^61 with a quotient from
+ * three partial products; results are identical).
  * ctxs is a HOST array.  MONT_E_DOMAIN if two moduli share a factor;
  * MONT_E_UNSUPPORTED for contexts that are not 64-bit; MONT_E_INVAL for k
  * outside [1, 16], n > ld, or a null or misaligned pointer.

@@ -39,8 +39,8 @@ constexpr int CRT_PAIRS = CRT_MAX * (CRT_MAX - 1) / 2;
 struct CrtTab {
     uint64_t N[CRT_MAX];
     uint64_t np[CRT_MAX];
-    uint64_t c[CRT_PAIRS];   // forms 0, 1: (N_j^{-1} mod N_i) R mod N_i;  form 2: N_j^{-1} mod N_i
-    uint64_t cq[CRT_PAIRS];  // form 2: floor(c 2^64 / N_i)
+    uint64_t c[CRT_PAIRS];   // forms 0, 1: (N_j^{-1} mod N_i) R mod N_i;  forms 2, 3: N_j^{-1} mod N_i
+    uint64_t cq[CRT_PAIRS];  // forms 2, 3: floor(c 2^64 / N_i)
 };
 
 __host__ __device__ constexpr int crt_pair(int j, int i) { return i * (i - 1) / 2 + j; }
@@ -52,6 +52,20 @@ __host__ __device__ constexpr int crt_pair(int j, int i) { return i * (i - 1) / 
 __device__ __forceinline__ uint64_t shoup_mul(uint64_t d, uint64_t c, uint64_t cq, uint64_t N)
 {
     const uint64_t q = mulhi_64(d, cq);
+    return d * c - q * N;
+}
+
+// Shoup's product with the quotient from three of the four 32 x 32 partial
+// products of d cq (the low x low one is dropped): with d = d1 2^32 + d0 and
+// cq = k1 2^32 + k0, q = d1 k1 + hi(d1 k0) + hi(d0 k1) misses from the exact
+// floor(d cq / 2^64) only the carries of lo(d1 k0) + lo(d0 k1) + hi(d0 k0)
+// into bit 64, at most 2.  So q is between floor(d c / N) - 3 and d c / N, and
+// d c - q N is d c mod N plus 0, N, 2N or 3N: a value below 4N.
+__device__ __forceinline__ uint64_t shoup_mul3(uint64_t d, uint64_t c, uint64_t cq, uint64_t N)
+{
+    const uint32_t d0 = (uint32_t)d, d1 = (uint32_t)(d >> 32);
+    const uint32_t k0 = (uint32_t)cq, k1 = (uint32_t)(cq >> 32);
+    const uint64_t q = (uint64_t)d1 * k1 + ((uint64_t)__umulhi(d1, k0) + __umulhi(d0, k1));
     return d * c - q * N;
 }
 
@@ -77,7 +91,10 @@ __device__ __forceinline__ u128v mul_add_62(uint64_t a, uint64_t N, uint64_t c)
 // t <- shoup(t + 2N_i - v_j) with t < 2N_i and v_j < N_j < 2N_i, so the
 // operand stays below 4N_i < 2^64 and each step is one fixed-operand product
 // with no reduction before or after it (the digit is reduced once at the
-// end), and carry-free Horner steps.
+// end), and carry-free Horner steps.  FORM 3: FORM 2 with every modulus below
+// 2^61 and the three-product quotient: t < 4N_i, the operand t + 2N_i - v_j
+// stays below 6N_i < 2^64, and the digit is reduced by subtracting 2N_i and
+// N_i at the end.
 template <int K, int FORM>
 __global__ void __launch_bounds__(BLOCK)
     k_crt(CrtTab tab, const uint64_t *__restrict__ res, uint64_t ld, uint64_t n, uint64_t *__restrict__ out)
@@ -100,7 +117,9 @@ __global__ void __launch_bounds__(BLOCK)
 #pragma unroll
         for (int j = 0; j < i; ++j) {
             const uint64_t cb = tab.c[crt_pair(j, i)];
-            if constexpr (FORM == 2) {
+            if constexpr (FORM == 3) {
+                t = shoup_mul3(t + 2 * c.N - v[j], cb, tab.cq[crt_pair(j, i)], c.N);
+            } else if constexpr (FORM == 2) {
                 t = shoup_mul(t + 2 * c.N - v[j], cb, tab.cq[crt_pair(j, i)], c.N);
             } else if constexpr (FORM == 1) {
                 const uint64_t vj = v[j] >= c.N ? v[j] - c.N : v[j];
@@ -112,7 +131,9 @@ __global__ void __launch_bounds__(BLOCK)
                 t = a >= b ? a - b : a + (c.N - b);
             }
         }
-        if constexpr (FORM == 2)
+        if constexpr (FORM == 3)
+            t = t >= 2 * c.N ? t - 2 * c.N : t;
+        if constexpr (FORM >= 2)
             t = t >= c.N ? t - c.N : t;
         v[i] = t;
     }
@@ -128,7 +149,7 @@ __global__ void __launch_bounds__(BLOCK)
         // acc holds K - 1 - i words; acc * N_i + v_i fills K - i words
 #pragma unroll
         for (int w = 0; w < K - 1 - i; ++w) {
-            if constexpr (FORM == 2) {
+            if constexpr (FORM >= 2) {
                 const u128v p = mul_add_62(acc[w], Ni, carry);
                 acc[w] = p.lo;
                 carry = p.hi;
@@ -178,7 +199,9 @@ static void go_crt(const CrtTab &t, int form, const uint64_t *res, uint64_t ld, 
                    hipStream_t s)
 {
     const unsigned grid = (unsigned)((n + BLOCK - 1) / BLOCK);
-    if (form == 2)
+    if (form == 3)
+        hipLaunchKernelGGL((k_crt<K, 3>), dim3(grid), dim3(BLOCK), 0, s, t, res, ld, n, out);
+    else if (form == 2)
         hipLaunchKernelGGL((k_crt<K, 2>), dim3(grid), dim3(BLOCK), 0, s, t, res, ld, n, out);
     else if (form == 1)
         hipLaunchKernelGGL((k_crt<K, 1>), dim3(grid), dim3(BLOCK), 0, s, t, res, ld, n, out);
@@ -231,7 +254,7 @@ extern "C" mont_status_t mont_crt(const mont_ctx_t *ctxs, uint32_t k, const void
         hi = std::max(hi, ctxs[i].N);
     }
     const bool narrow = (u128)hi < 2 * (u128)lo;  // every v_j < 2 N_i: one conditional subtraction reduces it
-    const int form = narrow ? (hi < (1ull << 62) ? 2 : 1) : 0;
+    const int form = narrow ? (hi < (1ull << 61) ? 3 : hi < (1ull << 62) ? 2 : 1) : 0;
     for (uint32_t i = 1; i < k; ++i) {
         const uint64_t Ni = ctxs[i].N;
         for (uint32_t j = 0; j < i; ++j) {
@@ -239,7 +262,7 @@ extern "C" mont_status_t mont_crt(const mont_ctx_t *ctxs, uint32_t k, const void
             if (!c)
                 return fail(MONT_E_DOMAIN, "moduli %u and %u are not coprime", j, i);
             const int p = crt_pair((int)j, (int)i);
-            if (form == 2) {
+            if (form >= 2) {
                 t.c[p] = c;
                 t.cq[p] = (uint64_t)(((u128)c << 64) / Ni);  // below 2^64: c < N_i
             } else {

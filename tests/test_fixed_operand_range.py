@@ -13,6 +13,10 @@ m = -T N^{-1} mod R, stays below 2N for every a < R when b < N (T < R N).
 
 Both are checked here with Python integers: exhaustively over every 16-bit a,
 by sampling at 32 and 64 bits (with the largest inputs always included).
+
+Shoup's product by a fixed c with a quotient from three of the four partial
+products (the CRT reconstruction's steps for moduli below 2^61) is checked the
+same way: its result stays below 4N for every 64-bit input.
 """
 import random
 
@@ -77,3 +81,33 @@ def test_montgomery_lazy_below_2n(w, N):
         for a in (g.randrange(R), R - 1, g.randrange(25 * N) % R):
             r = montgomery_lazy(w, N, a, b)
             assert r < 2 * N and r % N == a * b * pow(R, -1, N) % N, (w, N, a, b)
+
+
+def shoup3(d, c, cq, N):
+    """The CRT kernel's Shoup product with a three-partial-product quotient (the
+    low x low product of d and cq dropped), modulo 2^64 as the kernel computes it."""
+    M32 = (1 << 32) - 1
+    d0, d1, k0, k1 = d & M32, d >> 32, cq & M32, cq >> 32
+    q = d1 * k1 + ((d1 * k0) >> 32) + ((d0 * k1) >> 32)
+    return (d * c - q * N) % (1 << 64), q
+
+
+@pytest.mark.parametrize("bits", [40, 59, 60, 61])
+def test_shoup_three_product_quotient(bits):
+    """For N < 2^61, c < N, cq = floor(c 2^64 / N) and any 64-bit d: the result is
+    d c mod N plus at most 3N (below 4N), and the quotient is at most 2 below the
+    exact floor(d cq / 2^64).  With t < 4N and a digit v below 2N, the next
+    operand t + 2N - v stays below 6N < 2^64."""
+    rnd = random.Random(bits)
+    for _ in range(300):
+        N = rnd.randrange(1 << (bits - 1), 1 << bits) | 1
+        for c in [1, 2, N - 1, N - 2, N // 2] + [rnd.randrange(1, N) for _ in range(10)]:
+            cq = (c << 64) // N
+            ds = [0, 1, (1 << 64) - 1, (1 << 64) - 2, 6 * N - 1, 4 * N - 1] + \
+                 [rnd.randrange(1 << 64) for _ in range(20)]
+            for d in ds:
+                r, q = shoup3(d, c, cq, N)
+                exact = (d * cq) >> 64
+                assert exact - 2 <= q <= exact
+                assert r < 4 * N and r % N == d * c % N, (N, c, d)
+    assert 6 * ((1 << 61) - 1) < 1 << 64

@@ -690,9 +690,9 @@ def words_to_ints(w):
 def test_crt_parity(k, kind):
     g = inp.rng(94, k)
     if kind == "primes60":
-        mods = inp.random_primes(g, 60, k)          # within a factor 2 and below 2^62: Shoup steps
+        mods = inp.random_primes(g, 60, k)          # within a factor 2 and below 2^61: three-product quotients
     elif kind == "primes62":
-        mods = inp.random_primes(g, 62, k)          # Shoup steps with moduli just below their 2^62 bound
+        mods = inp.random_primes(g, 62, k)          # in [2^61, 2^62): exact Shoup quotients
     elif kind == "primes64":
         mods = inp.random_primes(g, 64, k)          # within a factor 2, above 2^63: one-subtraction path
     else:
