@@ -168,6 +168,17 @@ def test_signed_montgomery_brute_force(w):
         assert not np.any((got * R - T) % N)
 
 
+def test_mods_range_is_section_2s():
+    """The least absolute remainder of Section 2 lies in [-n/2, n/2): for even n
+    the tie value n/2 is taken as -n/2.  Checked as the congruence and the range
+    for every x in a window, not by re-typing the formula."""
+    for n in (7, 8, 9, 16, 256, 3329):
+        for x in range(-3 * n, 3 * n):
+            r = orc.mods(x, n)
+            assert (r - x) % n == 0 and -n <= 2 * r < n, (x, n, r)
+    assert orc.mods(4, 8) == -4 and orc.mods(128, 256) == -128 and orc.mods(3, 7) == 3 and orc.mods(4, 7) == -3
+
+
 def test_signed_montgomery_tie_rule():
     """m0 = -R/2 is taken when a0 N^{-1} = R/2 (mods is [-R/2, R/2))."""
     w, N = 8, 101
