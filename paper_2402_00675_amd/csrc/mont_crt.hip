@@ -69,6 +69,15 @@ __device__ __forceinline__ uint64_t shoup_mul3(uint64_t d, uint64_t c, uint64_t 
     return d * c - q * N;
 }
 
+// t - m when t >= m, else t: the borrow of the subtraction picks the result.
+__device__ __forceinline__ uint64_t sub_if_ge(uint64_t t, uint64_t m)
+{
+    unsigned b0, b1;
+    const uint32_t dl = __builtin_subc((uint32_t)t, (uint32_t)m, 0u, &b0);
+    const uint32_t dh = __builtin_subc((uint32_t)(t >> 32), (uint32_t)(m >> 32), b0, &b1);
+    return b1 ? t : ((uint64_t)dh << 32 | dl);
+}
+
 // a N + c for N < 2^62 (n1 < 2^30) and any 64-bit a, c; the sum is below
 // 2^127.  Partial sums: a0 n0 + lo(c) < 2^64, t1 = a0 n1 + hi(p00) < 2^62 +
 // 2^32, mid = a1 n0 + lo(t1) + hi(c) < 2^64, hi = a1 n1 + hi(t1) + hi(mid)
@@ -101,11 +110,13 @@ __global__ void __launch_bounds__(BLOCK)
 {
     const uint64_t base = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * BLOCK;  // the block's first element
     const uint64_t e = base + threadIdx.x;
-    const bool live = e < n;  // the lanes past n still take part in the block's output pass
+    // the lanes past n still take part in the block's output pass: they read
+    // the last element (their results are not written)
+    const uint64_t *p = res + (e < n ? e : n - 1);
     uint64_t x[K];
 #pragma unroll
-    for (int i = 0; i < K; ++i)
-        x[i] = live ? __builtin_nontemporal_load(res + (uint64_t)i * ld + e) : 0;
+    for (int i = 0; i < K; ++i, p += ld)
+        x[i] = __builtin_nontemporal_load(p);
     uint64_t v[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
@@ -132,9 +143,9 @@ __global__ void __launch_bounds__(BLOCK)
             }
         }
         if constexpr (FORM == 3)
-            t = t >= 2 * c.N ? t - 2 * c.N : t;
+            t = sub_if_ge(t, 2 * c.N);
         if constexpr (FORM >= 2)
-            t = t >= c.N ? t - c.N : t;
+            t = sub_if_ge(t, c.N);
         v[i] = t;
     }
     uint64_t acc[K];
