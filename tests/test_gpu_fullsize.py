@@ -186,3 +186,25 @@ def test_ntt_bench_shape_sampled(variant):
         assert np.array_equal(got[r], orc.dft(32, N, x[r], root)), r
     mg.ntt(c, d, root, inverse=True, variant=variant)
     assert np.array_equal(d.cpu().numpy(), x)
+
+
+@pytest.mark.parametrize("variant", ["classic", "plantard"])
+@pytest.mark.parametrize("log2n", [4, 8, 12])
+def test_ntt16_full_size_sampled(variant, log2n):
+    """2^26 16-bit coefficients mod 12289 (the size of the benchmark's length
+    sweep), at lengths where the 16-bit transform computes in 32-bit words:
+    16 seeded transforms checked against the DFT by its definition, and the
+    round trip checked in full."""
+    N, n = 12289, 1 << log2n
+    batch = (1 << 26) // n
+    c = mg.setup(N, 16)
+    root = next(w for w in (pow(q, (N - 1) // n, N) for q in range(2, 100)) if pow(w, n // 2, N) == N - 1)
+    x = inp.uniform_residues(inp.rng(inp.W_R16, 11 + log2n), N, batch * n, np.uint16).reshape(batch, n)
+    d = dev(x)
+    mg.ntt(c, d, root, variant=variant)
+    got = d.cpu().numpy()
+    rows = np.random.default_rng(log2n).choice(batch, size=16, replace=False)
+    for r in rows:
+        assert np.array_equal(got[r], orc.dft(16, N, x[r], root)), r
+    mg.ntt(c, d, root, inverse=True, variant=variant)
+    assert np.array_equal(d.cpu().numpy(), x)
