@@ -115,8 +115,11 @@ __global__ void __launch_bounds__(BLOCK)
     const uint64_t *p = res + (e < n ? e : n - 1);
     uint64_t x[K];
 #pragma unroll
-    for (int i = 0; i < K; ++i, p += ld)
+    for (int i = 0; i < K; ++i) {
         x[i] = __builtin_nontemporal_load(p);
+        if (i + 1 < K)
+            p += ld;  // never past the last row
+    }
     uint64_t v[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
