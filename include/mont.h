@@ -209,7 +209,11 @@ mont_status_t mont_crt(const mont_ctx_t *ctxs, uint32_t k, const void *res, size
  * (MONT_CLASSIC) or with Plantard's product by a fixed operand
  * (MONT_PLANTARD, Section 3.2); other variants return MONT_E_UNSUPPORTED.
  * Twiddle tables are built once per (N, root, n, variant, direction) and
- * kept in library-owned device memory for the life of the process.
+ * kept in library-owned device memory for the life of the process.  The
+ * coefficients are words of the context's width; with a 16-bit context,
+ * transforms of length 16 or more whose 16-bit butterflies would need a
+ * reduction between stages are computed with the 32-bit reductions of the
+ * same modulus (16-bit words in and out, the same results).
  */
 mont_status_t mont_ntt(const mont_ctx_t *ctx, void *data, size_t batch, uint32_t log2n, uint64_t root, int inverse,
                        mont_variant_t variant, void *stream);
