@@ -86,10 +86,12 @@ def test_ntt_rejects_bad_root_and_variant():
 
 @pytest.mark.parametrize("w,N", [(16, 12289), (32, 8380417), (64, prime_1_mod(62, 12, 1))])
 def test_ntt_unaligned_rows(w, N):
-    """Rows that do not start on a 16-byte boundary take the element-wise path."""
+    """Rows that do not start on a 16-byte boundary take the element-wise path
+    (at w = 16 both the 16-bit arithmetic, lengths 4 and 8, and the 32-bit
+    arithmetic on 16-bit words, from 16 on)."""
     c = mg.setup(N, w)
     g = inp.rng(93, 500 + w)
-    for n, batch in ((16, 7), (64, 5), (256, 6), (512, 3), (1024, 3), (2048, 3), (4096, 2)):
+    for n, batch in ((4, 5), (8, 9), (16, 7), (64, 5), (256, 6), (512, 3), (1024, 3), (2048, 3), (4096, 2)):
         wr = root(N, n)
         x = g.integers(0, N, size=(batch, n), dtype=np.uint64).astype(DT[w])
         want = np.stack([orc.dft(w, N, x[i], wr) for i in range(batch)])
