@@ -390,7 +390,7 @@ __global__ void __launch_bounds__(BLOCK) k_range(KCtx c, uint64_t T0, void *__re
 #pragma unroll
         for (int e = 0; e < E; ++e)
             o[e] = red.redc((TT)(t0 + (TT)e));
-        store_chunk<El, E, false>(po + i * E, o);
+        store_chunk<El, E, true>(po + i * E, o);
     }
     if constexpr (E > 1) {
         if (blockIdx.x == 0 && threadIdx.x < (unsigned)E) {
