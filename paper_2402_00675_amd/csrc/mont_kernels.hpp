@@ -335,10 +335,12 @@ __device__ __forceinline__ void pow_lanes(const R &red, const typename R::E (&x)
 }
 
 // Window width of the standalone exponentiation kernel: 4 bits for the 32-bit
-// signed ladder (a 16-entry table of 4-byte words per element), 2 bits where
-// the table entries are 8 bytes or the products are the general form.
+// signed ladder and the lazy 64-bit one (16-entry tables: 64 or 128 bytes per
+// element in LDS; at 64 bits the LDS then holds two 512-element workgroups
+// per CU, and the 6 % fewer products still win), 2 bits for the general
+// forms.
 template <int MODE>
-constexpr int pow_window() { return MODE == 3 ? 4 : 2; }
+constexpr int pow_window() { return MODE == 3 || MODE == 1 ? 4 : 2; }
 
 template <int W, int U, int MODE>
 __global__ void __launch_bounds__(BLOCK)
