@@ -121,13 +121,11 @@ static void launch_defaults()
         for (auto &b : a)
             for (auto &l : b)
                 l = Launch{};
-    // exponentiation is ALU-bound: two independent elements per lane (run in
-    // lockstep) hide the latency of the dependent multiply chains; one, two
-    // and four measure within 1 % of each other on MI355X (2^22 elements,
-    // clocks at steady state), and two keeps the LDS window tables small
-    for (auto &b : g_launch[2])
-        for (auto &l : b)
-            l.unroll = 2;
+    // exponentiation (op 2) keeps the default of one element per lane: with
+    // 4-bit window tables in LDS (16 entries per element) more workgroups
+    // then fit on a CU, and on MI355X (2^22 elements, clocks at steady state)
+    // one element per lane measured 7 % faster than two at 64 bits and 1 %
+    // at 32 bits; four were 11-30 % slower
     g_launch_init = true;
 }
 

@@ -498,7 +498,7 @@ def test_pow_parity(w):
         assert bad.size == 0, (N, bad[:5], x[bad[:5]], e[bad[:5]])
 
 
-@pytest.mark.parametrize("unroll", [1, 4])
+@pytest.mark.parametrize("unroll", [1, 2, 4])
 def test_pow_launch_shapes(unroll):
     """Every lockstep width of the ladder (elements per lane) gives the same results."""
     g = inp.rng(96, 100 + unroll)
