@@ -183,8 +183,14 @@ __device__ __forceinline__ void butterfly(const R &red, typename R::E &u, typena
     }
 }
 
-// Workgroups per CU for the one-wave-per-polynomial kernel (its waves loop over the batch).
-constexpr int NTTW_BPC = 8;
+// Workgroups per CU launched for the one-wave-per-unit kernel (its waves loop
+// over the batch, the next unit's loads in flight).  Measured on MI355X over
+// 2^26 coefficients: up to length 256 (one block of 256 positions per unit)
+// 32 per CU beat 8 by 3-12 % at every width (more than the CU holds at once,
+// so the dispatcher refills CUs as workgroups finish; 64 was no better and one
+// unit per wave, with nothing prefetched, up to 2.4x slower); at 512 and 1024
+// (two and four blocks per unit) 8 stayed best or within 1 %.
+__host__ __device__ constexpr int nttw_bpc(uint32_t log2n) { return log2n <= 8 ? 32 : 8; }
 
 // Butterfly by the unit twiddle (the first two stages of a bit-reversed
 // decimation-in-time transform multiply by 1 or by w^(n/4) only).  LAZY:
@@ -783,7 +789,7 @@ static hipError_t go_ntt(const KCtx &k, int variant, void *data, size_t batch, u
         constexpr uint64_t WAVES = BLOCK / 64;
         const uint64_t nelem = (uint64_t)batch << log2n;
         const uint64_t units = log2n >= 8 ? (uint64_t)batch : (nelem + 255) / 256;
-        const uint64_t blocks = std::min<uint64_t>((units + WAVES - 1) / WAVES, (uint64_t)device_cus() * NTTW_BPC);
+        const uint64_t blocks = std::min<uint64_t>((units + WAVES - 1) / WAVES, (uint64_t)device_cus() * nttw_bpc(log2n));
         const dim3 g((unsigned)blocks);
         // chunk loads (n / 256 words per lane and slot) when the polynomials are aligned to them
         const size_t chunk = std::min<size_t>(16, std::max<size_t>(1, (size_t)n / 256) * sizeof(El));

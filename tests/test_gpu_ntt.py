@@ -117,10 +117,14 @@ def test_ntt_many_per_wave(w, N):
     whole batch through the round trip."""
     c = mg.setup(N, w)
     g = inp.rng(93, 700 + w + N % 89)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
     for n in (2, 8, 16, 64, 128, 256, 512, 1024, 2048, 4096):
         if (N - 1) % n:
             continue
-        batch = (3 * 8192 + 5) * 256 // n + (3 if n < 256 else 0) if n <= 1024 else 2 * 8192 + 5
+        # the one-wave kernel launches 32 workgroups of four waves per CU up to
+        # length 256 and 8 at 512 and 1024: give every wave two units or more
+        waves = cus * (32 if n <= 256 else 8) * 4
+        batch = (2 * waves + 5) * 256 // n + (3 if n < 256 else 0) if n <= 1024 else 2 * 8192 + 5
         wr = root(N, n)
         x = g.integers(0, N, size=(batch, n), dtype=np.uint64).astype(DT[w])
         rows = sorted(set(g.choice(batch, size=40, replace=False).tolist()) | {batch - 1})
